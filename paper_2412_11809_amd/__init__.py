@@ -1,0 +1,172 @@
+"""Python binding of the hit-clustering library (``libhc.so``).
+
+Thin ctypes marshalling over the C-ABI declared in ``include/hc.h``; every
+step of the clustering runs in the library's HIP kernels.  PyTorch is used
+only to hold device memory and to name the stream to run on.
+
+The functions carry the C names (``hc_cluster``, ``hc_workspace_size`` ...);
+``cluster`` is a convenience wrapper that allocates the outputs.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhc.so")
+
+HC_OK = 0
+HC_ERR_ARG = -1
+HC_ERR_RANGE = -2
+HC_ERR_WORKSPACE = -3
+HC_ERR_DEVICE = -4
+HC_ERR_DISORDER = -5
+HC_ERR_OVERFLOW = -6
+HC_ERR_BUDGET = -7
+HC_ERR_BUSY = -8
+DT_INFINITE = (1 << 64) - 1
+
+# hc_hit and hc_features as numpy record types (same byte layout as hc.h)
+HIT_DTYPE = np.dtype([("toa", "<u8"), ("x", "<u2"), ("y", "<u2"), ("tot", "<u2"), ("reserved", "<u2")])
+FEATURE_DTYPE = np.dtype([
+    ("label", "<i4"), ("size", "<u4"), ("sum_tot", "<u8"), ("toa_min", "<u8"),
+    ("toa_max", "<u8"), ("sum_x_tot", "<u8"), ("sum_y_tot", "<u8"),
+    ("cx", "<f8"), ("cy", "<f8"),
+])
+
+
+class HcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (status %d)" % (msg, code))
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
+                ("disorder_hint", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libhc.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libhc.so is not built (%s); run __graft_entry__.build() or "
+                          "python -m paper_2412_11809_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    lib.hc_workspace_size.restype = ctypes.c_size_t
+    lib.hc_workspace_size.argtypes = [ctypes.POINTER(_Opts), ctypes.c_int64]
+    lib.hc_cluster.restype = ctypes.c_int
+    lib.hc_cluster.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Opts)]
+    lib.hc_last_error.restype = ctypes.c_char_p
+    lib.hc_version.restype = ctypes.c_char_p
+    lib.hc_timing_enable.argtypes = [ctypes.c_int]
+    lib.hc_timing_read.restype = ctypes.c_int
+    lib.hc_timing_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    _lib = lib
+    return lib
+
+
+def _opts(width, height, disorder_hint, workspace, stream):
+    o = _Opts()
+    o.width, o.height, o.disorder_hint, o.flags = width, height, disorder_hint, 0
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    if stream is not None:
+        o.stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return o
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _check(rc):
+    if rc != HC_OK:
+        raise HcError(rc, load_library().hc_last_error().decode())
+
+
+def hc_version():
+    return load_library().hc_version().decode()
+
+
+def hc_last_error():
+    return load_library().hc_last_error().decode()
+
+
+def hc_workspace_size(n, width=256, height=256, disorder_hint=0):
+    o = _opts(width, height, disorder_hint, None, None)
+    return int(load_library().hc_workspace_size(ctypes.byref(o), int(n)))
+
+
+def hc_cluster(hits, n, dt, labels, features, n_clusters, width=256, height=256, disorder_hint=0,
+               workspace=None, stream=None):
+    """Direct call of the C entry point on device tensors (no allocation).
+
+    hits: uint8 tensor of n*16 bytes; labels: int32[n]; features: uint8 tensor
+    of >= n*64 bytes or None; n_clusters: int32[1] (all on the GPU)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(hits.device)
+    o = _opts(width, height, disorder_hint, workspace, stream)
+    rc = load_library().hc_cluster(_ptr(hits), int(n), int(dt), _ptr(labels), _ptr(features),
+                                   _ptr(n_clusters), ctypes.byref(o))
+    _check(rc)
+
+
+def hits_to_device(hits, device="cuda"):
+    """numpy HIT_DTYPE array -> uint8 CUDA tensor (16 bytes per hit)."""
+    import torch
+    hits = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    return torch.from_numpy(hits.view(np.uint8).reshape(-1)).to(device)
+
+
+def cluster(hits, dt, width=256, height=256, disorder_hint=0, features=True, workspace=None,
+            stream=None):
+    """Cluster a device tensor of hits; returns (labels, features_bytes, n_clusters)
+    as device tensors (features_bytes is uint8 [n, 64] or None)."""
+    import torch
+    n = hits.numel() // 16
+    dev = hits.device
+    labels = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    feats = torch.empty((max(n, 1), 64), dtype=torch.uint8, device=dev) if features else None
+    k = torch.empty(1, dtype=torch.int32, device=dev)
+    hc_cluster(hits, n, dt, labels, feats, k, width, height, disorder_hint, workspace, stream)
+    return labels[:n], feats, k
+
+
+def features_to_numpy(feats, k):
+    """Device feature bytes + count -> numpy FEATURE_DTYPE[k]."""
+    k = int(k)
+    if k <= 0:
+        return np.empty(0, dtype=FEATURE_DTYPE)
+    return feats[:k].cpu().numpy().reshape(-1).view(FEATURE_DTYPE).copy()
+
+
+# ---- kernel timing (diagnostics)
+def hc_timing_enable(on=True):
+    load_library().hc_timing_enable(1 if on else 0)
+
+
+def hc_timing_reset():
+    load_library().hc_timing_reset()
+
+
+def hc_timing_read(cap=64):
+    lib = load_library()
+    names = (ctypes.c_char_p * cap)()
+    cnt = (ctypes.c_int64 * cap)()
+    ms = (ctypes.c_double * cap)()
+    k = lib.hc_timing_read(names, cnt, ms, cap)
+    if k < 0:
+        _check(k)
+    return {names[i].decode(): (int(cnt[i]), float(ms[i])) for i in range(min(k, cap))}

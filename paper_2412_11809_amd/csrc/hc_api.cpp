@@ -1,0 +1,273 @@
+// C-ABI of the hit-clustering library: argument checking, workspace layout,
+// the launch sequence of hc_cluster, error strings and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hc.h"
+#include "hc_internal.h"
+
+namespace hc {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+static int device_fail(hipError_t e, const char* what)
+{
+    return fail(HC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------ workspace
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disorder, Work* w, char* base)
+{
+    Work x{};
+    x.n = (int32_t)n;
+    x.width = width;
+    x.height = height;
+    const int64_t D = disorder ? disorder : 4096;
+    int T = 8192;
+    if (2 * D <= 2048) T = 2048;
+    else if (2 * D <= 4096) T = 4096;
+    x.sort_tile = T;
+    x.sort_ipt = T / kSortThreads;
+    int64_t m = (2 * D + T - 1) / T;
+    if (m < 1) m = 1;
+    x.force_fallback = m > kMaxNeighbourTiles ? 1 : 0;
+    x.sort_m = (int32_t)(m > kMaxNeighbourTiles ? kMaxNeighbourTiles : m);
+    x.n_sort_tiles = (int32_t)((n + T - 1) / T);
+    x.n_link_tiles = (int32_t)((n + kLinkTile - 1) / kLinkTile);
+    x.n_feat_tiles = (int32_t)((n + kFeatTile - 1) / kFeatTile);
+    x.n_scan_blocks = (int32_t)((n + kScanBlock - 1) / kScanBlock);
+    x.n_fb_blocks = (int32_t)((n + kFbBlock - 1) / kFbBlock);
+    x.edge_cap = (int64_t)x.n_link_tiles * kLinkHaloCap;
+    x.carry_cap = n;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return base ? base + at : nullptr;
+    };
+    const size_t N = (size_t)n;
+    x.status = (Status*)take(sizeof(Status));
+    x.tiles = (TileInfo*)take(sizeof(TileInfo) * (size_t)x.n_sort_tiles);
+    x.ts_rel = (uint32_t*)take(4 * N);
+    x.ts_lidx = (uint16_t*)take(2 * N);
+    x.ts_xy = (uint32_t*)take(4 * N);
+    x.ts_tot = (uint16_t*)take(2 * N);
+    x.s_toa = (uint64_t*)take(8 * N);
+    x.s_xy = (uint32_t*)take(4 * N);
+    x.s_tot = (uint16_t*)take(2 * N);
+    x.s_idx = (int32_t*)take(4 * N);
+    x.gparent = (int32_t*)take(4 * N);
+    x.edges = (int2*)take(sizeof(int2) * (size_t)x.edge_cap);
+    x.overflow_tiles = (int32_t*)take(4 * (size_t)x.n_link_tiles);
+    x.slots = (SlotRec*)take(sizeof(SlotRec) * N);
+    x.carries = (SlotRec*)take(sizeof(SlotRec) * (size_t)x.carry_cap);
+    x.scan_state = (unsigned long long*)take(8 * (size_t)x.n_scan_blocks);
+    x.fb_key[0] = (uint64_t*)take(8 * N);
+    x.fb_key[1] = (uint64_t*)take(8 * N);
+    x.fb_val[0] = (uint32_t*)take(4 * N);
+    x.fb_val[1] = (uint32_t*)take(4 * N);
+    x.fb_hist = (uint32_t*)take(4 * 256 * (size_t)x.n_fb_blocks);
+    if (w) *w = x;
+    return off;
+}
+
+// One cached workspace per device for callers that pass none.
+struct CachedWs {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_ws_mu;
+static std::vector<CachedWs> g_ws;
+
+static int cached_workspace(size_t need, void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    CachedWs& c = g_ws[dev];
+    if (c.bytes < need) {
+        if (c.ptr) {
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess) return device_fail(e, "hipDeviceSynchronize");
+            (void)hipFree(c.ptr);
+            c.ptr = nullptr;
+            c.bytes = 0;
+        }
+        e = hipMalloc(&c.ptr, need);
+        if (e != hipSuccess) return device_fail(e, "hipMalloc(workspace)");
+        c.bytes = need;
+    }
+    *out = c.ptr;
+    return HC_OK;
+}
+
+int persistent_grid()
+{
+    static std::mutex mu;
+    static std::vector<int> cus;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cus.size() <= dev) cus.resize(dev + 1, 0);
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+// ---------------------------------------------------------------- timing
+struct TimingRec {
+    const char* name;
+    hipEvent_t start, stop;
+};
+static bool g_timing = false;
+static std::vector<TimingRec> g_trecs;
+static size_t g_tused = 0;
+
+TimedLaunch::TimedLaunch(const char* name, hipStream_t s) : name_(name), s_(s), slot_(-1)
+{
+    if (!g_timing) return;
+    if (g_tused == g_trecs.size()) {
+        TimingRec r{name, nullptr, nullptr};
+        if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
+        g_trecs.push_back(r);
+    }
+    slot_ = (int)g_tused++;
+    g_trecs[slot_].name = name;
+    (void)hipEventRecord(g_trecs[slot_].start, s);
+}
+
+TimedLaunch::~TimedLaunch()
+{
+    if (slot_ >= 0) (void)hipEventRecord(g_trecs[slot_].stop, s_);
+}
+
+}  // namespace hc
+
+using namespace hc;
+
+extern "C" {
+
+const char* hc_last_error(void) { return g_err.c_str(); }
+
+const char* hc_version(void) { return "hc 0.1 (gfx950)"; }
+
+size_t hc_workspace_size(const hc_opts* opts, int64_t n)
+{
+    if (n < 0) return 0;
+    const uint32_t W = opts && opts->width ? opts->width : 256;
+    const uint32_t H = opts && opts->height ? opts->height : 256;
+    return plan_workspace(n, W, H, opts ? opts->disorder_hint : 0, nullptr, nullptr);
+}
+
+int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_features* features,
+               int32_t* n_clusters, const hc_opts* opts)
+{
+    if (n < 0) return fail(HC_ERR_ARG, "n < 0");
+    if (!n_clusters) return fail(HC_ERR_ARG, "n_clusters is NULL");
+    if (n > 0 && (!hits || !labels)) return fail(HC_ERR_ARG, "hits or labels is NULL");
+    const uint32_t W = opts && opts->width ? opts->width : 256;
+    const uint32_t H = opts && opts->height ? opts->height : 256;
+    if (W > 65535 || H > 65535) return fail(HC_ERR_ARG, "sensor dimensions must be 1..65535");
+    if (opts && opts->flags) return fail(HC_ERR_ARG, "flags must be 0");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    hipError_t e;
+    if (n == 0) {
+        if ((e = launch_write_count(n_clusters, 0, s)) != hipSuccess) return device_fail(e, "write_count");
+        return HC_OK;
+    }
+    Work w;
+    const uint32_t D = opts ? opts->disorder_hint : 0;
+    const size_t need = plan_workspace(n, W, H, D, &w, nullptr);
+    void* ws = opts ? opts->workspace : nullptr;
+    if (ws) {
+        if (opts->workspace_bytes < need)
+            return fail(HC_ERR_WORKSPACE, "workspace of " + std::to_string(opts->workspace_bytes) +
+                                              " bytes, need " + std::to_string(need));
+    } else {
+        int rc = cached_workspace(need, &ws);
+        if (rc != HC_OK) return rc;
+    }
+    plan_workspace(n, W, H, D, &w, (char*)ws);
+    w.dt = dt;
+
+#define HC_LAUNCH(call, what)                                   \
+    do {                                                         \
+        if ((e = (call)) != hipSuccess) return device_fail(e, what); \
+    } while (0)
+    HC_LAUNCH(launch_init(w, s), "init");
+    HC_LAUNCH(launch_tile_sort(hits, w, s), "tile_sort");
+    if (!w.force_fallback) HC_LAUNCH(launch_tile_merge(w, s), "tile_merge");
+    HC_LAUNCH(launch_sort_fallback(hits, w, s), "sort_fallback");
+    HC_LAUNCH(launch_link(w, s), "link");
+    HC_LAUNCH(launch_link_fallback(w, s), "link_fallback");
+    HC_LAUNCH(launch_union_edges(w, s), "union_edges");
+    HC_LAUNCH(launch_flatten(w, labels, s), "flatten");
+    if (features) {
+        HC_LAUNCH(launch_features(w, labels, s), "features");
+        HC_LAUNCH(launch_carries(w, s), "carries");
+    }
+    HC_LAUNCH(launch_compact(w, labels, features, n_clusters, s), "compact");
+#undef HC_LAUNCH
+    return HC_OK;
+}
+
+int hc_timing_enable(int on)
+{
+    g_timing = on != 0;
+    return HC_OK;
+}
+
+int hc_timing_reset(void)
+{
+    g_tused = 0;
+    return HC_OK;
+}
+
+int hc_timing_read(const char** names, int64_t* launches, double* total_ms, int32_t cap)
+{
+    std::vector<const char*> nm;
+    std::vector<int64_t> cnt;
+    std::vector<double> ms;
+    for (size_t i = 0; i < g_tused; i++) {
+        TimingRec& r = g_trecs[i];
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e != hipSuccess) return device_fail(e, "hipEventSynchronize");
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, r.start, r.stop);
+        if (e != hipSuccess) return device_fail(e, "hipEventElapsedTime");
+        size_t k = 0;
+        while (k < nm.size() && std::string(nm[k]) != r.name) k++;
+        if (k == nm.size()) {
+            nm.push_back(r.name);
+            cnt.push_back(0);
+            ms.push_back(0.0);
+        }
+        cnt[k]++;
+        ms[k] += t;
+    }
+    for (size_t k = 0; k < nm.size() && (int32_t)k < cap; k++) {
+        if (names) names[k] = nm[k];
+        if (launches) launches[k] = cnt[k];
+        if (total_ms) total_ms[k] = ms[k];
+    }
+    return (int)nm.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal declarations of the hit-clustering library: workspace layout,
+// launch parameters and the kernel launchers of each translation unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hc.h"
+
+namespace hc {
+
+// ---------------------------------------------------------------- constants
+constexpr int kSortThreads = 512;     // threads of the tile-sort / merge kernels
+constexpr int kLinkTile = 1024;       // sorted hits per link work-group
+constexpr int kLinkHaloCap = 1024;    // earlier hits a link work-group can hold
+constexpr int kLinkThreads = 256;
+constexpr int kLinkHash = 4096;       // pixel hash slots (>= 2 x (tile + halo))
+constexpr int kFeatTile = 512;        // sorted hits per feature work-group
+constexpr int kFeatThreads = 256;
+constexpr int kFeatHash = 1024;       // root hash slots (>= 2 x tile)
+constexpr int kScanBlock = 2048;      // input indices per compaction block
+constexpr int kScanThreads = 256;
+constexpr int kFbBlock = 2048;        // elements per fallback radix block
+constexpr int kFbThreads = 512;
+constexpr int kFbMaxPasses = 8;       // 8-bit digits of a 64-bit key
+constexpr int kMaxNeighbourTiles = 8; // sort merge looks at most this far
+
+// Partial or final integer features of one cluster (64 bytes).
+struct SlotRec {
+    uint32_t size;
+    int32_t root;  // carries: the cluster's label; slots: unused
+    uint64_t sum_tot, toa_min, toa_max, sum_xt, sum_yt, sum_x, sum_y;
+};
+static_assert(sizeof(SlotRec) == 64, "slot record is one cache line");
+
+struct TileInfo {
+    uint64_t base;     // smallest ToA in the tile
+    uint64_t max_toa;  // largest ToA
+    int32_t min_idx;   // input index of the tile's first element in (toa, idx) order
+    int32_t max_idx;   // ... and of its last element
+    int32_t wide;      // ToA range does not fit 32 bits (tile left unsorted)
+    int32_t count;
+};
+
+// State of one ticketed fallback radix sort (see hc_radix.h).
+struct RadixState {
+    int32_t ticket;
+    int32_t plan_done;
+    int32_t total_tasks;
+    int32_t passes;
+    int32_t active;
+    int32_t pad_;
+    uint64_t key_min;
+    int32_t hist_done[kFbMaxPasses];
+    int32_t scan_done[kFbMaxPasses];
+    int32_t scatter_done[kFbMaxPasses];
+    int32_t query_done;
+    int32_t pad2_[15];
+};
+
+struct Status {
+    int32_t err_range;      // a hit lies outside the sensor
+    int32_t sort_fallback;  // tile sort/merge could not order the input
+    int32_t n_overflow;     // link tiles whose halo did not fit
+    int32_t n_edges;        // cross-tile unions queued by the link kernel
+    int32_t n_carries;      // partial features queued for atomic merging
+    int32_t scan_ticket;    // compaction block ticket
+    int32_t err_internal;   // an index derived from device data was out of range
+    int32_t pad_[9];
+    RadixState rs[2];       // [0]: ToA sort fallback, [1]: pixel sort fallback
+};
+
+// Device pointers into one workspace, for n hits.
+struct Work {
+    int32_t n;
+    uint32_t width, height;
+    uint64_t dt;
+    // sort tiling
+    int32_t sort_tile;   // T: hits per sort tile (power of two)
+    int32_t sort_ipt;    // T / kSortThreads
+    int32_t sort_m;      // neighbour tiles searched on each side
+    int32_t n_sort_tiles;
+    int32_t force_fallback;
+    int32_t n_link_tiles;
+    int32_t n_feat_tiles;
+    int32_t n_scan_blocks;
+    int32_t n_fb_blocks;
+    int64_t edge_cap;
+    int64_t carry_cap;
+
+    Status* status;
+    TileInfo* tiles;
+    uint32_t* ts_rel;
+    uint16_t* ts_lidx;
+    uint32_t* ts_xy;
+    uint16_t* ts_tot;
+    uint64_t* s_toa;
+    uint32_t* s_xy;
+    uint16_t* s_tot;
+    int32_t* s_idx;
+    int32_t* gparent;
+    int2* edges;
+    int32_t* overflow_tiles;
+    SlotRec* slots;
+    SlotRec* carries;
+    unsigned long long* scan_state;
+    uint64_t* fb_key[2];
+    uint32_t* fb_val[2];
+    uint32_t* fb_hist;
+};
+
+// Workspace planning (host).
+size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disorder, Work* w,
+                      char* base);
+
+// Kernel launchers; each returns the hipError_t of its launch.
+hipError_t launch_init(const Work& w, hipStream_t s);
+hipError_t launch_tile_sort(const hc_hit* hits, const Work& w, hipStream_t s);
+hipError_t launch_tile_merge(const Work& w, hipStream_t s);
+hipError_t launch_sort_fallback(const hc_hit* hits, const Work& w, hipStream_t s);
+hipError_t launch_link(const Work& w, hipStream_t s);
+hipError_t launch_link_fallback(const Work& w, hipStream_t s);
+hipError_t launch_union_edges(const Work& w, hipStream_t s);
+hipError_t launch_flatten(const Work& w, int32_t* labels, hipStream_t s);
+hipError_t launch_features(const Work& w, const int32_t* labels, hipStream_t s);
+hipError_t launch_carries(const Work& w, hipStream_t s);
+hipError_t launch_compact(const Work& w, const int32_t* labels, hc_features* features,
+                          int32_t* n_clusters, hipStream_t s);
+hipError_t launch_write_count(int32_t* n_clusters, int32_t value, hipStream_t s);
+
+// Kernel timing hooks (hc_api.cpp): bracket a launch with events when enabled.
+struct TimedLaunch {
+    TimedLaunch(const char* name, hipStream_t s);
+    ~TimedLaunch();
+    const char* name_;
+    hipStream_t s_;
+    int slot_;
+};
+
+}  // namespace hc

@@ -1,0 +1,195 @@
+// Ticketed LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits.
+//
+// Used only on fallback paths, so it is built for robustness rather than
+// speed: it runs inside ONE persistent launch whose work-groups draw task
+// tickets from a counter.  A task waits only for tasks with smaller tickets
+// (which are already held by running work-groups), so the launch needs no
+// co-residency guarantee and every wait ends.  Task 0 decides whether the
+// sort is needed at all; if not, every other work-group exits at once.
+//
+// Tasks: 0 = plan; then per pass p: kFbBlock-sized histogram tasks, one scan
+// task, scatter tasks; then `extra` caller tasks (queries on the result).
+// Sorting is stable, so equal keys keep their source order.
+#pragma once
+
+#include "hc_device.h"
+
+namespace hc {
+
+struct RadixLds {
+    uint32_t k0[kFbBlock], k1[kFbBlock];
+    uint16_t v0[kFbBlock], v1[kFbBlock];
+    uint16_t cnt[16 * kFbThreads];
+    uint32_t wsum[kFbThreads / kWave];
+    uint64_t key[kFbBlock];
+    uint32_t val[kFbBlock];
+    uint32_t hist[256];
+    uint32_t start[256];
+    int32_t task;
+    int32_t misc;
+};
+
+// Exclusive scan of `len` u32 counters in place by one work-group.
+__device__ inline void radix_scan_counts(uint32_t* h, int64_t len, RadixLds& L)
+{
+    constexpr int PER = 8;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < len; c0 += (int64_t)kFbThreads * PER) {
+        uint32_t v[PER];
+        uint32_t s = 0;
+        const int64_t b = c0 + (int64_t)threadIdx.x * PER;
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            v[j] = (b + j < len) ? h[b + j] : 0u;
+            s += v[j];
+        }
+        uint32_t total;
+        uint32_t run = carry + block_exclusive_scan<kFbThreads>(s, L.wsum, &total);
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            if (b + j < len) h[b + j] = run;
+            run += v[j];
+        }
+        carry += total;
+    }
+}
+
+// Src: int64 count() const; void load(int64 i, uint64& key, uint32& val) const
+//      (pass-0 keys, raw: the engine subtracts st.key_min).
+// Plan: __device__ void plan(RadixState& st, RadixLds& L) run by task 0's
+//      work-group; sets st.active, st.key_min, st.passes (>= 1) and the
+//      number of extra tasks through its return value.
+// Final: void store(int64 pos, uint64 rel_key, uint32 val) for the last pass.
+// Extra: void extra(int task, const uint64* keys, const uint32* vals, RadixLds& L)
+template <class Job>
+__device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uint32_t* val_buf[2],
+                             uint32_t* hist, int32_t nb, int32_t* err)
+{
+    __shared__ RadixLds L;
+    const int t = threadIdx.x;
+    const int64_t n = job.count();
+    while (true) {
+        __syncthreads();
+        if (t == 0) L.task = __hip_atomic_fetch_add(&st->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int task = L.task;
+        if (task == 0) {
+            if (t == 0) {
+                st->active = 0;
+                st->passes = 1;
+                st->key_min = 0;
+                st->total_tasks = 1;
+            }
+            __syncthreads();
+            const int extra = job.plan(*st, L);
+            __syncthreads();
+            if (t == 0) {
+                if (st->active) st->total_tasks = 1 + st->passes * (2 * nb + 1) + extra;
+                __threadfence();
+                __hip_atomic_store(&st->plan_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            continue;
+        }
+        wait_at_least(&st->plan_done, 1, nullptr);
+        if (task >= __hip_atomic_load(&st->total_tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        const int passes = st->passes;
+        const uint64_t kmin = st->key_min;
+        const int per_pass = 2 * nb + 1;
+        const int tt = task - 1;
+        if (tt >= passes * per_pass) {
+            wait_at_least(&st->scatter_done[passes - 1], nb, nullptr);
+            const int last = (passes - 1) & 1;
+            job.extra(tt - passes * per_pass, key_buf[last], val_buf[last], L);
+            continue;
+        }
+        const int p = tt / per_pass, r = tt % per_pass;
+        const int shift = 8 * p;
+        const uint64_t* kin = key_buf[(p + 1) & 1];
+        const uint32_t* vin = val_buf[(p + 1) & 1];
+        if (r < nb) {  // ---- histogram of block r
+            const int b = r;
+            if (p > 0) wait_at_least(&st->scatter_done[p - 1], nb, nullptr);
+            for (int i = t; i < 256; i += kFbThreads) L.hist[i] = 0;
+            __syncthreads();
+            for (int i = t; i < kFbBlock; i += kFbThreads) {
+                const int64_t g = (int64_t)b * kFbBlock + i;
+                if (g < n) {
+                    uint64_t k;
+                    uint32_t v;
+                    if (p == 0) {
+                        job.load(g, k, v);
+                        k -= kmin;
+                    } else {
+                        k = kin[g];
+                    }
+                    atomicAdd(&L.hist[(k >> shift) & 255u], 1u);
+                }
+            }
+            __syncthreads();
+            for (int i = t; i < 256; i += kFbThreads) hist[(int64_t)i * nb + b] = L.hist[i];
+            signal_done(&st->hist_done[p]);
+        } else if (r == nb) {  // ---- exclusive scan of all block histograms
+            wait_at_least(&st->hist_done[p], nb, nullptr);
+            radix_scan_counts(hist, (int64_t)256 * nb, L);
+            signal_done(&st->scan_done[p]);
+        } else {  // ---- stable scatter of block b
+            const int b = r - nb - 1;
+            wait_at_least(&st->scan_done[p], 1, nullptr);
+            const int64_t g0 = (int64_t)b * kFbBlock;
+            const int cntb = (int)((n - g0) < kFbBlock ? (n - g0) : kFbBlock);
+            for (int i = t; i < kFbBlock; i += kFbThreads) {
+                if (i < cntb) {
+                    uint64_t k;
+                    uint32_t v;
+                    if (p == 0) {
+                        job.load(g0 + i, k, v);
+                        k -= kmin;
+                    } else {
+                        k = kin[g0 + i];
+                        v = vin[g0 + i];
+                    }
+                    L.key[i] = k;
+                    L.val[i] = v;
+                    L.k0[i] = (uint32_t)((k >> shift) & 255u);
+                } else {
+                    L.k0[i] = 0xFFu;  // pads sort after every real element
+                }
+                L.v0[i] = (uint16_t)i;
+            }
+            for (int i = t; i < 256; i += kFbThreads) L.hist[i] = 0;
+            __syncthreads();
+            for (int i = t; i < cntb; i += kFbThreads) atomicAdd(&L.hist[L.k0[i]], 1u);
+            __syncthreads();
+            {
+                const uint32_t c = t < 256 ? L.hist[t] : 0u;
+                const uint32_t e = block_exclusive_scan<kFbThreads>(c, L.wsum, nullptr);
+                if (t < 256) L.start[t] = e;
+            }
+            __syncthreads();
+            const int which = block_radix_sort<kFbThreads, kFbBlock / kFbThreads>(L.k0, L.v0, L.k1, L.v1,
+                                                                                  L.cnt, L.wsum, 8);
+            const uint32_t* sk = which ? L.k1 : L.k0;
+            const uint16_t* sv = which ? L.v1 : L.v0;
+            const bool last = (p == passes - 1);
+            uint64_t* kout = key_buf[p & 1];
+            uint32_t* vout = val_buf[p & 1];
+            for (int rr = t; rr < cntb; rr += kFbThreads) {
+                const uint32_t d = sk[rr];
+                const int e = sv[rr];
+                const int64_t pos = (int64_t)hist[(int64_t)d * nb + b] + (rr - (int)L.start[d]);
+                if (pos < 0 || pos >= n) {
+                    atomicOr(err, 1);
+                    continue;
+                }
+                if (last) job.store(pos, L.key[e], L.val[e]);
+                if (!last || Job::kKeepSorted) {
+                    kout[pos] = L.key[e];
+                    vout[pos] = L.val[e];
+                }
+            }
+            signal_done(&st->scatter_done[p]);
+        }
+    }
+}
+
+}  // namespace hc

@@ -1,0 +1,314 @@
+// Step A1 of the clustering path: order the hits by (ToA, input index).
+//
+// The paper sorts each buffer by ToA (radix sort, Step 3 of its high-level GPU
+// algorithm) before the neighbour sweep, and relies on the stream being only
+// partly unsorted ("t-ordered", Section 3.1).  Here that partial order is
+// exploited directly:
+//   k_tile_sort   sorts tiles of T consecutive input hits in LDS (stable radix
+//                 sort on ToA relative to the tile minimum), writes the tile in
+//                 sorted order plus its min/max keys;
+//   k_tile_merge  gives every element its global rank: all of its tile's
+//                 predecessors plus, for each of the m neighbour tiles on both
+//                 sides, the number of smaller keys there (binary search in
+//                 LDS).  This is exact whenever tiles more than m apart do not
+//                 interleave, which the kernel verifies from the tile min/max
+//                 keys (monotone tile minima and maxima, max of tile i below
+//                 min of tile i+m+1); a displacement of at most m*T/2 positions
+//                 guarantees it.
+//   k_sort_fallback  if any check failed (or a tile's ToA range exceeds 32
+//                 bits), re-sorts everything with a ticketed LSD radix sort;
+//                 otherwise it exits at once.
+// Output: the sorted structure-of-arrays s_toa / s_xy / s_tot / s_idx.
+#include "hc_device.h"
+#include "hc_radix.h"
+
+namespace hc {
+
+// --------------------------------------------------------------- init
+__global__ void k_init(Work w)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    int32_t* s = reinterpret_cast<int32_t*>(w.status);
+    for (int i = t; i < (int)(sizeof(Status) / 4); i += stride) s[i] = 0;
+    for (int i = t; i < w.n_scan_blocks; i += stride) w.scan_state[i] = 0ull;
+    if (t == 0 && w.force_fallback) w.status->sort_fallback = 1;
+}
+
+hipError_t launch_init(const Work& w, hipStream_t s)
+{
+    TimedLaunch tl("init", s);
+    int blocks = (w.n_scan_blocks + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 64 ? 64 : blocks);
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, w);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- tile sort
+template <int IPT>
+__global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __restrict__ hits, Work w)
+{
+    constexpr int T = kSortThreads * IPT;
+    __shared__ uint32_t k0[T], k1[T];
+    __shared__ uint16_t v0[T], v1[T];
+    __shared__ uint16_t cnt[16 * kSortThreads];
+    __shared__ uint32_t wsum[kSortThreads / kWave];
+    __shared__ uint64_t red[kSortThreads / kWave];
+
+    const int tile = xcd_tile(w.n_sort_tiles);
+    if (tile < 0) return;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)tile * T;
+    const int cnt_e = (int)((w.n - base) < T ? (w.n - base) : T);
+
+    uint64_t toa[IPT];
+    uint64_t tmin = ~0ull, tmax = 0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        const int e = t + j * kSortThreads;
+        toa[j] = 0;
+        if (e < cnt_e) {
+            const hc_hit h = hits[base + e];
+            toa[j] = h.toa;
+            tmin = h.toa < tmin ? h.toa : tmin;
+            tmax = h.toa > tmax ? h.toa : tmax;
+            bad |= (h.x >= w.width) | (h.y >= w.height);
+        }
+    }
+    if (bad) atomicOr(&w.status->err_range, 1);
+    tmin = block_min_u64<kSortThreads>(tmin, red);
+    tmax = block_max_u64<kSortThreads>(tmax, red);
+    const uint64_t range = tmax - tmin;
+    if (range > 0xFFFFFFFFull) {
+        if (t == 0) {
+            TileInfo ti;
+            ti.base = tmin;
+            ti.max_toa = tmax;
+            ti.min_idx = (int32_t)base;
+            ti.max_idx = (int32_t)(base + cnt_e - 1);
+            ti.wide = 1;
+            ti.count = cnt_e;
+            w.tiles[tile] = ti;
+            atomicOr(&w.status->sort_fallback, 1);
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        const int e = t + j * kSortThreads;
+        k0[e] = e < cnt_e ? (uint32_t)(toa[j] - tmin) : 0xFFFFFFFFu;
+        v0[e] = (uint16_t)e;
+    }
+    __syncthreads();
+    const int bits = range == 0 ? 0 : 32 - __builtin_clz((uint32_t)range);
+    const int which = block_radix_sort<kSortThreads, IPT>(k0, v0, k1, v1, cnt, wsum, bits);
+    const uint32_t* sk = which ? k1 : k0;
+    const uint16_t* sv = which ? v1 : v0;
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        const int e = t + j * kSortThreads;
+        if (e < cnt_e) {
+            uint16_t l = sv[e];
+            if (l >= cnt_e) {
+                atomicOr(&w.status->err_internal, 1);
+                l = 0;
+            }
+            const hc_hit h = hits[base + l];
+            w.ts_rel[base + e] = sk[e];
+            w.ts_lidx[base + e] = l;
+            w.ts_xy[base + e] = (uint32_t)h.x | ((uint32_t)h.y << 16);
+            w.ts_tot[base + e] = h.tot;
+        }
+    }
+    if (t == 0) {
+        TileInfo ti;
+        ti.base = tmin;
+        ti.max_toa = tmax;
+        ti.min_idx = (int32_t)(base + sv[0]);
+        ti.max_idx = (int32_t)(base + sv[cnt_e - 1]);
+        ti.wide = 0;
+        ti.count = cnt_e;
+        w.tiles[tile] = ti;
+    }
+}
+
+hipError_t launch_tile_sort(const hc_hit* hits, const Work& w, hipStream_t s)
+{
+    TimedLaunch tl("tile_sort", s);
+    dim3 grid(xcd_grid(w.n_sort_tiles)), block(kSortThreads);
+    switch (w.sort_ipt) {
+    case 4: hipLaunchKernelGGL(k_tile_sort<4>, grid, block, 0, s, hits, w); break;
+    case 8: hipLaunchKernelGGL(k_tile_sort<8>, grid, block, 0, s, hits, w); break;
+    case 16: hipLaunchKernelGGL(k_tile_sort<16>, grid, block, 0, s, hits, w); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- tile merge
+// Number of elements of a sorted tile (keys rel[0..cnt) relative to base)
+// smaller than key (toa, idx): elements of an earlier tile count when
+// toa <= key toa (their indices are smaller), of a later tile when toa < key.
+__device__ inline int count_below(const uint32_t* rel, int cnt, uint64_t base, uint64_t toa,
+                                  bool earlier, int lo)
+{
+    if (toa < base) return 0;
+    const uint64_t d64 = toa - base;
+    if (d64 > 0xFFFFFFFFull) return cnt;
+    const uint32_t d = (uint32_t)d64;
+    // first position in [lo, cnt) whose key is not below d (upper/lower bound)
+    int a = lo, b = cnt;
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        const bool below = earlier ? (rel[m] <= d) : (rel[m] < d);
+        if (below) a = m + 1; else b = m;
+    }
+    return a;
+}
+
+template <int IPT>
+__global__ __launch_bounds__(kSortThreads) void k_tile_merge(Work w)
+{
+    constexpr int T = kSortThreads * IPT;
+    __shared__ uint32_t nk[T];
+    if (w.status->sort_fallback) return;  // a wide tile: everything is re-sorted later
+    const int j = xcd_tile(w.n_sort_tiles);
+    if (j < 0) return;
+    const int t = threadIdx.x;
+    const int nt = w.n_sort_tiles, m = w.sort_m;
+    const TileInfo tj = w.tiles[j];
+
+    if (t == 0) {
+        bool bad = false;
+        if (j + 1 < nt) {
+            const TileInfo tn = w.tiles[j + 1];
+            bad |= key_less(tn.base, tn.min_idx, tj.base, tj.min_idx);
+            bad |= key_less(tn.max_toa, tn.max_idx, tj.max_toa, tj.max_idx);
+        }
+        if (j + m + 1 < nt) {
+            const TileInfo tf = w.tiles[j + m + 1];
+            bad |= !key_less(tj.max_toa, tj.max_idx, tf.base, tf.min_idx);
+        }
+        if (bad) atomicOr(&w.status->sort_fallback, 1);
+    }
+
+    const int64_t base = (int64_t)j * T;
+    const int r0 = t * IPT;
+    uint64_t toa[IPT];
+    int64_t rank[IPT];
+    const int first_tile = j - m < 0 ? 0 : j - m;
+#pragma unroll
+    for (int q = 0; q < IPT; q++) {
+        const int r = r0 + q;
+        toa[q] = r < tj.count ? tj.base + w.ts_rel[base + r] : ~0ull;
+        rank[q] = (int64_t)first_tile * T + r;
+    }
+    const int last_tile = j + m >= nt ? nt - 1 : j + m;
+    for (int i = first_tile; i <= last_tile; i++) {
+        if (i == j) continue;
+        const TileInfo ti = w.tiles[i];
+        __syncthreads();
+        for (int e = t; e < ti.count; e += kSortThreads) nk[e] = w.ts_rel[(int64_t)i * T + e];
+        __syncthreads();
+        int lo = 0;
+#pragma unroll
+        for (int q = 0; q < IPT; q++) {
+            if (r0 + q < tj.count) {
+                lo = count_below(nk, ti.count, ti.base, toa[q], i < j, lo);
+                rank[q] += lo;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < IPT; q++) {
+        const int r = r0 + q;
+        if (r < tj.count) {
+            const int64_t s = rank[q];
+            if (s >= 0 && s < w.n) {
+                w.s_toa[s] = toa[q];
+                w.s_idx[s] = (int32_t)(base + w.ts_lidx[base + r]);
+                w.s_xy[s] = w.ts_xy[base + r];
+                w.s_tot[s] = w.ts_tot[base + r];
+            }
+        }
+    }
+}
+
+hipError_t launch_tile_merge(const Work& w, hipStream_t s)
+{
+    TimedLaunch tl("tile_merge", s);
+    dim3 grid(xcd_grid(w.n_sort_tiles)), block(kSortThreads);
+    switch (w.sort_ipt) {
+    case 4: hipLaunchKernelGGL(k_tile_merge<4>, grid, block, 0, s, w); break;
+    case 8: hipLaunchKernelGGL(k_tile_merge<8>, grid, block, 0, s, w); break;
+    case 16: hipLaunchKernelGGL(k_tile_merge<16>, grid, block, 0, s, w); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ sort fallback
+struct ToaSortJob {
+    static constexpr bool kKeepSorted = false;
+    const hc_hit* hits;
+    Work w;
+    __device__ int64_t count() const { return w.n; }
+    __device__ void load(int64_t i, uint64_t& k, uint32_t& v) const
+    {
+        k = hits[i].toa;
+        v = (uint32_t)i;
+    }
+    __device__ int plan(RadixState& st, RadixLds& L)
+    {
+        // global ToA range from the tile minima / maxima
+        __shared__ uint64_t red[kFbThreads / kWave];
+        uint64_t mn = ~0ull, mx = 0;
+        for (int i = threadIdx.x; i < w.n_sort_tiles; i += kFbThreads) {
+            const TileInfo ti = w.tiles[i];
+            mn = ti.base < mn ? ti.base : mn;
+            mx = ti.max_toa > mx ? ti.max_toa : mx;
+        }
+        mn = block_min_u64<kFbThreads>(mn, red);
+        mx = block_max_u64<kFbThreads>(mx, red);
+        if (threadIdx.x == 0) {
+            const bool on = w.status->sort_fallback != 0 && w.status->err_range == 0;
+            st.active = on ? 1 : 0;
+            st.key_min = mn;
+            const uint64_t range = mx - mn;
+            const int bits = range == 0 ? 0 : 64 - __builtin_clzll(range);
+            st.passes = bits <= 8 ? 1 : (bits + 7) / 8;
+        }
+        (void)L;
+        return 0;
+    }
+    __device__ void store(int64_t pos, uint64_t rel, uint32_t v) const
+    {
+        const hc_hit h = hits[v];
+        w.s_toa[pos] = h.toa;
+        w.s_idx[pos] = (int32_t)v;
+        w.s_xy[pos] = (uint32_t)h.x | ((uint32_t)h.y << 16);
+        w.s_tot[pos] = h.tot;
+        (void)rel;
+    }
+    __device__ void extra(int, const uint64_t*, const uint32_t*, RadixLds&) {}
+};
+
+__global__ __launch_bounds__(kFbThreads) void k_sort_fallback(const hc_hit* __restrict__ hits, Work w)
+{
+    ToaSortJob job{hits, w};
+    uint64_t* kb[2] = {w.fb_key[0], w.fb_key[1]};
+    uint32_t* vb[2] = {w.fb_val[0], w.fb_val[1]};
+    radix_engine(job, &w.status->rs[0], kb, vb, w.fb_hist, w.n_fb_blocks, &w.status->err_internal);
+}
+
+int persistent_grid();
+
+hipError_t launch_sort_fallback(const hc_hit* hits, const Work& w, hipStream_t s)
+{
+    TimedLaunch tl("sort_fallback", s);
+    hipLaunchKernelGGL(k_sort_fallback, dim3(persistent_grid()), dim3(kFbThreads), 0, s, hits, w);
+    return hipGetLastError();
+}
+
+}  // namespace hc

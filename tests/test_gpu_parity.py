@@ -1,0 +1,190 @@
+"""GPU parity: labels and features of hc_cluster, called through the C-ABI,
+must equal the oracle's bit for bit (integer labels and sums exactly; the
+centroid doubles bit-exactly, as both sides perform one correctly rounded
+IEEE division of the same exact integers)."""
+import numpy as np
+import pytest
+
+import hitgen
+import oracle
+from refs import canonical, check_invariants
+
+pytestmark = pytest.mark.gpu
+
+U64MAX = (1 << 64) - 1
+
+
+@pytest.fixture(scope="module")
+def hc():
+    import torch
+    import paper_2412_11809_amd as hc
+    assert torch.cuda.is_available()
+    hc.load_library()
+    return hc
+
+
+def run_gpu(hc, hits, w, h, dt, hint=0, features=True, stream=None, workspace=None):
+    import torch
+    print("case: n=%d %dx%d dt=%d hint=%d" % (hits.size, w, h, dt, hint), flush=True)
+    d = hc.hits_to_device(hits)
+    labels, feats, k = hc.cluster(d, dt, w, h, disorder_hint=hint, features=features, stream=stream,
+                                  workspace=workspace)
+    torch.cuda.synchronize()
+    kk = int(k.item())
+    return labels.cpu().numpy(), (hc.features_to_numpy(feats, kk) if features else None), kk
+
+
+def assert_parity(hc, hits, w, h, dt, hint=0):
+    got_l, got_f, k = run_gpu(hc, hits, w, h, dt, hint)
+    want_l, want_f = oracle.cluster(hits, w, h, dt)
+    assert k == want_f.size, "cluster count %d, oracle %d" % (k, want_f.size)
+    bad = np.nonzero(got_l != want_l)[0]
+    assert bad.size == 0, "%d labels differ, first at %s: got %s want %s" % (
+        bad.size, bad[:5], got_l[bad[:5]], want_l[bad[:5]])
+    assert got_f.tobytes() == want_f.tobytes(), "features differ"
+    return got_l
+
+
+def test_config1_full(hc):
+    hits, p = hitgen.config1()
+    assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
+
+
+def test_config2_slice(hc):
+    hits, p = hitgen.config2(n=1_000_000, seed=99)
+    assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1023, 1024, 1025, 2047, 2048, 2049, 4097,
+                               8191, 8192, 8193, 65535, 65537, 200_003])
+def test_sizes(hc, n):
+    hits = hitgen.blob_stream(n, [5, n], span_ticks=max(64, n * 64), disorder=512)
+    assert_parity(hc, hits, 256, 256, 128, 512)
+
+
+def test_empty(hc):
+    import torch
+    import paper_2412_11809_amd as m
+    d = torch.empty(16, dtype=torch.uint8, device="cuda")
+    labels = torch.empty(1, dtype=torch.int32, device="cuda")
+    k = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+    m.hc_cluster(d, 0, 10, labels, None, k)
+    torch.cuda.synchronize()
+    assert k.item() == 0
+
+
+@pytest.mark.parametrize("hint", [0, 64, 512, 4096, 16384, 1 << 20])
+def test_disorder_hints(hc, hint):
+    """A wrong hint may cost speed, never exactness."""
+    hits = hitgen.blob_stream(300_000, [6, hint], disorder=6000, span_ticks=300_000 * 64)
+    assert_parity(hc, hits, 256, 256, 128, hint)
+
+
+def test_reversed_input(hc):
+    hits, p = hitgen.config1(n=50_000, seed=3)
+    hits = hits[np.argsort(hits["toa"], kind="stable")][::-1].copy()
+    assert_parity(hc, hits, 256, 256, p["dt"], 512)
+
+
+def test_dt_infinite_is_image_labelling(hc):
+    hits = hitgen.uniform_hits(40_000, 8, 256, 256, 1 << 30)
+    assert_parity(hc, hits, 256, 256, U64MAX, 512)
+
+
+def test_dt_zero(hc):
+    hits = hitgen.uniform_hits(60_000, 9, 64, 64, 5000, disorder=100)
+    assert_parity(hc, hits, 64, 64, 0, 128)
+
+
+def test_single_pixel(hc):
+    rng = np.random.default_rng(10)
+    hits = np.zeros(30_000, dtype=oracle.HIT_DTYPE)
+    hits["x"], hits["y"] = 17, 200
+    hits["toa"] = np.sort(rng.integers(0, 3_000_000, hits.size))
+    hits["tot"] = rng.integers(0, 50, hits.size)
+    assert_parity(hc, hits, 256, 256, 128, 512)
+
+
+def test_all_same_toa(hc):
+    hits = hitgen.uniform_hits(20_000, 11, 100, 100, 1)
+    assert_parity(hc, hits, 100, 100, 5, 512)
+
+
+def test_wide_toa_range(hc):
+    rng = np.random.default_rng(12)
+    hits = hitgen.uniform_hits(50_000, 12, 256, 256, 1)
+    hits["toa"] = np.sort(rng.integers(0, 1 << 62, hits.size)).astype(np.uint64)
+    hits["toa"][::7] += np.uint64(3)  # near-ties
+    assert_parity(hc, hits, 256, 256, 1 << 40, 512)
+
+
+def test_dense_small_sensor(hc):
+    hits = hitgen.uniform_hits(100_000, 13, 8, 8, 2_000_000, disorder=50)
+    assert_parity(hc, hits, 8, 8, 30, 64)
+
+
+def test_timepix4_sensor(hc):
+    hits, p = hitgen.config4(n=2_000_000)
+    assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
+
+
+def test_edges_of_sensor(hc):
+    rng = np.random.default_rng(14)
+    n = 50_000
+    hits = np.zeros(n, dtype=oracle.HIT_DTYPE)
+    hits["x"] = rng.choice([0, 1, 254, 255], n)
+    hits["y"] = rng.choice([0, 1, 254, 255], n)
+    hits["toa"] = np.sort(rng.integers(0, 50_000, n))
+    hits["tot"] = rng.integers(0, 1000, n)
+    assert_parity(hc, hits, 256, 256, 3, 512)
+
+
+def test_range_error_reported(hc):
+    hits, p = hitgen.config1(n=10_000, seed=4)
+    hits["x"][1234] = 256
+    _, _, k = run_gpu(hc, hits, 256, 256, 128, 512)
+    assert k == hc.HC_ERR_RANGE
+
+
+def test_repeatable(hc):
+    """Labels are schedule-independent: 20 repetitions agree exactly."""
+    hits, p = hitgen.config2(n=400_000, seed=21)
+    want = assert_parity(hc, hits, 256, 256, p["dt"], p["disorder"])
+    for _ in range(20):
+        got, _, _ = run_gpu(hc, hits, 256, 256, p["dt"], p["disorder"])
+        assert (got == want).all()
+
+
+def test_side_stream_and_workspace(hc):
+    import torch
+    hits, p = hitgen.config1(n=70_000, seed=5)
+    ws = torch.empty(hc.hc_workspace_size(hits.size, 256, 256, 512), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    got, gf, k = run_gpu(hc, hits, 256, 256, p["dt"], 512, stream=s, workspace=ws)
+    want, wf = oracle.cluster(hits, 256, 256, p["dt"])
+    assert (got == want).all() and gf.tobytes() == wf.tobytes()
+
+
+def test_small_workspace_rejected(hc):
+    import torch
+    d = hc.hits_to_device(hitgen.config1(n=5000)[0])
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    labels = torch.empty(5000, dtype=torch.int32, device="cuda")
+    k = torch.empty(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(hc.HcError) as e:
+        hc.hc_cluster(d, 5000, 128, labels, None, k, workspace=ws)
+    assert e.value.code == hc.HC_ERR_WORKSPACE
+
+
+def test_labels_only(hc):
+    hits, p = hitgen.config1(n=30_000, seed=6)
+    got, _, k = run_gpu(hc, hits, 256, 256, p["dt"], 512, features=False)
+    want, wf = oracle.cluster(hits, 256, 256, p["dt"])
+    assert (got == want).all() and k == wf.size
+
+
+def test_config2_full_size(hc):
+    """The benchmark's workload (10M hits) in the benchmark's configuration."""
+    hits, p = hitgen.config2()
+    got = assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
+    assert (got <= np.arange(got.size)).all()
