@@ -23,14 +23,13 @@ HBM_PEAK_GBS = 8000.0
 # write once, per hit and per cluster.  The whole path's figure is 20 B per
 # hit (read the 16-byte hit, write the 4-byte label) + 64 B per cluster.
 ALG_BYTES = {
-    "tile_sort": (16 + 12, 0),   # hit record in; rel ToA, tile index, pixel, ToT out
-    "tile_merge": (12 + 18, 0),  # sorted-tile record in; sorted ToA, pixel, ToT, index out
+    "tile_sort": (16 + 12, 0),   # hit record in; relative ToA + payload (index, ToT, pixel) out
+    "tile_rank": (4 + 4, 0),     # relative ToA in; global rank out
+    "tile_gather": (16 + 18, 0), # rank, relative ToA, payload in; sorted ToA, pixel, ToT, index out
     "link": (16 + 4, 0),         # sorted ToA, pixel, index in; parent out
-    "union_edges": (0, 0),
     "flatten": (4 + 4, 0),       # parent in; label out
     "features": (22, 64),        # index, label, ToA, pixel, ToT in; cluster record out
-    "carries": (0, 0),
-    "compact": (4, 64 + 64),     # labels in; record in, feature row out
+    "compact": (0, 64 + 64),     # cluster record in, feature row out
 }
 
 
@@ -74,6 +73,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--hits", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
@@ -155,6 +156,12 @@ def main():
         "kernels_ms_per_step": {name: round(v[1] / max(1, args.steps), 4) for name, v in sorted(times.items())},
         "sources": digest,
     }
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        out["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(hits, p, 30.0)
     print(json.dumps(out), flush=True)

@@ -61,19 +61,21 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.status = (Status*)take(sizeof(Status));
     x.tiles = (TileInfo*)take(sizeof(TileInfo) * (size_t)x.n_sort_tiles);
     x.ts_rel = (uint32_t*)take(4 * N);
-    x.ts_lidx = (uint16_t*)take(2 * N);
-    x.ts_xy = (uint32_t*)take(4 * N);
-    x.ts_tot = (uint16_t*)take(2 * N);
+    x.ts_pay = (uint2*)take(8 * N);
+    x.ts_rank = (uint32_t*)take(4 * N);
     x.s_toa = (uint64_t*)take(8 * N);
     x.s_xy = (uint32_t*)take(4 * N);
     x.s_tot = (uint16_t*)take(2 * N);
     x.s_idx = (int32_t*)take(4 * N);
+    x.link_h0 = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.gparent = (int32_t*)take(4 * N);
     x.edges = (int2*)take(sizeof(int2) * (size_t)x.edge_cap);
     x.overflow_tiles = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.slots = (SlotRec*)take(sizeof(SlotRec) * N);
     x.carries = (SlotRec*)take(sizeof(SlotRec) * (size_t)x.carry_cap);
-    x.scan_state = (unsigned long long*)take(8 * (size_t)x.n_scan_blocks);
+    x.blk_count = (uint32_t*)take(4 * (size_t)x.n_scan_blocks);
+    x.blk_off = (uint32_t*)take(4 * (size_t)x.n_scan_blocks);
+    x.root_mask = (unsigned long long*)take(8 * (size_t)x.n_scan_blocks * (kScanBlock / 64));
     x.fb_key[0] = (uint64_t*)take(8 * N);
     x.fb_key[1] = (uint64_t*)take(8 * N);
     x.fb_val[0] = (uint32_t*)take(4 * N);
@@ -215,6 +217,7 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_f
     HC_LAUNCH(launch_tile_sort(hits, w, s), "tile_sort");
     if (!w.force_fallback) HC_LAUNCH(launch_tile_merge(w, s), "tile_merge");
     HC_LAUNCH(launch_sort_fallback(hits, w, s), "sort_fallback");
+    HC_LAUNCH(launch_link_halo(w, s), "link_halo");
     HC_LAUNCH(launch_link(w, s), "link");
     HC_LAUNCH(launch_link_fallback(w, s), "link_fallback");
     HC_LAUNCH(launch_union_edges(w, s), "union_edges");

@@ -79,20 +79,56 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         }
     }
     __syncthreads();
+    // Consecutive sorted hits of one cluster sit in consecutive lanes: reduce
+    // each run of equal slots inside the wave first (segmented scans), so only
+    // the run's last lane touches the LDS accumulators.
+    const int lane = t & (kWave - 1);
+    const unsigned long long le_mask = lane == kWave - 1 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         const int s = slot[q];
-        if (s < 0) continue;
-        const uint32_t x = xy[q] & 0xFFFFu, y = xy[q] >> 16;
-        atomicAdd(&a_size[s], 1u);
-        atomicAdd(&a_st[s], tot[q]);
-        atomicAdd(&a_sx[s], x);
-        atomicAdd(&a_sy[s], y);
-        atomicAdd(&a_sxt[s], (unsigned long long)x * tot[q]);
-        atomicAdd(&a_syt[s], (unsigned long long)y * tot[q]);
-        atomicMin(&a_tmin[s], (unsigned long long)toa[q]);
-        atomicMax(&a_tmax[s], (unsigned long long)toa[q]);
-        if ((uint32_t)idx[q] + 1u == h_key[s]) a_own[s] = 1u;
+        const int sp = __shfl_up(s, 1, kWave);
+        const bool head = lane == 0 || sp != s;
+        const unsigned long long heads = __ballot(head);
+        const int start = kWave - 1 - __clzll(heads & le_mask);
+        const bool tail = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ull);
+        const bool valid = s >= 0;
+        const uint32_t x = valid ? (xy[q] & 0xFFFFu) : 0u, y = valid ? (xy[q] >> 16) : 0u;
+        uint32_t c = valid ? 1u : 0u, st = valid ? tot[q] : 0u, sx = x, sy = y;
+        uint32_t own = (valid && (uint32_t)idx[q] + 1u == h_key[s]) ? 1u : 0u;
+        unsigned long long sxt = (unsigned long long)x * st, syt = (unsigned long long)y * st;
+        unsigned long long tmn = valid ? (unsigned long long)toa[q] : ~0ull;
+        unsigned long long tmx = valid ? (unsigned long long)toa[q] : 0ull;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t c2 = __shfl_up(c, o, kWave), st2 = __shfl_up(st, o, kWave);
+            const uint32_t sx2 = __shfl_up(sx, o, kWave), sy2 = __shfl_up(sy, o, kWave);
+            const uint32_t own2 = __shfl_up(own, o, kWave);
+            const unsigned long long sxt2 = __shfl_up(sxt, o, kWave), syt2 = __shfl_up(syt, o, kWave);
+            const unsigned long long tmn2 = __shfl_up(tmn, o, kWave), tmx2 = __shfl_up(tmx, o, kWave);
+            if (lane - o >= start) {
+                c += c2;
+                st += st2;
+                sx += sx2;
+                sy += sy2;
+                own |= own2;
+                sxt += sxt2;
+                syt += syt2;
+                tmn = tmn2 < tmn ? tmn2 : tmn;
+                tmx = tmx2 > tmx ? tmx2 : tmx;
+            }
+        }
+        if (tail && valid) {
+            atomicAdd(&a_size[s], c);
+            atomicAdd(&a_st[s], st);
+            atomicAdd(&a_sx[s], sx);
+            atomicAdd(&a_sy[s], sy);
+            atomicAdd(&a_sxt[s], sxt);
+            atomicAdd(&a_syt[s], syt);
+            atomicMin(&a_tmin[s], tmn);
+            atomicMax(&a_tmax[s], tmx);
+            if (own) a_own[s] = 1u;
+        }
     }
     __syncthreads();
     for (int s = t; s < kFeatHash; s += kFeatThreads) {
@@ -155,63 +191,45 @@ hipError_t launch_carries(const Work& w, hipStream_t s)
 }
 
 // ------------------------------------------------------------ compaction
-constexpr unsigned long long kAgg = 1ull << 62, kIncl = 2ull << 62, kValMask = (1ull << 62) - 1;
-
-__global__ __launch_bounds__(kScanThreads) void k_compact(Work w, const int32_t* __restrict__ labels,
-                                                          hc_features* __restrict__ out, int32_t* n_clusters)
+// Exclusive scan of the per-block root counts (one work-group), which also
+// writes the cluster count (or the error status) to the caller.
+__global__ __launch_bounds__(1024) void k_scan_blocks(Work w, int32_t* n_clusters)
 {
-    constexpr int PER = kScanBlock / kScanThreads;
-    __shared__ int s_tile;
-    __shared__ uint32_t wsum[kScanThreads / kWave];
-    __shared__ unsigned long long s_prefix;
-    const int t = threadIdx.x;
-    if (t == 0) s_tile = atomicAdd(&w.status->scan_ticket, 1);
-    __syncthreads();
-    const int tile = s_tile;
-    if (w.status->err_range || w.status->err_internal) {
-        if (tile == 0 && t == 0) *n_clusters = w.status->err_range ? HC_ERR_RANGE : HC_ERR_DEVICE;
+    __shared__ uint32_t wsum[1024 / kWave];
+    const Status* st = w.status;
+    if (st->err_range || st->err_internal) {
+        if (threadIdx.x == 0) *n_clusters = st->err_range ? HC_ERR_RANGE : HC_ERR_DEVICE;
         return;
     }
-    const int64_t i0 = (int64_t)tile * kScanBlock + (int64_t)t * PER;
-    uint32_t flags = 0, c = 0;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < w.n_scan_blocks; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const uint32_t v = i < w.n_scan_blocks ? w.blk_count[i] : 0u;
+        uint32_t total;
+        const uint32_t e = block_exclusive_scan<1024>(v, wsum, &total);
+        if (i < w.n_scan_blocks) w.blk_off[i] = carry + e;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *n_clusters = (int32_t)carry;
+}
+
+// features[rank] for every root of one block of kScanBlock input indices.
+__global__ __launch_bounds__(kScanThreads) void k_compact(Work w, hc_features* __restrict__ out)
+{
+    constexpr int PER = kScanBlock / kScanThreads;  // 8 consecutive indices per thread
+    __shared__ uint32_t wsum[kScanThreads / kWave];
+    if (w.status->err_range || w.status->err_internal) return;
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int64_t base = (int64_t)b * kScanBlock;
+    // bits of indices [base + PER*t, base + PER*t + PER) within mask word (PER*t)/64
+    const unsigned long long word = w.root_mask[(int64_t)b * (kScanBlock / 64) + (PER * t) / 64];
+    const uint32_t bits = (uint32_t)((word >> ((PER * t) % 64)) & ((1u << PER) - 1u));
+    const uint32_t off = block_exclusive_scan<kScanThreads>(__popc(bits), wsum, nullptr);
+    uint64_t k = (uint64_t)w.blk_off[b] + off;
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-        const int64_t i = i0 + q;
-        if (i < w.n && labels[i] == (int32_t)i) {
-            flags |= 1u << q;
-            c++;
-        }
-    }
-    uint32_t total;
-    const uint32_t off = block_exclusive_scan<kScanThreads>(c, wsum, &total);
-    if (t == 0) {
-        unsigned long long prefix = 0;
-        if (tile == 0) {
-            __hip_atomic_store(&w.scan_state[0], kIncl | total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&w.scan_state[tile], kAgg | total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            int pred = tile - 1;
-            while (true) {
-                unsigned long long v;
-                while ((v = __hip_atomic_load(&w.scan_state[pred], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == 0ull)
-                    __builtin_amdgcn_s_sleep(1);
-                prefix += v & kValMask;
-                if (v & kIncl) break;
-                pred--;
-            }
-            __hip_atomic_store(&w.scan_state[tile], kIncl | (prefix + total), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-        s_prefix = prefix;
-        if (tile == w.n_scan_blocks - 1) *n_clusters = (int32_t)(prefix + total);
-    }
-    __syncthreads();
-    if (!out) return;
-    uint64_t k = s_prefix + off;
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-        if (!(flags & (1u << q))) continue;
-        const int64_t i = i0 + q;
+        if (!(bits & (1u << q))) continue;
+        const int64_t i = base + PER * t + q;
         const SlotRec r = w.slots[i];
         hc_features f;
         f.label = (int32_t)i;
@@ -235,8 +253,16 @@ __global__ __launch_bounds__(kScanThreads) void k_compact(Work w, const int32_t*
 hipError_t launch_compact(const Work& w, const int32_t* labels, hc_features* features, int32_t* n_clusters,
                           hipStream_t s)
 {
+    (void)labels;
+    {
+        TimedLaunch tl("scan_blocks", s);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, w, n_clusters);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (!features) return hipSuccess;
     TimedLaunch tl("compact", s);
-    hipLaunchKernelGGL(k_compact, dim3(w.n_scan_blocks), dim3(kScanThreads), 0, s, w, labels, features, n_clusters);
+    hipLaunchKernelGGL(k_compact, dim3(w.n_scan_blocks), dim3(kScanThreads), 0, s, w, features);
     return hipGetLastError();
 }
 

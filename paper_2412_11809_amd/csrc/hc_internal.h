@@ -13,7 +13,8 @@ namespace hc {
 constexpr int kSortThreads = 512;     // threads of the tile-sort / merge kernels
 constexpr int kLinkTile = 1024;       // sorted hits per link work-group
 constexpr int kLinkHaloCap = 1024;    // earlier hits a link work-group can hold
-constexpr int kLinkThreads = 256;
+constexpr int kLinkThreads = 512;
+constexpr int kLinkBitmapMaxWords = 8192;  // occupancy bitmap for sensors up to 512 x 512
 constexpr int kLinkHash = 4096;       // pixel hash slots (>= 2 x (tile + halo))
 constexpr int kFeatTile = 512;        // sorted hits per feature work-group
 constexpr int kFeatThreads = 256;
@@ -90,20 +91,22 @@ struct Work {
 
     Status* status;
     TileInfo* tiles;
-    uint32_t* ts_rel;
-    uint16_t* ts_lidx;
-    uint32_t* ts_xy;
-    uint16_t* ts_tot;
+    uint32_t* ts_rel;     // tile-sorted ToA relative to the tile minimum
+    uint2* ts_pay;        // tile-sorted payload: (local index | ToT << 16, x | y << 16)
+    uint32_t* ts_rank;    // tile-sorted global rank
     uint64_t* s_toa;
     uint32_t* s_xy;
     uint16_t* s_tot;
     int32_t* s_idx;
+    int32_t* link_h0;     // per link tile: first halo position, or -1 if it overflows
     int32_t* gparent;
     int2* edges;
     int32_t* overflow_tiles;
     SlotRec* slots;
     SlotRec* carries;
-    unsigned long long* scan_state;
+    uint32_t* blk_count;              // roots per block of kScanBlock indices
+    uint32_t* blk_off;                // exclusive scan of blk_count
+    unsigned long long* root_mask;    // one bit per input index: labels[i] == i
     uint64_t* fb_key[2];
     uint32_t* fb_val[2];
     uint32_t* fb_hist;
@@ -117,6 +120,7 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
 hipError_t launch_init(const Work& w, hipStream_t s);
 hipError_t launch_tile_sort(const hc_hit* hits, const Work& w, hipStream_t s);
 hipError_t launch_tile_merge(const Work& w, hipStream_t s);
+hipError_t launch_link_halo(const Work& w, hipStream_t s);
 hipError_t launch_sort_fallback(const hc_hit* hits, const Work& w, hipStream_t s);
 hipError_t launch_link(const Work& w, hipStream_t s);
 hipError_t launch_link_fallback(const Work& w, hipStream_t s);

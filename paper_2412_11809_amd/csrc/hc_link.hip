@@ -71,18 +71,51 @@ __device__ inline void lunion(int32_t* par, const int32_t* idx, int32_t a, int32
     }
 }
 
-__global__ __launch_bounds__(kLinkThreads) void k_link(Work w)
+// First halo position of every link tile: the earliest sorted position p
+// with toa(p) >= toa(p0) - dt (a suffix of the positions before p0, so a
+// binary search), or -1 when the halo exceeds kLinkHaloCap or the tile's
+// ToA span does not fit 32 bits (such tiles go to the fallback).
+__global__ void k_link_halo(Work w)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= w.n_link_tiles || w.status->err_range) return;
+    const int64_t p0 = (int64_t)k * kLinkTile;
+    const int64_t p1 = (p0 + kLinkTile) < w.n ? (p0 + kLinkTile) : w.n;
+    const uint64_t lo = sat_sub_u64(w.s_toa[p0], w.dt);
+    const int64_t lim = p0 - kLinkHaloCap > 0 ? p0 - kLinkHaloCap : 0;
+    int64_t a = lim, b = p0;
+    while (a < b) {
+        const int64_t m = (a + b) >> 1;
+        if (w.s_toa[m] < lo) a = m + 1; else b = m;
+    }
+    bool overflow = (a == lim && lim > 0 && w.s_toa[lim - 1] >= lo);
+    overflow |= (w.s_toa[p1 - 1] - w.s_toa[a]) > 0xFFFFFFFFull;
+    w.link_h0[k] = overflow ? -1 : (int32_t)a;
+}
+
+hipError_t launch_link_halo(const Work& w, hipStream_t s)
+{
+    TimedLaunch tl("link_halo", s);
+    hipLaunchKernelGGL(k_link_halo, dim3((w.n_link_tiles + 255) / 256), dim3(256), 0, s, w);
+    return hipGetLastError();
+}
+
+constexpr uint64_t kEmptySlot = 0ull;
+
+// One work-group per tile of kLinkTile sorted hits (+ halo), all in LDS.
+// Dynamic LDS holds an occupancy bitmap of the sensor (bm_words words; 0 =
+// no bitmap, every neighbour pixel is looked up in the hash).
+__global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
 {
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
+    constexpr int PER = kLinkTile / kLinkThreads;
     __shared__ uint32_t l_toa[LCAP];
     __shared__ uint32_t l_xy[LCAP];
     __shared__ int32_t l_idx[LCAP];
     __shared__ int32_t l_par[LCAP];
     __shared__ int16_t l_next[LCAP];
-    __shared__ uint32_t h_key[kLinkHash];
-    __shared__ int32_t h_head[kLinkHash];
-    __shared__ int64_t s_h0;
-    __shared__ int s_overflow;
+    __shared__ unsigned long long h_slot[kLinkHash];  // (pixel key << 32) | list head
+    extern __shared__ uint32_t bm[];
 
     if (w.status->err_range) return;
     const int tile = xcd_tile(w.n_link_tiles);
@@ -90,32 +123,8 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w)
     const int t = threadIdx.x;
     const int64_t p0 = (int64_t)tile * kLinkTile;
     const int64_t p1 = (p0 + kLinkTile) < w.n ? (p0 + kLinkTile) : w.n;
-
-    // ---- halo: earlier hits with toa >= toa(first) - dt (a suffix of the
-    // sorted positions before p0), searched backwards 64 at a time
-    if (t < kWave) {
-        const uint64_t lo = sat_sub_u64(w.s_toa[p0], w.dt);
-        const int64_t lim = p0 - kLinkHaloCap > 0 ? p0 - kLinkHaloCap : 0;
-        int64_t c = p0, h0 = p0;
-        while (c > lim) {
-            const int64_t cs = c - kWave > lim ? c - kWave : lim;
-            const int64_t q = c - kWave + t;
-            const bool in = q >= cs && w.s_toa[q] >= lo;
-            const int nin = __popcll(__ballot(in));
-            h0 = c - nin;
-            if (nin < c - cs) break;
-            c = cs;
-        }
-        bool overflow = (h0 == lim && lim > 0 && w.s_toa[lim - 1] >= lo);
-        overflow |= (w.s_toa[p1 - 1] - w.s_toa[h0]) > 0xFFFFFFFFull;
-        if (t == 0) {
-            s_h0 = h0;
-            s_overflow = overflow ? 1 : 0;
-        }
-    }
-    __syncthreads();
-    const int64_t h0 = s_h0;
-    if (s_overflow) {
+    const int64_t h0 = w.link_h0[tile];
+    if (h0 < 0) {  // halo too large: every hit is its own root here, the fallback joins them
         for (int64_t p = p0 + t; p < p1; p += kLinkThreads) {
             const int32_t id = w.s_idx[p];
             if (id >= 0 && id < w.n) w.gparent[id] = id;
@@ -130,6 +139,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w)
     const int L = (int)(p1 - h0);
     const int hl = (int)(p0 - h0);
     const uint64_t tbase = w.s_toa[h0];
+    const uint32_t W = w.width;
     for (int i = t; i < L; i += kLinkThreads) {
         const int64_t p = h0 + i;
         l_toa[i] = (uint32_t)(w.s_toa[p] - tbase);
@@ -142,48 +152,65 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w)
         l_idx[i] = id;
         l_par[i] = i;
     }
-    for (int i = t; i < kLinkHash; i += kLinkThreads) {
-        h_key[i] = 0u;
-        h_head[i] = -1;
-    }
+    for (int i = t; i < kLinkHash; i += kLinkThreads) h_slot[i] = kEmptySlot;
+    for (int i = t; i < bm_words; i += kLinkThreads) bm[i] = 0u;
     __syncthreads();
 
-    // ---- pixel hash: slot per occupied pixel, list of its hits
+    // ---- pixel hash (slot per occupied pixel, list of its hits) and bitmap
     for (int i = t; i < L; i += kLinkThreads) {
-        const uint32_t key = l_xy[i] + 1u;
+        const uint32_t xy = l_xy[i];
+        const uint32_t key = xy + 1u;
         uint32_t slot = pix_hash(key);
         while (true) {
-            const uint32_t old = atomicCAS(&h_key[slot], 0u, key);
-            if (old == 0u || old == key) break;
+            const unsigned long long mine = ((unsigned long long)key << 32) | 0xFFFFFFFFull;
+            const unsigned long long old = atomicCAS(&h_slot[slot], kEmptySlot, mine);
+            if (old == kEmptySlot || (uint32_t)(old >> 32) == key) break;
             slot = (slot + 1u) & (kLinkHash - 1);
         }
-        l_next[i] = (int16_t)atomicExch(&h_head[slot], i);
+        // push onto the slot's list: exchange the low half (the head)
+        l_next[i] = (int16_t)atomicExch(reinterpret_cast<int32_t*>(&h_slot[slot]), i);
+        if (bm_words) {
+            const uint32_t pix = (xy >> 16) * W + (xy & 0xFFFFu);
+            atomicOr(&bm[pix >> 5], 1u << (pix & 31u));
+        }
     }
     __syncthreads();
 
     // ---- neighbour search of the tile hits
     const uint64_t dt = w.dt;
-    const int W = (int)w.width, H = (int)w.height;
-    for (int i = hl + t; i < L; i += kLinkThreads) {
+    const int H = (int)w.height;
+#pragma unroll 1
+    for (int q = 0; q < PER; q++) {
+        const int i = hl + t + q * kLinkThreads;
+        if (i >= L) break;
         const uint32_t xy = l_xy[i];
         const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
         const uint32_t ti = l_toa[i];
-        for (int dy = -1; dy <= 1; dy++) {
-            const int qy = y + dy;
+        const int xlo = x > 0 ? x - 1 : 0;
+        const int xhi = x + 1 < (int)W ? x + 1 : (int)W - 1;
+        for (int qy = y - 1; qy <= y + 1; qy++) {
             if (qy < 0 || qy >= H) continue;
-            for (int dx = -1; dx <= 1; dx++) {
-                const int qx = x + dx;
-                if (qx < 0 || qx >= W) continue;
-                const uint32_t key = ((uint32_t)qx | ((uint32_t)qy << 16)) + 1u;
+            uint32_t occ = (1u << (xhi - xlo + 1)) - 1u;  // bit k: pixel xlo + k
+            if (bm_words) {
+                const uint32_t pa = (uint32_t)qy * W + (uint32_t)xlo;
+                const uint32_t wa = pa >> 5, sh = pa & 31u;
+                uint64_t bits = bm[wa];
+                if (sh > 29u && wa + 1 < (uint32_t)bm_words) bits |= (uint64_t)bm[wa + 1] << 32;
+                occ &= (uint32_t)(bits >> sh);
+            }
+            while (occ) {
+                const int k = __builtin_ctz(occ);
+                occ &= occ - 1u;
+                const uint32_t key = ((uint32_t)(xlo + k) | ((uint32_t)qy << 16)) + 1u;
                 uint32_t slot = pix_hash(key);
                 int a = -1;
                 while (true) {
-                    const uint32_t k = h_key[slot];
-                    if (k == key) {
-                        a = h_head[slot];
+                    const unsigned long long v = h_slot[slot];
+                    if ((uint32_t)(v >> 32) == key) {
+                        a = (int32_t)(uint32_t)v;
                         break;
                     }
-                    if (k == 0u) break;
+                    if (v == kEmptySlot) break;
                     slot = (slot + 1u) & (kLinkHash - 1);
                 }
                 while (a >= 0) {
@@ -216,7 +243,10 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w)
 hipError_t launch_link(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("link", s);
-    hipLaunchKernelGGL(k_link, dim3(xcd_grid(w.n_link_tiles)), dim3(kLinkThreads), 0, s, w);
+    const uint64_t pixels = (uint64_t)w.width * w.height;
+    const int bm_words = pixels <= (uint64_t)kLinkBitmapMaxWords * 32 ? (int)((pixels + 31) / 32) : 0;
+    hipLaunchKernelGGL(k_link, dim3(xcd_grid(w.n_link_tiles)), dim3(kLinkThreads), (size_t)bm_words * 4, s, w,
+                       bm_words);
     return hipGetLastError();
 }
 
@@ -301,6 +331,7 @@ struct PixSortJob {
 
 __global__ __launch_bounds__(kFbThreads) void k_link_fallback(Work w)
 {
+    if (!w.status->n_overflow || w.status->err_range) return;  // the common case
     PixSortJob job{w};
     uint64_t* kb[2] = {w.fb_key[0], w.fb_key[1]};
     uint32_t* vb[2] = {w.fb_val[0], w.fb_val[1]};
@@ -335,20 +366,40 @@ hipError_t launch_union_edges(const Work& w, hipStream_t s)
 }
 
 // ------------------------------------------------------------ flatten
-__global__ void k_flatten(Work w, int32_t* __restrict__ labels)
+// labels[i] = root(i).  One work-group per block of kScanBlock indices; a
+// root (labels[i] == i) is a cluster: its bit is set in the block's mask and
+// the block's root count is stored for the compaction scan.
+__global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __restrict__ labels)
 {
+    static_assert(kScanBlock == 8 * kScanThreads && kScanThreads % kWave == 0, "mask layout");
+    __shared__ uint32_t wsum[kScanThreads / kWave];
     if (w.status->err_range) return;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < w.n; i += (int64_t)gridDim.x * blockDim.x)
-        labels[i] = gfind(w.gparent, (int32_t)i, &w.status->err_internal);
+    const int b = blockIdx.x;
+    const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    const int64_t base = (int64_t)b * kScanBlock;
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < kScanBlock / kScanThreads; q++) {
+        const int64_t i = base + q * kScanThreads + t;
+        bool root = false;
+        if (i < w.n) {
+            const int32_t r = gfind(w.gparent, (int32_t)i, &w.status->err_internal);
+            labels[i] = r;
+            root = (r == (int32_t)i);
+        }
+        const unsigned long long m = __ballot(root);
+        if (lane == 0) w.root_mask[(int64_t)b * (kScanBlock / 64) + q * (kScanThreads / kWave) + wid] = m;
+        c += root;
+    }
+    uint32_t total;
+    block_exclusive_scan<kScanThreads>(c, wsum, &total);
+    if (t == 0) w.blk_count[b] = total;
 }
 
 hipError_t launch_flatten(const Work& w, int32_t* labels, hipStream_t s)
 {
     TimedLaunch tl("flatten", s);
-    int64_t blocks = ((int64_t)w.n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_flatten, dim3((unsigned)blocks), dim3(256), 0, s, w, labels);
+    hipLaunchKernelGGL(k_flatten, dim3(w.n_scan_blocks), dim3(kScanThreads), 0, s, w, labels);
     return hipGetLastError();
 }
 

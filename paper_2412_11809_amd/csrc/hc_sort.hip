@@ -31,16 +31,13 @@ __global__ void k_init(Work w)
     const int stride = gridDim.x * blockDim.x;
     int32_t* s = reinterpret_cast<int32_t*>(w.status);
     for (int i = t; i < (int)(sizeof(Status) / 4); i += stride) s[i] = 0;
-    for (int i = t; i < w.n_scan_blocks; i += stride) w.scan_state[i] = 0ull;
     if (t == 0 && w.force_fallback) w.status->sort_fallback = 1;
 }
 
 hipError_t launch_init(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("init", s);
-    int blocks = (w.n_scan_blocks + 255) / 256;
-    blocks = blocks < 1 ? 1 : (blocks > 64 ? 64 : blocks);
-    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, w);
     return hipGetLastError();
 }
 
@@ -116,9 +113,8 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __rest
             }
             const hc_hit h = hits[base + l];
             w.ts_rel[base + e] = sk[e];
-            w.ts_lidx[base + e] = l;
-            w.ts_xy[base + e] = (uint32_t)h.x | ((uint32_t)h.y << 16);
-            w.ts_tot[base + e] = h.tot;
+            w.ts_pay[base + e] = make_uint2((uint32_t)l | ((uint32_t)h.tot << 16),
+                                            (uint32_t)h.x | ((uint32_t)h.y << 16));
         }
     }
     if (t == 0) {
@@ -150,6 +146,7 @@ hipError_t launch_tile_sort(const hc_hit* hits, const Work& w, hipStream_t s)
 // Number of elements of a sorted tile (keys rel[0..cnt) relative to base)
 // smaller than key (toa, idx): elements of an earlier tile count when
 // toa <= key toa (their indices are smaller), of a later tile when toa < key.
+// Searches [lo, cnt) only: the caller's keys ascend, so counts do too.
 __device__ inline int count_below(const uint32_t* rel, int cnt, uint64_t base, uint64_t toa,
                                   bool earlier, int lo)
 {
@@ -157,7 +154,6 @@ __device__ inline int count_below(const uint32_t* rel, int cnt, uint64_t base, u
     const uint64_t d64 = toa - base;
     if (d64 > 0xFFFFFFFFull) return cnt;
     const uint32_t d = (uint32_t)d64;
-    // first position in [lo, cnt) whose key is not below d (upper/lower bound)
     int a = lo, b = cnt;
     while (a < b) {
         const int m = (a + b) >> 1;
@@ -167,8 +163,12 @@ __device__ inline int count_below(const uint32_t* rel, int cnt, uint64_t base, u
     return a;
 }
 
+// Global rank of every element of tile j: all elements of tiles before
+// j - m, its position in its own tile, and its count in each neighbour tile.
+// Written in tile-sorted order (coalesced).  Also checks the conditions
+// under which this is exact.
 template <int IPT>
-__global__ __launch_bounds__(kSortThreads) void k_tile_merge(Work w)
+__global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
 {
     constexpr int T = kSortThreads * IPT;
     __shared__ uint32_t nk[T];
@@ -196,13 +196,13 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_merge(Work w)
     const int64_t base = (int64_t)j * T;
     const int r0 = t * IPT;
     uint64_t toa[IPT];
-    int64_t rank[IPT];
+    uint32_t rank[IPT];
     const int first_tile = j - m < 0 ? 0 : j - m;
 #pragma unroll
     for (int q = 0; q < IPT; q++) {
         const int r = r0 + q;
         toa[q] = r < tj.count ? tj.base + w.ts_rel[base + r] : ~0ull;
-        rank[q] = (int64_t)first_tile * T + r;
+        rank[q] = (uint32_t)((int64_t)first_tile * T + r);
     }
     const int last_tile = j + m >= nt ? nt - 1 : j + m;
     for (int i = first_tile; i <= last_tile; i++) {
@@ -216,33 +216,78 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_merge(Work w)
         for (int q = 0; q < IPT; q++) {
             if (r0 + q < tj.count) {
                 lo = count_below(nk, ti.count, ti.base, toa[q], i < j, lo);
-                rank[q] += lo;
+                rank[q] += (uint32_t)lo;
             }
         }
     }
 #pragma unroll
-    for (int q = 0; q < IPT; q++) {
-        const int r = r0 + q;
-        if (r < tj.count) {
-            const int64_t s = rank[q];
-            if (s >= 0 && s < w.n) {
-                w.s_toa[s] = toa[q];
-                w.s_idx[s] = (int32_t)(base + w.ts_lidx[base + r]);
-                w.s_xy[s] = w.ts_xy[base + r];
-                w.s_tot[s] = w.ts_tot[base + r];
-            }
+    for (int q = 0; q < IPT; q++)
+        if (r0 + q < tj.count) w.ts_rank[base + r0 + q] = rank[q];
+}
+
+// Output tile k (sorted positions [kT, kT + T)) collects the elements of
+// tiles k-m .. k+m whose rank falls in it, then writes the sorted arrays
+// with coalesced stores.
+template <int IPT>
+__global__ __launch_bounds__(kSortThreads) void k_tile_gather(Work w)
+{
+    constexpr int T = kSortThreads * IPT;
+    __shared__ uint32_t slot[T];
+    if (w.status->sort_fallback) return;
+    const int k = xcd_tile(w.n_sort_tiles);
+    if (k < 0) return;
+    const int t = threadIdx.x;
+    const int nt = w.n_sort_tiles, m = w.sort_m;
+    const int64_t out0 = (int64_t)k * T;
+    const int cnt_out = (int)((w.n - out0) < T ? (w.n - out0) : T);
+    for (int r = t; r < T; r += kSortThreads) slot[r] = 0xFFFFFFFFu;
+    __syncthreads();
+    const int first_tile = k - m < 0 ? 0 : k - m;
+    const int last_tile = k + m >= nt ? nt - 1 : k + m;
+    for (int i = first_tile; i <= last_tile; i++) {
+        const int ci = w.tiles[i].count;
+        for (int e = t; e < ci; e += kSortThreads) {
+            const int64_t r = (int64_t)w.ts_rank[(int64_t)i * T + e] - out0;
+            if (r >= 0 && r < cnt_out) slot[r] = ((uint32_t)(i - first_tile) << 16) | (uint32_t)e;
         }
+    }
+    __syncthreads();
+    for (int r = t; r < cnt_out; r += kSortThreads) {
+        const uint32_t v = slot[r];
+        if (v == 0xFFFFFFFFu) {
+            atomicOr(&w.status->err_internal, 1);
+            continue;
+        }
+        const int i = first_tile + (int)(v >> 16);
+        const int64_t src = (int64_t)i * T + (v & 0xFFFFu);
+        const uint2 pay = w.ts_pay[src];
+        const int64_t dst = out0 + r;
+        w.s_toa[dst] = w.tiles[i].base + w.ts_rel[src];
+        w.s_idx[dst] = (int32_t)((int64_t)i * T + (pay.x & 0xFFFFu));
+        w.s_tot[dst] = (uint16_t)(pay.x >> 16);
+        w.s_xy[dst] = pay.y;
     }
 }
 
 hipError_t launch_tile_merge(const Work& w, hipStream_t s)
 {
-    TimedLaunch tl("tile_merge", s);
     dim3 grid(xcd_grid(w.n_sort_tiles)), block(kSortThreads);
+    {
+        TimedLaunch tl("tile_rank", s);
+        switch (w.sort_ipt) {
+        case 4: hipLaunchKernelGGL(k_tile_rank<4>, grid, block, 0, s, w); break;
+        case 8: hipLaunchKernelGGL(k_tile_rank<8>, grid, block, 0, s, w); break;
+        case 16: hipLaunchKernelGGL(k_tile_rank<16>, grid, block, 0, s, w); break;
+        default: return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    TimedLaunch tl("tile_gather", s);
     switch (w.sort_ipt) {
-    case 4: hipLaunchKernelGGL(k_tile_merge<4>, grid, block, 0, s, w); break;
-    case 8: hipLaunchKernelGGL(k_tile_merge<8>, grid, block, 0, s, w); break;
-    case 16: hipLaunchKernelGGL(k_tile_merge<16>, grid, block, 0, s, w); break;
+    case 4: hipLaunchKernelGGL(k_tile_gather<4>, grid, block, 0, s, w); break;
+    case 8: hipLaunchKernelGGL(k_tile_gather<8>, grid, block, 0, s, w); break;
+    case 16: hipLaunchKernelGGL(k_tile_gather<16>, grid, block, 0, s, w); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -296,6 +341,7 @@ struct ToaSortJob {
 
 __global__ __launch_bounds__(kFbThreads) void k_sort_fallback(const hc_hit* __restrict__ hits, Work w)
 {
+    if (!w.status->sort_fallback || w.status->err_range) return;  // the common case
     ToaSortJob job{hits, w};
     uint64_t* kb[2] = {w.fb_key[0], w.fb_key[1]};
     uint32_t* vb[2] = {w.fb_val[0], w.fb_val[1]};
