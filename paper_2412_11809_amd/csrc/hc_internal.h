@@ -14,8 +14,8 @@ constexpr int kSortThreads = 512;     // threads of the tile-sort / merge kernel
 constexpr int kLinkTile = 1024;       // sorted hits per link work-group
 constexpr int kLinkHaloCap = 1024;    // earlier hits a link work-group can hold
 constexpr int kLinkThreads = 512;
-constexpr int kLinkBitmapMaxWords = 8192;  // occupancy bitmap for sensors up to 512 x 512
-constexpr int kLinkHash = 4096;       // pixel hash slots (>= 2 x (tile + halo))
+
+
 constexpr int kFeatTile = 512;        // sorted hits per feature work-group
 constexpr int kFeatThreads = 256;
 constexpr int kFeatHash = 1024;       // root hash slots (>= 2 x tile)
@@ -141,4 +141,15 @@ struct TimedLaunch {
     int slot_;
 };
 
+}  // namespace hc
+
+namespace hc {
+// Occupancy bitmap of the link kernel: one bit per sensor pixel, plus one
+// prefix count per word (dynamic LDS of 8 bytes per word).  Sensors with more
+// than kLinkMaxPixels pixels send every tile to the fallback.
+constexpr uint64_t kLinkMaxPixels = 448ull * 512ull;
+inline int link_bitmap_words(uint32_t width, uint32_t height)
+{
+    return (int)(((uint64_t)width * height + 31) / 32);
+}
 }  // namespace hc

@@ -30,9 +30,8 @@
 
 namespace hc {
 
-__device__ inline uint32_t pix_hash(uint32_t key) { return (key * 0x9E3779B1u) >> 20; }  // 12 bits
 
-// ---- LDS union-find over local slots, roots = smallest input index
+// ---- LDS union-find over local slots; a tree's root is its smallest slot
 __device__ inline int32_t ld_lds(const int32_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -53,13 +52,13 @@ __device__ inline int32_t lfind(int32_t* par, int32_t x)
     }
 }
 
-__device__ inline void lunion(int32_t* par, const int32_t* idx, int32_t a, int32_t b)
+__device__ inline void lunion(int32_t* par, int32_t a, int32_t b)
 {
     while (true) {
         a = lfind(par, a);
         b = lfind(par, b);
         if (a == b) return;
-        if (idx[a] > idx[b]) {
+        if (a > b) {
             const int32_t t = a;
             a = b;
             b = t;
@@ -73,8 +72,9 @@ __device__ inline void lunion(int32_t* par, const int32_t* idx, int32_t a, int32
 
 // First halo position of every link tile: the earliest sorted position p
 // with toa(p) >= toa(p0) - dt (a suffix of the positions before p0, so a
-// binary search), or -1 when the halo exceeds kLinkHaloCap or the tile's
-// ToA span does not fit 32 bits (such tiles go to the fallback).
+// binary search), or -1 when the halo exceeds kLinkHaloCap, the tile's ToA
+// span does not fit 32 bits or the sensor is too large for the LDS pixel
+// bitmap (such tiles go to the fallback).
 __global__ void k_link_halo(Work w)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -90,6 +90,7 @@ __global__ void k_link_halo(Work w)
     }
     bool overflow = (a == lim && lim > 0 && w.s_toa[lim - 1] >= lo);
     overflow |= (w.s_toa[p1 - 1] - w.s_toa[a]) > 0xFFFFFFFFull;
+    overflow |= (uint64_t)w.width * w.height > kLinkMaxPixels;  // no room for the pixel bitmap
     w.link_h0[k] = overflow ? -1 : (int32_t)a;
 }
 
@@ -100,22 +101,43 @@ hipError_t launch_link_halo(const Work& w, hipStream_t s)
     return hipGetLastError();
 }
 
-constexpr uint64_t kEmptySlot = 0ull;
-
 // One work-group per tile of kLinkTile sorted hits (+ halo), all in LDS.
-// Dynamic LDS holds an occupancy bitmap of the sensor (bm_words words; 0 =
-// no bitmap, every neighbour pixel is looked up in the hash).
+//
+// Local slots 0..L-1 are the sorted positions h0..p1-1, so a smaller slot is
+// an earlier hit.  The paper's per-pixel "last hit" matrix is replaced by a
+// tile-sized index of the occupied pixels:
+//   * an occupancy bitmap of the sensor plus the popcount prefix of its words
+//     gives every occupied pixel a dense rank (pixel order) without hashing;
+//   * a CSR lists, per occupied pixel, the slots of its hits in ascending
+//     order, so the three pixels of a neighbour row are three consecutive
+//     segments and the latest earlier hit at a pixel is found by stepping back
+//     from its segment's end (usually one step).
+// Each tile hit joins, for each of its (up to) 9 neighbour pixels, the latest
+// earlier hit there if it lies within dt -- the hit the paper's matrix would
+// hold.  Joins are applied in bulk rounds (hook the larger root under the
+// smaller with an atomic minimum, then jump pointers until every tree is a
+// star) in an LDS forest whose roots are the earliest slots, as in the paper's
+// time-ordered forest.  The smallest input index of every local tree is then
+// published as the label candidate of its tile hits; halo hits joined by the
+// tile become cross-tile edges.
+// Dynamic LDS: bitmap (bm_words words) followed by the word prefix counts.
 __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
 {
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
     constexpr int PER = kLinkTile / kLinkThreads;
+    constexpr int LPER = LCAP / kLinkThreads;
+    constexpr uint32_t kUnsorted = 0x80000000u;
     __shared__ uint32_t l_toa[LCAP];
     __shared__ uint32_t l_xy[LCAP];
-    __shared__ int32_t l_idx[LCAP];
     __shared__ int32_t l_par[LCAP];
-    __shared__ int16_t l_next[LCAP];
-    __shared__ unsigned long long h_slot[kLinkHash];  // (pixel key << 32) | list head
-    extern __shared__ uint32_t bm[];
+    __shared__ uint16_t l_rank[LCAP];     // hit's rank among its pixel's hits, then root
+    __shared__ uint16_t l_pixr[LCAP];     // hit's pixel rank
+    __shared__ uint16_t csr[LCAP];        // slots grouped by pixel rank
+    __shared__ uint32_t pstart[LCAP + 1]; // count, then first CSR position per pixel rank [| kUnsorted]
+    __shared__ uint32_t wsum[kLinkThreads / kWave];
+    extern __shared__ uint32_t dyn[];
+    uint32_t* bm = dyn;
+    uint32_t* wpre = dyn + bm_words;
 
     if (w.status->err_range) return;
     const int tile = xcd_tile(w.n_link_tiles);
@@ -140,101 +162,212 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
     const int hl = (int)(p0 - h0);
     const uint64_t tbase = w.s_toa[h0];
     const uint32_t W = w.width;
-    for (int i = t; i < L; i += kLinkThreads) {
-        const int64_t p = h0 + i;
-        l_toa[i] = (uint32_t)(w.s_toa[p] - tbase);
-        l_xy[i] = w.s_xy[p];
-        int32_t id = w.s_idx[p];
-        if (id < 0 || id >= w.n) {
-            atomicOr(&w.status->err_internal, 1);
-            id = 0;
+    int32_t ids[LPER];
+#pragma unroll
+    for (int q = 0; q < LPER; q++) {
+        const int i = t + q * kLinkThreads;
+        ids[q] = -1;
+        if (i < L) {
+            const int64_t p = h0 + i;
+            l_toa[i] = (uint32_t)(w.s_toa[p] - tbase);
+            l_xy[i] = w.s_xy[p];
+            l_par[i] = i;
+            int32_t id = w.s_idx[p];
+            if (id < 0 || id >= w.n) {
+                atomicOr(&w.status->err_internal, 1);
+                id = 0;
+            }
+            ids[q] = id;
         }
-        l_idx[i] = id;
-        l_par[i] = i;
     }
-    for (int i = t; i < kLinkHash; i += kLinkThreads) h_slot[i] = kEmptySlot;
     for (int i = t; i < bm_words; i += kLinkThreads) bm[i] = 0u;
+    for (int i = t; i <= LCAP; i += kLinkThreads) pstart[i] = 0u;
     __syncthreads();
 
-    // ---- pixel hash (slot per occupied pixel, list of its hits) and bitmap
+    // ---- occupancy bitmap
     for (int i = t; i < L; i += kLinkThreads) {
         const uint32_t xy = l_xy[i];
-        const uint32_t key = xy + 1u;
-        uint32_t slot = pix_hash(key);
-        while (true) {
-            const unsigned long long mine = ((unsigned long long)key << 32) | 0xFFFFFFFFull;
-            const unsigned long long old = atomicCAS(&h_slot[slot], kEmptySlot, mine);
-            if (old == kEmptySlot || (uint32_t)(old >> 32) == key) break;
-            slot = (slot + 1u) & (kLinkHash - 1);
+        const uint32_t pix = (xy >> 16) * W + (xy & 0xFFFFu);
+        atomicOr(&bm[pix >> 5], 1u << (pix & 31u));
+    }
+    __syncthreads();
+    // ---- popcount prefix of the bitmap words (rank of the first pixel of a word)
+    {
+        const int per = (bm_words + kLinkThreads - 1) / kLinkThreads;
+        const int w0 = t * per;
+        uint32_t c = 0;
+        for (int k = 0; k < per; k++)
+            if (w0 + k < bm_words) c += __popc(bm[w0 + k]);
+        uint32_t run = block_exclusive_scan<kLinkThreads>(c, wsum, nullptr);
+        for (int k = 0; k < per; k++)
+            if (w0 + k < bm_words) {
+                wpre[w0 + k] = run;
+                run += __popc(bm[w0 + k]);
+            }
+    }
+    __syncthreads();
+    // ---- per-pixel counts (the atomic returns each hit's rank in its pixel)
+    for (int i = t; i < L; i += kLinkThreads) {
+        const uint32_t xy = l_xy[i];
+        const uint32_t pix = (xy >> 16) * W + (xy & 0xFFFFu);
+        const uint32_t wd = pix >> 5;
+        const uint32_t r = wpre[wd] + __popc(bm[wd] & ((1u << (pix & 31u)) - 1u));
+        l_pixr[i] = (uint16_t)r;
+        l_rank[i] = (uint16_t)atomicAdd(&pstart[r], 1u);
+    }
+    __syncthreads();
+    // ---- exclusive scan of the counts -> first CSR position per pixel rank
+    {
+        uint32_t c[LPER];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < LPER; k++) {
+            c[k] = pstart[t * LPER + k];
+            sum += c[k];
         }
-        // push onto the slot's list: exchange the low half (the head)
-        l_next[i] = (int16_t)atomicExch(reinterpret_cast<int32_t*>(&h_slot[slot]), i);
-        if (bm_words) {
-            const uint32_t pix = (xy >> 16) * W + (xy & 0xFFFFu);
-            atomicOr(&bm[pix >> 5], 1u << (pix & 31u));
+        uint32_t run = block_exclusive_scan<kLinkThreads>(sum, wsum, nullptr);
+#pragma unroll
+        for (int k = 0; k < LPER; k++) {
+            pstart[t * LPER + k] = run;
+            run += c[k];
+        }
+        if (t == kLinkThreads - 1) pstart[LCAP] = run;
+    }
+    __syncthreads();
+    for (int i = t; i < L; i += kLinkThreads) csr[pstart[l_pixr[i]] + l_rank[i]] = (uint16_t)i;
+    __syncthreads();
+    // ---- sort every pixel's segment by slot (segments are short; a pile-up
+    // of more than 64 hits on one pixel is left unsorted and scanned instead)
+    for (int r = t; r < LCAP; r += kLinkThreads) {
+        // a neighbouring thread may already have flagged pstart[r + 1]
+        const int s0 = (int)(pstart[r] & ~kUnsorted), s1 = (int)(pstart[r + 1] & ~kUnsorted);
+        const int cnt = s1 - s0;
+        if (cnt < 2) continue;
+        if (cnt > 64) {
+            pstart[r] = (uint32_t)s0 | kUnsorted;
+            continue;
+        }
+        for (int a = s0 + 1; a < s1; a++) {
+            const uint16_t v = csr[a];
+            int b = a - 1;
+            while (b >= s0 && csr[b] > v) {
+                csr[b + 1] = csr[b];
+                b--;
+            }
+            csr[b + 1] = v;
         }
     }
     __syncthreads();
 
-    // ---- neighbour search of the tile hits
+    // ---- neighbour search: latest earlier hit per neighbour pixel
     const uint64_t dt = w.dt;
     const int H = (int)w.height;
-#pragma unroll 1
+    int cand[PER][9];
+#pragma unroll
     for (int q = 0; q < PER; q++) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) cand[q][k] = -1;
         const int i = hl + t + q * kLinkThreads;
-        if (i >= L) break;
+        if (i >= L) continue;
         const uint32_t xy = l_xy[i];
         const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
         const uint32_t ti = l_toa[i];
         const int xlo = x > 0 ? x - 1 : 0;
         const int xhi = x + 1 < (int)W ? x + 1 : (int)W - 1;
-        for (int qy = y - 1; qy <= y + 1; qy++) {
+        const uint32_t rowmask = (1u << (xhi - xlo + 1)) - 1u;
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            const int qy = y - 1 + r;
             if (qy < 0 || qy >= H) continue;
-            uint32_t occ = (1u << (xhi - xlo + 1)) - 1u;  // bit k: pixel xlo + k
-            if (bm_words) {
-                const uint32_t pa = (uint32_t)qy * W + (uint32_t)xlo;
-                const uint32_t wa = pa >> 5, sh = pa & 31u;
-                uint64_t bits = bm[wa];
-                if (sh > 29u && wa + 1 < (uint32_t)bm_words) bits |= (uint64_t)bm[wa + 1] << 32;
-                occ &= (uint32_t)(bits >> sh);
-            }
-            while (occ) {
-                const int k = __builtin_ctz(occ);
-                occ &= occ - 1u;
-                const uint32_t key = ((uint32_t)(xlo + k) | ((uint32_t)qy << 16)) + 1u;
-                uint32_t slot = pix_hash(key);
+            const uint32_t pa = (uint32_t)qy * W + (uint32_t)xlo;
+            const uint32_t wa = pa >> 5, sh = pa & 31u;
+            uint64_t bits = bm[wa];
+            if (sh > 29u && wa + 1 < (uint32_t)bm_words) bits |= (uint64_t)bm[wa + 1] << 32;
+            const uint32_t occ = (uint32_t)(bits >> sh) & rowmask;
+            if (!occ) continue;
+            // rank of the first occupied pixel of this row segment
+            int rk = (int)(wpre[wa] + __popc(bm[wa] & ((1u << sh) - 1u)));
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                if (!(occ & (1u << k))) continue;
+                const uint32_t st = pstart[rk];
+                const int s0 = (int)(st & ~kUnsorted), s1 = (int)(pstart[rk + 1] & ~kUnsorted);
+                rk++;
                 int a = -1;
-                while (true) {
-                    const unsigned long long v = h_slot[slot];
-                    if ((uint32_t)(v >> 32) == key) {
-                        a = (int32_t)(uint32_t)v;
-                        break;
+                if (!(st & kUnsorted)) {
+                    int j = s1 - 1;
+                    while (j >= s0 && (int)csr[j] >= i) j--;
+                    if (j >= s0) a = csr[j];
+                } else {
+                    for (int j = s0; j < s1; j++) {
+                        const int v = csr[j];
+                        if (v < i && v > a) a = v;
                     }
-                    if (v == kEmptySlot) break;
-                    slot = (slot + 1u) & (kLinkHash - 1);
                 }
-                while (a >= 0) {
-                    if (a < i && (uint64_t)(ti - l_toa[a]) <= dt) {
-                        lunion(l_par, l_idx, a, i);
-                        break;
-                    }
-                    a = l_next[a];
+                if (a >= 0 && (uint64_t)(ti - l_toa[a]) <= dt) {
+#pragma unroll
+                    for (int kk = 0; kk < 9; kk++)
+                        if (kk == 3 * r + k) cand[q][kk] = a;
                 }
             }
         }
     }
-    __syncthreads();
-    for (int i = t; i < L; i += kLinkThreads) st_lds(l_par + i, lfind(l_par, i));
-    __syncthreads();
 
-    // ---- publish: tile hits get their local root, joined halo hits become edges
-    for (int i = t; i < L; i += kLinkThreads) {
-        const int32_t r = l_par[i];
+    // ---- union-find in bulk rounds: hook every edge's larger root under the
+    // smaller (atomic minimum), then jump pointers until every tree is a
+    // star; repeat until no edge joins two different roots
+    while (true) {
+        bool changed = false;
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int i = hl + t + q * kLinkThreads;
+            if (i >= L) continue;
+            const int pi = l_par[i];
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                if (cand[q][k] < 0) continue;
+                const int pc = l_par[cand[q][k]];
+                if (pc != pi) {
+                    atomicMin(&l_par[pc > pi ? pc : pi], pc > pi ? pi : pc);
+                    changed = true;
+                }
+            }
+        }
+        __syncthreads();
+        for (int x = t; x < L; x += kLinkThreads) {
+            int p = l_par[x];
+            while (true) {
+                const int g = l_par[p];
+                if (g == p) break;
+                p = g;
+            }
+            l_par[x] = p;
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+
+    // ---- smallest input index per local tree, then publish
+    int32_t* minidx = reinterpret_cast<int32_t*>(pstart);  // reused: L <= LCAP
+    for (int i = t; i < L; i += kLinkThreads) minidx[i] = 0x7FFFFFFF;
+    __syncthreads();
+    int32_t root[LPER];
+#pragma unroll
+    for (int q = 0; q < LPER; q++) {
+        const int i = t + q * kLinkThreads;
+        root[q] = i < L ? l_par[i] : -1;
+        if (root[q] >= 0) atomicMin(&minidx[root[q]], ids[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < LPER; q++) {
+        const int i = t + q * kLinkThreads;
+        if (i >= L) continue;
+        const int32_t m = minidx[root[q]];
         if (i >= hl) {
-            w.gparent[l_idx[i]] = l_idx[r];
-        } else if (r != i) {
+            w.gparent[ids[q]] = m;
+        } else if (ids[q] != m) {
             const int e = atomicAdd(&w.status->n_edges, 1);
-            if (e < w.edge_cap) w.edges[e] = make_int2(l_idx[i], l_idx[r]);
+            if (e < w.edge_cap) w.edges[e] = make_int2(ids[q], m);
             else atomicOr(&w.status->err_internal, 1);
         }
     }
@@ -243,9 +376,8 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
 hipError_t launch_link(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("link", s);
-    const uint64_t pixels = (uint64_t)w.width * w.height;
-    const int bm_words = pixels <= (uint64_t)kLinkBitmapMaxWords * 32 ? (int)((pixels + 31) / 32) : 0;
-    hipLaunchKernelGGL(k_link, dim3(xcd_grid(w.n_link_tiles)), dim3(kLinkThreads), (size_t)bm_words * 4, s, w,
+    const int bm_words = link_bitmap_words(w.width, w.height);
+    hipLaunchKernelGGL(k_link, dim3(xcd_grid(w.n_link_tiles)), dim3(kLinkThreads), (size_t)bm_words * 8, s, w,
                        bm_words);
     return hipGetLastError();
 }
