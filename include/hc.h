@@ -107,6 +107,51 @@ size_t hc_workspace_size(const hc_opts* opts, int64_t n);
 int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels,
                hc_features* features, int32_t* n_clusters, const hc_opts* opts);
 
+/* ---- Stream form: one detector's hit stream, pushed chunk by chunk --------
+ *
+ * The stream is "t-ordered" (paper, Section 3.1): for any two hits i < j in
+ * push order, toa_i < toa_j + t, with t = max_disorder_ticks.  Clusters that
+ * straddle chunk borders (the paper's border and open clusters, Section 3.3;
+ * border grouping, step 5 of its high-level GPU algorithm) are stitched
+ * exactly: open hits stay on the device and are clustered again with the
+ * next chunk.  With M the largest ToA pushed so far, every later hit has
+ * toa > M - t; a cluster is closed -- its labels final, its features emitted
+ * (Algorithm "processHit", closeAndDispatchOldClusters) -- once
+ * toa_max + dt <= M - t.
+ *
+ * Labels are stream-global: the smallest global index (0-based position in
+ * the concatenation of all pushed chunks) of the hit's cluster.  They are
+ * written into each chunk's labels buffer as its clusters close, possibly
+ * during a later push or the flush; a chunk is complete when its tag is
+ * reported by hc_stream_poll.  At most 2^31 - 1 hits per stream.
+ * A stream is single-producer; all its work runs on opts->stream. */
+typedef struct hc_stream hc_stream;
+
+/* opts: sensor size, disorder_hint (positional, for the sort), stream; the
+ * workspace fields are ignored (the stream owns its device buffers). */
+int hc_stream_create(const hc_opts* opts, uint64_t dt, uint64_t max_disorder_ticks, hc_stream** out);
+
+/* Append n hits (device array).  labels: device int32[n] that the library
+ * fills as the chunk's clusters close; it must stay valid until `tag` is
+ * returned by hc_stream_poll.  Returns HC_ERR_DISORDER (chunk rejected,
+ * stream unchanged) if a hit has toa <= M - t, HC_ERR_RANGE (rejected) if a
+ * hit is off the sensor, HC_ERR_OVERFLOW past 2^31 - 1 hits.  Blocks until
+ * the chunk has been processed on the device. */
+int hc_stream_push(hc_stream* s, const hc_hit* hits, int32_t n, int32_t* labels, uint64_t tag);
+
+/* Drain completion events into HOST buffers: up to cap tags of chunks whose
+ * labels are all final (in completion order), and up to closed_cap features
+ * of closed clusters (labels stream-global; ascending label within one push).
+ * Entries beyond the caps stay queued for the next call. */
+int hc_stream_poll(hc_stream* s, uint64_t* done_tags, int32_t cap, int32_t* n_done, hc_features* closed,
+                   int32_t closed_cap, int32_t* n_closed);
+
+/* Close every open cluster (end of stream); afterwards all pushed chunks are
+ * complete. */
+int hc_stream_flush(hc_stream* s);
+
+void hc_stream_destroy(hc_stream* s);
+
 /* Human-readable description of the last error on this thread. */
 const char* hc_last_error(void);
 

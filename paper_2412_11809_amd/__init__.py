@@ -170,3 +170,69 @@ def hc_timing_read(cap=64):
     if k < 0:
         _check(k)
     return {names[i].decode(): (int(cnt[i]), float(ms[i])) for i in range(min(k, cap))}
+
+
+# ---- stream form
+def _bind_stream(lib):
+    if getattr(lib, "_stream_bound", False):
+        return lib
+    lib.hc_stream_create.restype = ctypes.c_int
+    lib.hc_stream_create.argtypes = [ctypes.POINTER(_Opts), ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+    lib.hc_stream_push.restype = ctypes.c_int
+    lib.hc_stream_push.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_uint64]
+    lib.hc_stream_poll.restype = ctypes.c_int
+    lib.hc_stream_poll.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.hc_stream_flush.restype = ctypes.c_int
+    lib.hc_stream_flush.argtypes = [ctypes.c_void_p]
+    lib.hc_stream_destroy.restype = None
+    lib.hc_stream_destroy.argtypes = [ctypes.c_void_p]
+    lib._stream_bound = True
+    return lib
+
+
+class HcStream:
+    """One detector stream (hc_stream_*): push device chunks, poll completions."""
+
+    def __init__(self, dt, max_disorder_ticks, width=256, height=256, disorder_hint=0, stream=None):
+        import torch
+        self._lib = _bind_stream(load_library())
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._torch_stream = stream
+        o = _opts(width, height, disorder_hint, None, stream)
+        h = ctypes.c_void_p()
+        _check(self._lib.hc_stream_create(ctypes.byref(o), int(dt), int(max_disorder_ticks), ctypes.byref(h)))
+        self._h = h
+
+    def hc_stream_push(self, hits, n, labels, tag):
+        rc = self._lib.hc_stream_push(self._h, _ptr(hits), int(n), _ptr(labels), int(tag))
+        _check(rc)
+
+    def push(self, hits, labels, tag):
+        self.hc_stream_push(hits, hits.numel() // 16, labels, tag)
+
+    def poll(self, cap=1 << 16, closed_cap=1 << 20):
+        tags = np.empty(max(cap, 1), dtype=np.uint64)
+        feats = np.empty(max(closed_cap, 1), dtype=FEATURE_DTYPE)
+        nd, nc = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.hc_stream_poll(self._h, tags.ctypes.data, cap, ctypes.byref(nd),
+                                        feats.ctypes.data, closed_cap, ctypes.byref(nc)))
+        return tags[: nd.value].tolist(), feats[: nc.value].copy()
+
+    def flush(self):
+        _check(self._lib.hc_stream_flush(self._h))
+
+    def close(self):
+        if self._h:
+            self._lib.hc_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

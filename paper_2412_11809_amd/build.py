@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhc.so")
-SOURCES = ["hc_api.cpp", "hc_sort.hip", "hc_link.hip", "hc_feat.hip"]
+SOURCES = ["hc_api.cpp", "hc_sort.hip", "hc_link.hip", "hc_feat.hip", "hc_stream.hip"]
 ARCH = "gfx950"
 
 

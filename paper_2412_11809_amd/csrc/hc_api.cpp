@@ -160,6 +160,35 @@ TimedLaunch::~TimedLaunch()
     if (slot_ >= 0) (void)hipEventRecord(g_trecs[slot_].stop, s_);
 }
 
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+int set_device_error(hipError_t e, const char* what) { return device_fail(e, what); }
+
+int enqueue_cluster(const hc_hit* hits, const Work& w, int32_t* labels, hc_features* features,
+                    int32_t* n_clusters, hipStream_t s)
+{
+    hipError_t e;
+#define HC_LAUNCH(call, what)                                        \
+    do {                                                             \
+        if ((e = (call)) != hipSuccess) return device_fail(e, what); \
+    } while (0)
+    HC_LAUNCH(launch_init(w, s), "init");
+    HC_LAUNCH(launch_tile_sort(hits, w, s), "tile_sort");
+    if (!w.force_fallback) HC_LAUNCH(launch_tile_merge(w, s), "tile_merge");
+    HC_LAUNCH(launch_sort_fallback(hits, w, s), "sort_fallback");
+    HC_LAUNCH(launch_link_halo(w, s), "link_halo");
+    HC_LAUNCH(launch_link(w, s), "link");
+    HC_LAUNCH(launch_link_fallback(w, s), "link_fallback");
+    HC_LAUNCH(launch_union_edges(w, s), "union_edges");
+    HC_LAUNCH(launch_flatten(w, labels, s), "flatten");
+    if (features) {
+        HC_LAUNCH(launch_features(w, labels, s), "features");
+        HC_LAUNCH(launch_carries(w, s), "carries");
+    }
+    HC_LAUNCH(launch_compact(w, labels, features, n_clusters, s), "compact");
+#undef HC_LAUNCH
+    return HC_OK;
+}
+
 }  // namespace hc
 
 using namespace hc;
@@ -209,26 +238,7 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_f
     plan_workspace(n, W, H, D, &w, (char*)ws);
     w.dt = dt;
 
-#define HC_LAUNCH(call, what)                                   \
-    do {                                                         \
-        if ((e = (call)) != hipSuccess) return device_fail(e, what); \
-    } while (0)
-    HC_LAUNCH(launch_init(w, s), "init");
-    HC_LAUNCH(launch_tile_sort(hits, w, s), "tile_sort");
-    if (!w.force_fallback) HC_LAUNCH(launch_tile_merge(w, s), "tile_merge");
-    HC_LAUNCH(launch_sort_fallback(hits, w, s), "sort_fallback");
-    HC_LAUNCH(launch_link_halo(w, s), "link_halo");
-    HC_LAUNCH(launch_link(w, s), "link");
-    HC_LAUNCH(launch_link_fallback(w, s), "link_fallback");
-    HC_LAUNCH(launch_union_edges(w, s), "union_edges");
-    HC_LAUNCH(launch_flatten(w, labels, s), "flatten");
-    if (features) {
-        HC_LAUNCH(launch_features(w, labels, s), "features");
-        HC_LAUNCH(launch_carries(w, s), "carries");
-    }
-    HC_LAUNCH(launch_compact(w, labels, features, n_clusters, s), "compact");
-#undef HC_LAUNCH
-    return HC_OK;
+    return enqueue_cluster(hits, w, labels, features, n_clusters, s);
 }
 
 int hc_timing_enable(int on)

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "hc.h"
 
 namespace hc {
@@ -24,7 +26,7 @@ constexpr int kScanThreads = 256;
 constexpr int kFbBlock = 2048;        // elements per fallback radix block
 constexpr int kFbThreads = 512;
 constexpr int kFbMaxPasses = 8;       // 8-bit digits of a 64-bit key
-constexpr int kMaxNeighbourTiles = 8; // sort merge looks at most this far
+constexpr int kMaxNeighbourTiles = 16; // sort merge looks at most this far
 
 // Partial or final integer features of one cluster (64 bytes).
 struct SlotRec {
@@ -131,6 +133,14 @@ hipError_t launch_carries(const Work& w, hipStream_t s);
 hipError_t launch_compact(const Work& w, const int32_t* labels, hc_features* features,
                           int32_t* n_clusters, hipStream_t s);
 hipError_t launch_write_count(int32_t* n_clusters, int32_t value, hipStream_t s);
+
+// The whole plain clustering sequence on one workspace (hc_api.cpp).
+int enqueue_cluster(const hc_hit* hits, const Work& w, int32_t* labels, hc_features* features,
+                    int32_t* n_clusters, hipStream_t s);
+// Record an error for hc_last_error and return its code.
+int set_error(int code, const std::string& msg);
+int set_device_error(hipError_t e, const char* what);
+int persistent_grid();
 
 // Kernel timing hooks (hc_api.cpp): bracket a launch with events when enabled.
 struct TimedLaunch {

@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kFbThreads) void k_link_fallback(Work w)
     radix_engine(job, &w.status->rs[1], kb, vb, w.fb_hist, w.n_fb_blocks, &w.status->err_internal);
 }
 
-int persistent_grid();
+
 
 hipError_t launch_link_fallback(const Work& w, hipStream_t s)
 {

@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kFbThreads) void k_sort_fallback(const hc_hit* __re
     radix_engine(job, &w.status->rs[0], kb, vb, w.fb_hist, w.n_fb_blocks, &w.status->err_internal);
 }
 
-int persistent_grid();
+
 
 hipError_t launch_sort_fallback(const hc_hit* hits, const Work& w, hipStream_t s)
 {
