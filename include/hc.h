@@ -92,7 +92,7 @@ enum {
     HC_ERR_DISORDER = -5,  /* stream: a hit violates the disorder contract */
     HC_ERR_OVERFLOW = -6,  /* more than 2^31 - 1 hits in one labelling */
     HC_ERR_BUDGET = -7,    /* server: request exceeds the memory budget */
-    HC_ERR_BUSY = -8       /* server: no slot free */
+    HC_ERR_BUSY = -8       /* server: shutting down, or still busy at a wait's timeout */
 };
 
 /* Bytes of device workspace hc_cluster needs for n hits with these options. */
@@ -151,6 +151,144 @@ int hc_stream_poll(hc_stream* s, uint64_t* done_tags, int32_t cap, int32_t* n_do
 int hc_stream_flush(hc_stream* s);
 
 void hc_stream_destroy(hc_stream* s);
+
+/* ---- Batch form: many independent chunks, one launch per stage ----------
+ *
+ * Chunks of uneven size (e.g. from several detectors) are clustered
+ * independently, each with its own dt, by ONE sequence of launches whose
+ * tiles cover all chunks (tiles never straddle two chunks), so small and large
+ * chunks load the GPU evenly.  The paper partitions hits into chunks, one per
+ * thread (step 4 of its high-level GPU algorithm); here chunks are independent
+ * inputs and every chunk is cut into tiles.
+ *
+ * hits:       device array, the chunks one after another
+ * offsets:    HOST int64[n_chunks + 1], chunk c = hits[offsets[c], offsets[c+1])
+ * dts:        HOST uint64[n_chunks], time window of every chunk (ticks)
+ * labels:     device int32[n]: chunk-local labels (smallest index within the
+ *             chunk of the hit's cluster)
+ * features:   device hc_features[n] or NULL: chunk c's clusters at rows
+ *             offsets[c] .. offsets[c] + n_clusters[c] - 1, ascending label
+ * n_clusters: device int32[n_chunks] (or an error status per chunk)
+ * plan:       tuning choices from hc_batch_autotune, or NULL for defaults.
+ * A chunk's ToA span must fit 2^(64 - bits(n_chunks - 1)) ticks, else its
+ * status is HC_ERR_RANGE. */
+typedef struct hc_batch_plan hc_batch_plan;
+typedef struct hc_batch_graph hc_batch_graph;
+
+int hc_cluster_batch(const hc_hit* hits, const int64_t* offsets, int32_t n_chunks, const uint64_t* dts,
+                     int32_t* labels, hc_features* features, int32_t* n_clusters, const hc_batch_plan* plan,
+                     const hc_opts* opts);
+
+/* Bytes of workspace hc_cluster_batch needs (opts->workspace may supply it). */
+size_t hc_batch_workspace_size(const int64_t* offsets, int32_t n_chunks, const hc_batch_plan* plan,
+                               const hc_opts* opts);
+
+/* Autotuner: runs every candidate plan (sort tile size / neighbour reach, XCD
+ * tile mapping) on this batch, rejects any candidate whose labels, features
+ * or counts differ from the default plan's in a single bit, and returns the
+ * fastest.  Uses labels/features/n_clusters as scratch (they end up holding
+ * the result).  The choice is cached per (device, size class) for the process. */
+int hc_batch_autotune(const hc_hit* hits, const int64_t* offsets, int32_t n_chunks, const uint64_t* dts,
+                      int32_t* labels, hc_features* features, int32_t* n_clusters, const hc_opts* opts,
+                      hc_batch_plan** out);
+/* Human-readable plan (e.g. "sort_tile=8192 reach=1 xcd_map=1 time_ms=0.42"). */
+int hc_batch_plan_describe(const hc_batch_plan* plan, char* buf, size_t cap);
+void hc_batch_plan_destroy(hc_batch_plan* plan);
+
+/* Capture the whole batch launch sequence (same arguments, fixed pointers) in
+ * a HIP graph; hc_batch_graph_launch replays it on `stream` (a hipStream_t).
+ * The graph owns its workspace; inputs may change between replays, sizes may
+ * not. */
+int hc_batch_graph_create(const hc_hit* hits, const int64_t* offsets, int32_t n_chunks, const uint64_t* dts,
+                          int32_t* labels, hc_features* features, int32_t* n_clusters,
+                          const hc_batch_plan* plan, const hc_opts* opts, hc_batch_graph** out);
+int hc_batch_graph_launch(hc_batch_graph* graph, void* stream);
+void hc_batch_graph_destroy(hc_batch_graph* graph);
+
+/* ---- Served form: continuous batching of many detector streams ---------
+ *
+ * A request loop for detector chunks that arrive over time (the paper's
+ * online setting: hits are read, clustered and handed on while the detector
+ * keeps taking data, Sections 3 and 4).  Every detector stream owns an
+ * hc_stream (device-resident open clusters, exact stitching across chunks)
+ * on its own HIP stream and host worker thread, so the device work of
+ * different streams overlaps.  A chunk is admitted when one of `max_slots`
+ * slots is free and the device memory it needs (its hits and labels, plus the
+ * growth of its stream's state) fits in `hbm_budget` beside everything the
+ * server already holds; otherwise it waits, in arrival order per stream.
+ *
+ * Host buffers: hits[n] is copied to the device after admission and labels[n]
+ * receives the chunk's final (stream-global) labels; both belong to the
+ * caller and must stay valid until the chunk's completion is polled.  Pinned
+ * memory (hipHostMalloc) makes the copies asynchronous DMA.
+ * Every call is thread-safe; submissions to one stream must come in stream
+ * order (one producer per stream). */
+typedef struct hc_server hc_server;
+
+typedef struct {
+    uint32_t width, height;      /* sensor of every stream (0 => 256) */
+    int32_t n_streams;           /* stream ids 0 .. n_streams - 1 (1..256) */
+    int32_t max_slots;           /* chunks in device processing at once (0 => n_streams) */
+    uint64_t dt;                 /* time window of the clusters, ticks */
+    uint64_t max_disorder_ticks; /* t of every stream (see hc_stream_create) */
+    uint64_t hbm_budget;         /* bytes of device memory the server may hold (0 => 16 GiB) */
+    uint32_t disorder_hint;      /* positional displacement hint (0 => 4096) */
+    uint32_t flags;              /* must be 0 */
+} hc_server_config;
+
+typedef struct {
+    uint64_t tag;            /* caller's tag of the chunk */
+    int32_t stream_id;
+    int32_t status;          /* HC_OK, or why the chunk was rejected (labels then untouched) */
+    int32_t n_hits;
+    int32_t n_closed;        /* clusters closed by this chunk's push (0 if rejected) */
+    uint64_t t_arrive_ns;    /* the caller's arrival stamp (hc_server_now_ns clock) */
+    uint64_t t_admit_ns;     /* admitted: slot and memory granted */
+    uint64_t t_processed_ns; /* device work done; closed clusters copied to the host */
+    uint64_t t_final_ns;     /* every label of the chunk final and in labels[] */
+} hc_completion;
+
+typedef struct {
+    int64_t submitted, completed, rejected, hits_completed;
+    int64_t queued;            /* submitted chunks not yet admitted */
+    int64_t pending_final;     /* processed chunks whose labels are not final yet */
+    uint64_t hbm_budget, hbm_in_use, hbm_peak;
+    int32_t max_slots, peak_slots_in_use;
+    /* latency quantiles over all completed chunks, ns */
+    uint64_t processing_p50, processing_p99, final_p50, final_p99;
+} hc_server_stats;
+
+/* Monotonic clock (ns) for t_arrive stamps. */
+uint64_t hc_server_now_ns(void);
+
+/* Start the worker threads and per-stream state on the current device. */
+int hc_server_create(const hc_server_config* cfg, hc_server** out);
+
+/* Queue a chunk of stream `stream_id` (never blocks on the device).
+ * Returns HC_ERR_ARG for a bad id or buffer, HC_ERR_BUDGET if a chunk of n
+ * hits can never fit the budget, HC_ERR_BUSY after hc_server_destroy began. */
+int hc_server_submit(hc_server* s, int32_t stream_id, const hc_hit* hits, int32_t n, int32_t* labels,
+                     uint64_t tag, uint64_t t_arrive_ns);
+
+/* End of stream `stream_id`: close all its open clusters once the chunks
+ * queued before this call are processed (their labels then become final). */
+int hc_server_flush(hc_server* s, int32_t stream_id);
+
+/* Completed chunks (final labels or rejection), oldest first. */
+int hc_server_poll(hc_server* s, hc_completion* out, int32_t cap, int32_t* n_out);
+
+/* Features of closed clusters of one stream (stream-global labels), in
+ * closing order. */
+int hc_server_closed(hc_server* s, int32_t stream_id, hc_features* out, int32_t cap, int32_t* n_out);
+
+/* Wait until no chunk is queued or in device processing (chunks waiting for
+ * finality may remain until more data or a flush); HC_ERR_BUSY on timeout. */
+int hc_server_wait_idle(hc_server* s, int32_t timeout_ms);
+
+int hc_server_stats_read(hc_server* s, hc_server_stats* out);
+
+/* Stops the workers after the work already queued, frees all device state. */
+void hc_server_destroy(hc_server* s);
 
 /* Human-readable description of the last error on this thread. */
 const char* hc_last_error(void);

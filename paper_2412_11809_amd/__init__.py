@@ -236,3 +236,304 @@ class HcStream:
             self.close()
         except Exception:
             pass
+
+
+# ---- batch form
+def _bind_batch(lib):
+    if getattr(lib, "_batch_bound", False):
+        return lib
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.hc_cluster_batch.restype = ctypes.c_int
+    lib.hc_cluster_batch.argtypes = [vp, i64p, ctypes.c_int32, u64p, vp, vp, vp, vp, ctypes.POINTER(_Opts)]
+    lib.hc_batch_workspace_size.restype = ctypes.c_size_t
+    lib.hc_batch_workspace_size.argtypes = [i64p, ctypes.c_int32, vp, ctypes.POINTER(_Opts)]
+    lib.hc_batch_autotune.restype = ctypes.c_int
+    lib.hc_batch_autotune.argtypes = [vp, i64p, ctypes.c_int32, u64p, vp, vp, vp, ctypes.POINTER(_Opts),
+                                      ctypes.POINTER(vp)]
+    lib.hc_batch_plan_describe.restype = ctypes.c_int
+    lib.hc_batch_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.hc_batch_plan_destroy.restype = None
+    lib.hc_batch_plan_destroy.argtypes = [vp]
+    lib.hc_batch_graph_create.restype = ctypes.c_int
+    lib.hc_batch_graph_create.argtypes = [vp, i64p, ctypes.c_int32, u64p, vp, vp, vp, vp, ctypes.POINTER(_Opts),
+                                          ctypes.POINTER(vp)]
+    lib.hc_batch_graph_launch.restype = ctypes.c_int
+    lib.hc_batch_graph_launch.argtypes = [vp, vp]
+    lib.hc_batch_graph_destroy.restype = None
+    lib.hc_batch_graph_destroy.argtypes = [vp]
+    lib._batch_bound = True
+    return lib
+
+
+def _batch_tables(offsets, dts):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_chunks = len(offsets) - 1
+    if np.isscalar(dts) or np.ndim(dts) == 0:
+        dts = np.full(max(n_chunks, 0), int(dts), dtype=np.uint64)
+    dts = np.ascontiguousarray(dts, dtype=np.uint64)
+    if n_chunks < 1 or len(dts) != n_chunks:
+        raise ValueError("offsets needs n_chunks + 1 entries and dts n_chunks")
+    return offsets, dts, n_chunks
+
+
+class BatchPlan:
+    """Handle of an hc_batch_plan (from hc_batch_autotune)."""
+
+    def __init__(self, lib, handle):
+        self._lib, self._h = lib, handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def describe(self):
+        buf = ctypes.create_string_buffer(256)
+        _check(self._lib.hc_batch_plan_describe(self._h, buf, 256))
+        return buf.value.decode()
+
+    def close(self):
+        if self._h:
+            self._lib.hc_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchGraph:
+    """Handle of an hc_batch_graph (captured batch launch sequence)."""
+
+    def __init__(self, lib, handle, keep):
+        self._lib, self._h, self._keep = lib, handle, keep
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(self._lib.hc_batch_graph_launch(self._h, s))
+
+    def close(self):
+        if self._h:
+            self._lib.hc_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _plan_ptr(plan):
+    return None if plan is None else plan.handle
+
+
+def hc_batch_workspace_size(offsets, plan=None, width=256, height=256, disorder_hint=0):
+    lib = _bind_batch(load_library())
+    offsets, _, n_chunks = _batch_tables(offsets, 0)
+    o = _opts(width, height, disorder_hint, None, None)
+    return int(lib.hc_batch_workspace_size(offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_chunks,
+                                           _plan_ptr(plan), ctypes.byref(o)))
+
+
+def hc_cluster_batch(hits, offsets, dts, labels, features, n_clusters, plan=None, width=256, height=256,
+                     disorder_hint=0, workspace=None, stream=None):
+    """Direct call of hc_cluster_batch on device tensors; offsets/dts are host arrays."""
+    import torch
+    lib = _bind_batch(load_library())
+    offsets, dts, n_chunks = _batch_tables(offsets, dts)
+    if stream is None:
+        stream = torch.cuda.current_stream(hits.device)
+    o = _opts(width, height, disorder_hint, workspace, stream)
+    _check(lib.hc_cluster_batch(_ptr(hits), offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_chunks,
+                                dts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _ptr(labels),
+                                _ptr(features), _ptr(n_clusters), _plan_ptr(plan), ctypes.byref(o)))
+
+
+def hc_batch_autotune(hits, offsets, dts, labels, features, n_clusters, width=256, height=256,
+                      disorder_hint=0, stream=None):
+    """Runs hc_batch_autotune; returns a BatchPlan (outputs hold the chosen plan's result)."""
+    import torch
+    lib = _bind_batch(load_library())
+    offsets, dts, n_chunks = _batch_tables(offsets, dts)
+    if stream is None:
+        stream = torch.cuda.current_stream(hits.device)
+    o = _opts(width, height, disorder_hint, None, stream)
+    h = ctypes.c_void_p()
+    _check(lib.hc_batch_autotune(_ptr(hits), offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_chunks,
+                                 dts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _ptr(labels),
+                                 _ptr(features), _ptr(n_clusters), ctypes.byref(o), ctypes.byref(h)))
+    return BatchPlan(lib, h.value)
+
+
+def hc_batch_graph_create(hits, offsets, dts, labels, features, n_clusters, plan=None, width=256,
+                          height=256, disorder_hint=0):
+    """Captures the batch launch sequence; returns a BatchGraph to replay."""
+    lib = _bind_batch(load_library())
+    offsets, dts, n_chunks = _batch_tables(offsets, dts)
+    o = _opts(width, height, disorder_hint, None, None)
+    h = ctypes.c_void_p()
+    _check(lib.hc_batch_graph_create(_ptr(hits), offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     n_chunks, dts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                     _ptr(labels), _ptr(features), _ptr(n_clusters), _plan_ptr(plan),
+                                     ctypes.byref(o), ctypes.byref(h)))
+    return BatchGraph(lib, h.value, (hits, labels, features, n_clusters))
+
+
+def cluster_batch(hits, offsets, dts, width=256, height=256, disorder_hint=0, features=True, plan=None,
+                  stream=None):
+    """Cluster a batch of chunks (device hits, host offsets); returns
+    (labels, features_bytes [n, 64] or None, n_clusters int32[n_chunks]) on the device."""
+    import torch
+    offsets, dts, n_chunks = _batch_tables(offsets, dts)
+    n = int(offsets[-1])
+    dev = hits.device
+    labels = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    feats = torch.empty((max(n, 1), 64), dtype=torch.uint8, device=dev) if features else None
+    k = torch.empty(n_chunks, dtype=torch.int32, device=dev)
+    hc_cluster_batch(hits, offsets, dts, labels, feats, k, plan, width, height, disorder_hint, None, stream)
+    return labels[:n], feats, k
+
+
+# ---- served form
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_uint32), ("height", ctypes.c_uint32), ("n_streams", ctypes.c_int32),
+                ("max_slots", ctypes.c_int32), ("dt", ctypes.c_uint64), ("max_disorder_ticks", ctypes.c_uint64),
+                ("hbm_budget", ctypes.c_uint64), ("disorder_hint", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+COMPLETION_DTYPE = np.dtype([
+    ("tag", "<u8"), ("stream_id", "<i4"), ("status", "<i4"), ("n_hits", "<i4"), ("n_closed", "<i4"),
+    ("t_arrive_ns", "<u8"), ("t_admit_ns", "<u8"), ("t_processed_ns", "<u8"), ("t_final_ns", "<u8"),
+])
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("hits_completed", ctypes.c_int64), ("queued", ctypes.c_int64), ("pending_final", ctypes.c_int64),
+                ("hbm_budget", ctypes.c_uint64), ("hbm_in_use", ctypes.c_uint64), ("hbm_peak", ctypes.c_uint64),
+                ("max_slots", ctypes.c_int32), ("peak_slots_in_use", ctypes.c_int32),
+                ("processing_p50", ctypes.c_uint64), ("processing_p99", ctypes.c_uint64),
+                ("final_p50", ctypes.c_uint64), ("final_p99", ctypes.c_uint64)]
+
+
+def _bind_server(lib):
+    if getattr(lib, "_server_bound", False):
+        return lib
+    vp = ctypes.c_void_p
+    lib.hc_server_now_ns.restype = ctypes.c_uint64
+    lib.hc_server_now_ns.argtypes = []
+    lib.hc_server_create.restype = ctypes.c_int
+    lib.hc_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
+    lib.hc_server_submit.restype = ctypes.c_int
+    lib.hc_server_submit.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, ctypes.c_uint64, ctypes.c_uint64]
+    lib.hc_server_flush.restype = ctypes.c_int
+    lib.hc_server_flush.argtypes = [vp, ctypes.c_int32]
+    lib.hc_server_poll.restype = ctypes.c_int
+    lib.hc_server_poll.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.hc_server_closed.restype = ctypes.c_int
+    lib.hc_server_closed.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.hc_server_wait_idle.restype = ctypes.c_int
+    lib.hc_server_wait_idle.argtypes = [vp, ctypes.c_int32]
+    lib.hc_server_stats_read.restype = ctypes.c_int
+    lib.hc_server_stats_read.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+    lib.hc_server_destroy.restype = None
+    lib.hc_server_destroy.argtypes = [vp]
+    lib._server_bound = True
+    return lib
+
+
+def hc_server_now_ns():
+    return int(_bind_server(load_library()).hc_server_now_ns())
+
+
+class HcServer:
+    """Served form (hc_server_*): submit host chunks of several detector
+    streams; the library admits them by slot and HBM budget and overlaps their
+    device work.  Host buffers must stay alive until their completion is polled
+    (this wrapper keeps a reference until then)."""
+
+    def __init__(self, n_streams, dt, max_disorder_ticks, width=256, height=256, max_slots=0,
+                 hbm_budget=0, disorder_hint=0):
+        self._lib = _bind_server(load_library())
+        c = _ServerConfig()
+        c.width, c.height, c.n_streams, c.max_slots = width, height, n_streams, max_slots
+        c.dt, c.max_disorder_ticks, c.hbm_budget = int(dt), int(max_disorder_ticks), int(hbm_budget)
+        c.disorder_hint, c.flags = disorder_hint, 0
+        h = ctypes.c_void_p()
+        _check(self._lib.hc_server_create(ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def hc_server_submit(self, stream_id, hits, n, labels, tag, t_arrive_ns):
+        _check(self._lib.hc_server_submit(self._h, int(stream_id), hits, int(n), labels, int(tag),
+                                          int(t_arrive_ns)))
+
+    def submit(self, stream_id, hits, labels, tag, t_arrive_ns=None):
+        """hits: host HIT_DTYPE array (pinned or pageable); labels: host int32 array."""
+        if t_arrive_ns is None:
+            t_arrive_ns = hc_server_now_ns()
+        hp, lp = _host_ptr(hits), _host_ptr(labels)
+        n = _host_len(hits, 16)
+        self._keep[(int(stream_id), int(tag))] = (hits, labels)
+        try:
+            self.hc_server_submit(stream_id, hp, n, lp, tag, t_arrive_ns)
+        except Exception:
+            self._keep.pop((int(stream_id), int(tag)), None)
+            raise
+
+    def flush(self, stream_id):
+        _check(self._lib.hc_server_flush(self._h, int(stream_id)))
+
+    def poll(self, cap=4096):
+        out = np.empty(max(cap, 1), dtype=COMPLETION_DTYPE)
+        k = ctypes.c_int32()
+        _check(self._lib.hc_server_poll(self._h, out.ctypes.data, cap, ctypes.byref(k)))
+        out = out[: k.value].copy()
+        for c in out:
+            self._keep.pop((int(c["stream_id"]), int(c["tag"])), None)
+        return out
+
+    def closed(self, stream_id, cap=1 << 20):
+        out = np.empty(max(cap, 1), dtype=FEATURE_DTYPE)
+        k = ctypes.c_int32()
+        _check(self._lib.hc_server_closed(self._h, int(stream_id), out.ctypes.data, cap, ctypes.byref(k)))
+        return out[: k.value].copy()
+
+    def wait_idle(self, timeout_ms=60000):
+        _check(self._lib.hc_server_wait_idle(self._h, int(timeout_ms)))
+
+    def stats(self):
+        s = _ServerStats()
+        _check(self._lib.hc_server_stats_read(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            self._lib.hc_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host_ptr(a):
+    if hasattr(a, "data_ptr"):
+        assert not a.is_cuda, "server buffers live in host memory"
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _host_len(a, item):
+    if hasattr(a, "data_ptr"):
+        return a.numel() * a.element_size() // item
+    return a.nbytes // item

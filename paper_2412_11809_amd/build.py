@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhc.so")
-SOURCES = ["hc_api.cpp", "hc_sort.hip", "hc_link.hip", "hc_feat.hip", "hc_stream.hip"]
+SOURCES = ["hc_api.cpp", "hc_sort.hip", "hc_link.hip", "hc_feat.hip", "hc_stream.hip", "hc_batch.hip", "hc_server.hip"]
 ARCH = "gfx950"
 
 

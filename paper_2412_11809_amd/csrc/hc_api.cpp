@@ -27,12 +27,17 @@ static int device_fail(hipError_t e, const char* what)
 // ------------------------------------------------------------ workspace
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disorder, Work* w, char* base)
+static int64_t tiles_of(int64_t count, int size) { return (count + size - 1) / size; }
+
+size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disorder, Work* w, char* base,
+                      const SegSpec* segs, int n_seg)
 {
     Work x{};
     x.n = (int32_t)n;
     x.width = width;
     x.height = height;
+    x.n_seg = n_seg < 1 ? 1 : n_seg;
+    x.xcd_map = 1;
     const int64_t D = disorder ? disorder : 4096;
     int T = 8192;
     if (2 * D <= 2048) T = 2048;
@@ -43,10 +48,18 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     if (m < 1) m = 1;
     x.force_fallback = m > kMaxNeighbourTiles ? 1 : 0;
     x.sort_m = (int32_t)(m > kMaxNeighbourTiles ? kMaxNeighbourTiles : m);
-    x.n_sort_tiles = (int32_t)((n + T - 1) / T);
-    x.n_link_tiles = (int32_t)((n + kLinkTile - 1) / kLinkTile);
-    x.n_feat_tiles = (int32_t)((n + kFeatTile - 1) / kFeatTile);
-    x.n_scan_blocks = (int32_t)((n + kScanBlock - 1) / kScanBlock);
+    const int sizes[4] = {T, kLinkTile, kFeatTile, kScanBlock};
+    int64_t nt[4] = {0, 0, 0, 0};
+    if (x.n_seg == 1) {
+        for (int k = 0; k < 4; k++) nt[k] = tiles_of(n, sizes[k]);
+    } else {
+        for (int sg = 0; sg < n_seg; sg++)
+            for (int k = 0; k < 4; k++) nt[k] += tiles_of(segs[sg].count, sizes[k]);
+    }
+    x.n_sort_tiles = (int32_t)nt[0];
+    x.n_link_tiles = (int32_t)nt[1];
+    x.n_feat_tiles = (int32_t)nt[2];
+    x.n_scan_blocks = (int32_t)nt[3];
     x.n_fb_blocks = (int32_t)((n + kFbBlock - 1) / kFbBlock);
     x.edge_cap = (int64_t)x.n_link_tiles * kLinkHaloCap;
     x.carry_cap = n;
@@ -59,6 +72,18 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     };
     const size_t N = (size_t)n;
     x.status = (Status*)take(sizeof(Status));
+    if (x.n_seg > 1) {
+        // one contiguous region: chunk table, then the chunk of every tile per kind
+        size_t tb = align_up(sizeof(SegInfo) * (size_t)x.n_seg, 16);
+        for (int k = 0; k < 4; k++) tb += align_up(4 * (size_t)nt[k], 16);
+        char* r = (char*)take(tb);
+        x.segs = (SegInfo*)r;
+        size_t at = align_up(sizeof(SegInfo) * (size_t)x.n_seg, 16);
+        for (int k = 0; k < 4; k++) {
+            x.tile_seg[k] = r ? (int32_t*)(r + at) : nullptr;
+            at += align_up(4 * (size_t)nt[k], 16);
+        }
+    }
     x.tiles = (TileInfo*)take(sizeof(TileInfo) * (size_t)x.n_sort_tiles);
     x.ts_rel = (uint32_t*)take(4 * N);
     x.ts_pay = (uint2*)take(8 * N);
@@ -74,7 +99,7 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.slots = (SlotRec*)take(sizeof(SlotRec) * N);
     x.carries = (SlotRec*)take(sizeof(SlotRec) * (size_t)x.carry_cap);
     x.blk_count = (uint32_t*)take(4 * (size_t)x.n_scan_blocks);
-    x.blk_off = (uint32_t*)take(4 * (size_t)x.n_scan_blocks);
+    x.blk_off = (uint32_t*)take(4 * (size_t)x.n_scan_blocks + 4);
     x.root_mask = (unsigned long long*)take(8 * (size_t)x.n_scan_blocks * (kScanBlock / 64));
     x.fb_key[0] = (uint64_t*)take(8 * N);
     x.fb_key[1] = (uint64_t*)take(8 * N);
@@ -85,6 +110,51 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     return off;
 }
 
+size_t segment_table_bytes(const Work& w)
+{
+    if (w.n_seg <= 1) return 0;
+    const int64_t nt[4] = {w.n_sort_tiles, w.n_link_tiles, w.n_feat_tiles, w.n_scan_blocks};
+    size_t tb = align_up(sizeof(SegInfo) * (size_t)w.n_seg, 16);
+    for (int k = 0; k < 4; k++) tb += align_up(4 * (size_t)nt[k], 16);
+    return tb;
+}
+
+int upload_segments(const Work& w, const SegSpec* segs, int n_seg, hipStream_t s, void* staging,
+                    size_t staging_bytes)
+{
+    if (w.n_seg <= 1) return HC_OK;
+    const size_t tb = segment_table_bytes(w);
+    if (!staging || staging_bytes < tb) return fail(HC_ERR_ARG, "segment staging buffer too small");
+    char* h = (char*)staging;
+    SegInfo* si = (SegInfo*)h;
+    const int sizes[4] = {w.sort_tile, kLinkTile, kFeatTile, kScanBlock};
+    int32_t* ts[4];
+    size_t at = align_up(sizeof(SegInfo) * (size_t)n_seg, 16);
+    const int64_t nt[4] = {w.n_sort_tiles, w.n_link_tiles, w.n_feat_tiles, w.n_scan_blocks};
+    for (int k = 0; k < 4; k++) {
+        ts[k] = (int32_t*)(h + at);
+        at += align_up(4 * (size_t)nt[k], 16);
+    }
+    int64_t t0[4] = {0, 0, 0, 0};
+    for (int sg = 0; sg < n_seg; sg++) {
+        SegInfo& r = si[sg];
+        r.start = segs[sg].start;
+        r.count = segs[sg].count;
+        r.pad_ = 0;
+        r.dt = segs[sg].dt;
+        r.out = segs[sg].out;
+        r.toa_min = ~0ull;
+        for (int k = 0; k < 4; k++) {
+            r.tile0[k] = (int32_t)t0[k];
+            const int64_t c = tiles_of(segs[sg].count, sizes[k]);
+            for (int64_t q = 0; q < c; q++) ts[k][t0[k] + q] = sg;
+            t0[k] += c;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(w.segs, h, tb, hipMemcpyHostToDevice, s);
+    return e == hipSuccess ? HC_OK : device_fail(e, "segment table upload");
+}
+
 // One cached workspace per device for callers that pass none.
 struct CachedWs {
     void* ptr = nullptr;
@@ -93,7 +163,7 @@ struct CachedWs {
 static std::mutex g_ws_mu;
 static std::vector<CachedWs> g_ws;
 
-static int cached_workspace(size_t need, void** out)
+int cached_workspace(size_t need, void** out)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -139,12 +209,21 @@ struct TimingRec {
     hipEvent_t start, stop;
 };
 static bool g_timing = false;
+static std::mutex g_tmu;  // launches from several host threads (server workers)
 static std::vector<TimingRec> g_trecs;
 static size_t g_tused = 0;
+
+bool timing_set(bool on)
+{
+    const bool prev = g_timing;
+    g_timing = on;
+    return prev;
+}
 
 TimedLaunch::TimedLaunch(const char* name, hipStream_t s) : name_(name), s_(s), slot_(-1)
 {
     if (!g_timing) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
     if (g_tused == g_trecs.size()) {
         TimingRec r{name, nullptr, nullptr};
         if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
@@ -157,7 +236,9 @@ TimedLaunch::TimedLaunch(const char* name, hipStream_t s) : name_(name), s_(s), 
 
 TimedLaunch::~TimedLaunch()
 {
-    if (slot_ >= 0) (void)hipEventRecord(g_trecs[slot_].stop, s_);
+    if (slot_ < 0) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    (void)hipEventRecord(g_trecs[slot_].stop, s_);
 }
 
 int set_error(int code, const std::string& msg) { return fail(code, msg); }
@@ -249,6 +330,7 @@ int hc_timing_enable(int on)
 
 int hc_timing_reset(void)
 {
+    std::lock_guard<std::mutex> lk(g_tmu);
     g_tused = 0;
     return HC_OK;
 }
@@ -258,6 +340,7 @@ int hc_timing_read(const char** names, int64_t* launches, double* total_ms, int3
     std::vector<const char*> nm;
     std::vector<int64_t> cnt;
     std::vector<double> ms;
+    std::lock_guard<std::mutex> lk(g_tmu);
     for (size_t i = 0; i < g_tused; i++) {
         TimingRec& r = g_trecs[i];
         hipError_t e = hipEventSynchronize(r.stop);

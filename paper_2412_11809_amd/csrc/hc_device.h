@@ -17,13 +17,51 @@ constexpr int kWave = 64;
 // L2 each).  Give every XCD a contiguous range of tiles, so a tile and its
 // neighbours -- which read each other's data -- share an L2.
 __host__ __device__ inline int xcd_grid(int ntiles) { return 8 * ((ntiles + 7) / 8); }
-__device__ inline int xcd_tile(int ntiles)
+__device__ inline int xcd_tile(int ntiles, int xcd_map = 1)
 {
-    const int per = (ntiles + 7) / 8;
     const int b = blockIdx.x;
+    if (!xcd_map) return b < ntiles ? b : -1;
+    const int per = (ntiles + 7) / 8;
     const int t = (b & 7) * per + (b >> 3);
     return t < ntiles ? t : -1;
 }
+
+// -------------------------------------------------------- tile ranges
+// Hits [start, start + count) of tile `tile` of a kind with `size` hits per
+// tile; seg_start / seg_end bound the chunk the tile belongs to.
+struct TileRange {
+    int seg;
+    int count;
+    int64_t start;
+    int64_t seg_start, seg_end;
+    int tile0, tile1;  // the chunk's tiles of this kind: [tile0, tile1)
+};
+
+__device__ inline TileRange tile_range(const Work& w, int kind, int tile, int size)
+{
+    TileRange r;
+    if (w.n_seg <= 1) {
+        r.seg = 0;
+        r.seg_start = 0;
+        r.seg_end = w.n;
+        r.tile0 = 0;
+        r.tile1 = (int)((w.n + size - 1) / size);
+        r.start = (int64_t)tile * size;
+    } else {
+        r.seg = w.tile_seg[kind][tile];
+        const SegInfo& s = w.segs[r.seg];
+        r.seg_start = s.start;
+        r.seg_end = s.start + s.count;
+        r.tile0 = s.tile0[kind];
+        r.tile1 = s.tile0[kind] + (s.count + size - 1) / size;
+        r.start = s.start + (int64_t)(tile - s.tile0[kind]) * size;
+    }
+    const int64_t left = r.seg_end - r.start;
+    r.count = (int)(left < size ? left : size);
+    return r;
+}
+
+__device__ inline uint64_t seg_dt(const Work& w, int seg) { return w.n_seg <= 1 ? w.dt : w.segs[seg].dt; }
 
 // ------------------------------------------------------- saturating math
 __device__ inline uint64_t sat_sub_u64(uint64_t a, uint64_t b) { return a > b ? a - b : 0; }

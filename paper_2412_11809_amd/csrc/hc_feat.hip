@@ -29,10 +29,12 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     constexpr int PER = kFeatTile / kFeatThreads;
 
     if (w.status->err_range) return;
-    const int tile = xcd_tile(w.n_feat_tiles);
+    const int tile = xcd_tile(w.n_feat_tiles, w.xcd_map);
     if (tile < 0) return;
     const int t = threadIdx.x;
-    const int64_t p0 = (int64_t)tile * kFeatTile;
+    const TileRange tr = tile_range(w, kFeatKind, tile, kFeatTile);
+    const int64_t p0 = tr.start;
+    const int64_t p_end = tr.start + tr.count;
     for (int i = t; i < kFeatHash; i += kFeatThreads) h_key[i] = 0u;
     __syncthreads();
 
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     for (int q = 0; q < PER; q++) {
         const int64_t p = p0 + t + q * kFeatThreads;
         slot[q] = -1;
-        if (p < w.n) {
+        if (p < p_end) {
             idx[q] = w.s_idx[p];
             toa[q] = w.s_toa[p];
             xy[q] = w.s_xy[p];
@@ -197,8 +199,9 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Work w, int32_t* n_cluster
 {
     __shared__ uint32_t wsum[1024 / kWave];
     const Status* st = w.status;
-    if (st->err_range || st->err_internal) {
-        if (threadIdx.x == 0) *n_clusters = st->err_range ? HC_ERR_RANGE : HC_ERR_DEVICE;
+    if (st->err_range || st->err_internal || st->err_span) {
+        const int32_t code = (st->err_range || st->err_span) ? HC_ERR_RANGE : HC_ERR_DEVICE;
+        for (int sg = threadIdx.x; sg < w.n_seg; sg += blockDim.x) n_clusters[sg] = code;
         return;
     }
     uint32_t carry = 0;
@@ -210,29 +213,49 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Work w, int32_t* n_cluster
         if (i < w.n_scan_blocks) w.blk_off[i] = carry + e;
         carry += total;
     }
-    if (threadIdx.x == 0) *n_clusters = (int32_t)carry;
+    if (threadIdx.x == 0) w.blk_off[w.n_scan_blocks] = carry;
+    if (w.n_seg <= 1) {
+        if (threadIdx.x == 0) *n_clusters = (int32_t)carry;
+        return;
+    }
+    __syncthreads();
+    for (int sg = threadIdx.x; sg < w.n_seg; sg += blockDim.x) {  // clusters per chunk
+        const SegInfo& si = w.segs[sg];
+        const int b0 = si.tile0[kScanKind], b1 = b0 + (si.count + kScanBlock - 1) / kScanBlock;
+        n_clusters[sg] = (int32_t)(w.blk_off[b1] - w.blk_off[b0]);
+    }
 }
 
 // features[rank] for every root of one block of kScanBlock input indices.
-__global__ __launch_bounds__(kScanThreads) void k_compact(Work w, hc_features* __restrict__ out)
+// For a batch of chunks it also turns the labels of its block chunk-local.
+__global__ __launch_bounds__(kScanThreads) void k_compact(Work w, int32_t* __restrict__ labels,
+                                                          hc_features* __restrict__ out)
 {
     constexpr int PER = kScanBlock / kScanThreads;  // 8 consecutive indices per thread
     __shared__ uint32_t wsum[kScanThreads / kWave];
-    if (w.status->err_range || w.status->err_internal) return;
+    const Status* st = w.status;
+    if (st->err_range || st->err_internal || st->err_span) return;
     const int b = blockIdx.x, t = threadIdx.x;
-    const int64_t base = (int64_t)b * kScanBlock;
+    const TileRange tr = tile_range(w, kScanKind, b, kScanBlock);
+    const int64_t base = tr.start;
+    if (w.n_seg > 1) {
+        const int64_t end = tr.start + tr.count;
+        for (int64_t i = base + t; i < end; i += kScanThreads) labels[i] -= (int32_t)tr.seg_start;
+    }
+    if (!out) return;
     // bits of indices [base + PER*t, base + PER*t + PER) within mask word (PER*t)/64
     const unsigned long long word = w.root_mask[(int64_t)b * (kScanBlock / 64) + (PER * t) / 64];
     const uint32_t bits = (uint32_t)((word >> ((PER * t) % 64)) & ((1u << PER) - 1u));
     const uint32_t off = block_exclusive_scan<kScanThreads>(__popc(bits), wsum, nullptr);
-    uint64_t k = (uint64_t)w.blk_off[b] + off;
+    const int64_t first = w.n_seg > 1 ? w.segs[tr.seg].out - (int64_t)w.blk_off[tr.tile0] : 0;
+    uint64_t k = (uint64_t)(first + (int64_t)w.blk_off[b] + off);
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         if (!(bits & (1u << q))) continue;
         const int64_t i = base + PER * t + q;
         const SlotRec r = w.slots[i];
         hc_features f;
-        f.label = (int32_t)i;
+        f.label = (int32_t)(i - tr.seg_start);
         f.size = r.size;
         f.sum_tot = r.sum_tot;
         f.toa_min = r.toa_min;
@@ -250,19 +273,18 @@ __global__ __launch_bounds__(kScanThreads) void k_compact(Work w, hc_features* _
     }
 }
 
-hipError_t launch_compact(const Work& w, const int32_t* labels, hc_features* features, int32_t* n_clusters,
+hipError_t launch_compact(const Work& w, int32_t* labels, hc_features* features, int32_t* n_clusters,
                           hipStream_t s)
 {
-    (void)labels;
     {
         TimedLaunch tl("scan_blocks", s);
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, w, n_clusters);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (!features) return hipSuccess;
+    if (!features && w.n_seg <= 1) return hipSuccess;
     TimedLaunch tl("compact", s);
-    hipLaunchKernelGGL(k_compact, dim3(w.n_scan_blocks), dim3(kScanThreads), 0, s, w, features);
+    hipLaunchKernelGGL(k_compact, dim3(w.n_scan_blocks), dim3(kScanThreads), 0, s, w, labels, features);
     return hipGetLastError();
 }
 

@@ -58,7 +58,8 @@ struct RadixState {
     int32_t scan_done[kFbMaxPasses];
     int32_t scatter_done[kFbMaxPasses];
     int32_t query_done;
-    int32_t pad2_[15];
+    int32_t shift;          // batch sort: chunk id sits above this many ToA bits
+    int32_t pad2_[14];
 };
 
 struct Status {
@@ -69,8 +70,30 @@ struct Status {
     int32_t n_carries;      // partial features queued for atomic merging
     int32_t scan_ticket;    // compaction block ticket
     int32_t err_internal;   // an index derived from device data was out of range
-    int32_t pad_[9];
+    int32_t err_span;       // batch sort fallback: a chunk's ToA span too large
+    int32_t pad_[8];
     RadixState rs[2];       // [0]: ToA sort fallback, [1]: pixel sort fallback
+};
+
+// One independently clustered chunk of the input (the batch form has many;
+// the plain path has one).  Tiles of every kind never straddle two chunks:
+// the chunk's tiles of kind k are tile0[k] .. tile0[k] + ceil(count / size_k) - 1.
+enum TileKind { kSortKind = 0, kLinkKind = 1, kFeatKind = 2, kScanKind = 3 };
+struct SegInfo {
+    int64_t start;     // first hit (position in the concatenated input)
+    int32_t count;
+    int32_t pad_;
+    uint64_t dt;       // time window of the chunk
+    int64_t out;       // first row of the chunk's features in the output table
+    uint64_t toa_min;  // smallest ToA of the chunk (sort fallback)
+    int32_t tile0[4];  // first tile of each kind
+};
+
+struct SegSpec {
+    int64_t start;
+    int32_t count;
+    uint64_t dt;
+    int64_t out;
 };
 
 // Device pointers into one workspace, for n hits.
@@ -78,6 +101,10 @@ struct Work {
     int32_t n;
     uint32_t width, height;
     uint64_t dt;
+    int32_t xcd_map;         // 1: contiguous tile ranges per XCD, 0: round-robin
+    int32_t n_seg;           // 1: one chunk, tile ranges computed arithmetically
+    SegInfo* segs;           // n_seg > 1: chunk table
+    int32_t* tile_seg[4];    // n_seg > 1: chunk of every tile, per kind
     // sort tiling
     int32_t sort_tile;   // T: hits per sort tile (power of two)
     int32_t sort_ipt;    // T / kSortThreads
@@ -114,9 +141,13 @@ struct Work {
     uint32_t* fb_hist;
 };
 
-// Workspace planning (host).
+// Workspace planning (host).  With segs/n_seg > 1 the input is a batch of
+// independent chunks; upload_segments then fills the chunk and tile tables.
 size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disorder, Work* w,
-                      char* base);
+                      char* base, const SegSpec* segs = nullptr, int n_seg = 1);
+int upload_segments(const Work& w, const SegSpec* segs, int n_seg, hipStream_t s, void* pinned_staging,
+                    size_t staging_bytes);
+size_t segment_table_bytes(const Work& w);
 
 // Kernel launchers; each returns the hipError_t of its launch.
 hipError_t launch_init(const Work& w, hipStream_t s);
@@ -130,7 +161,7 @@ hipError_t launch_union_edges(const Work& w, hipStream_t s);
 hipError_t launch_flatten(const Work& w, int32_t* labels, hipStream_t s);
 hipError_t launch_features(const Work& w, const int32_t* labels, hipStream_t s);
 hipError_t launch_carries(const Work& w, hipStream_t s);
-hipError_t launch_compact(const Work& w, const int32_t* labels, hc_features* features,
+hipError_t launch_compact(const Work& w, int32_t* labels, hc_features* features,
                           int32_t* n_clusters, hipStream_t s);
 hipError_t launch_write_count(int32_t* n_clusters, int32_t value, hipStream_t s);
 
@@ -139,6 +170,15 @@ int enqueue_cluster(const hc_hit* hits, const Work& w, int32_t* labels, hc_featu
                     int32_t* n_clusters, hipStream_t s);
 // Record an error for hc_last_error and return its code.
 int set_error(int code, const std::string& msg);
+// Cached per-device workspace for callers that pass none (grown on demand).
+int cached_workspace(size_t need, void** out);
+// Switch per-kernel event timing on or off; returns the previous state.
+bool timing_set(bool on);
+// Device memory of a stream (hc_stream_*): held now, and after a push of n
+// hits (with the bytes alive only while its buffers grow in *transient).
+size_t stream_device_bytes(const hc_stream* st);
+size_t stream_bytes_after_push(const hc_stream* st, int64_t n, size_t* transient);
+int64_t stream_open_hits(const hc_stream* st);
 int set_device_error(hipError_t e, const char* what);
 int persistent_grid();
 

@@ -79,16 +79,18 @@ __global__ void k_link_halo(Work w)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= w.n_link_tiles || w.status->err_range) return;
-    const int64_t p0 = (int64_t)k * kLinkTile;
-    const int64_t p1 = (p0 + kLinkTile) < w.n ? (p0 + kLinkTile) : w.n;
-    const uint64_t lo = sat_sub_u64(w.s_toa[p0], w.dt);
-    const int64_t lim = p0 - kLinkHaloCap > 0 ? p0 - kLinkHaloCap : 0;
+    const TileRange tr = tile_range(w, kLinkKind, k, kLinkTile);
+    const int64_t p0 = tr.start;
+    const int64_t p1 = tr.start + tr.count;
+    const uint64_t lo = sat_sub_u64(w.s_toa[p0], seg_dt(w, tr.seg));
+    // the halo never reaches into the previous chunk
+    const int64_t lim = p0 - kLinkHaloCap > tr.seg_start ? p0 - kLinkHaloCap : tr.seg_start;
     int64_t a = lim, b = p0;
     while (a < b) {
         const int64_t m = (a + b) >> 1;
         if (w.s_toa[m] < lo) a = m + 1; else b = m;
     }
-    bool overflow = (a == lim && lim > 0 && w.s_toa[lim - 1] >= lo);
+    bool overflow = (a == lim && lim > tr.seg_start && w.s_toa[lim - 1] >= lo);
     overflow |= (w.s_toa[p1 - 1] - w.s_toa[a]) > 0xFFFFFFFFull;
     overflow |= (uint64_t)w.width * w.height > kLinkMaxPixels;  // no room for the pixel bitmap
     w.link_h0[k] = overflow ? -1 : (int32_t)a;
@@ -140,11 +142,12 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
     uint32_t* wpre = dyn + bm_words;
 
     if (w.status->err_range) return;
-    const int tile = xcd_tile(w.n_link_tiles);
+    const int tile = xcd_tile(w.n_link_tiles, w.xcd_map);
     if (tile < 0) return;
     const int t = threadIdx.x;
-    const int64_t p0 = (int64_t)tile * kLinkTile;
-    const int64_t p1 = (p0 + kLinkTile) < w.n ? (p0 + kLinkTile) : w.n;
+    const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
+    const int64_t p0 = tr.start;
+    const int64_t p1 = tr.start + tr.count;
     const int64_t h0 = w.link_h0[tile];
     if (h0 < 0) {  // halo too large: every hit is its own root here, the fallback joins them
         for (int64_t p = p0 + t; p < p1; p += kLinkThreads) {
@@ -260,7 +263,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
     __syncthreads();
 
     // ---- neighbour search: latest earlier hit per neighbour pixel
-    const uint64_t dt = w.dt;
+    const uint64_t dt = seg_dt(w, tr.seg);
     const int H = (int)w.height;
     int cand[PER][9];
 #pragma unroll
@@ -412,8 +415,10 @@ struct PixSortJob {
     __device__ void extra(int q, const uint64_t* keys, const uint32_t* vals, RadixLds&)
     {
         const int tile = w.overflow_tiles[q];
-        const int64_t p0 = (int64_t)tile * kLinkTile;
-        const int64_t p1 = (p0 + kLinkTile) < w.n ? (p0 + kLinkTile) : w.n;
+        const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
+        const int64_t p0 = tr.start;
+        const int64_t p1 = tr.start + tr.count;
+        const uint64_t dt = seg_dt(w, tr.seg);
         const int64_t n = w.n;
         for (int64_t p = p0 + threadIdx.x; p < p1; p += kFbThreads) {
             const uint32_t xy = w.s_xy[p];
@@ -450,7 +455,7 @@ struct PixSortJob {
                         const int64_t c = vals[a - 1];
                         if (c < 0 || c >= p) {
                             atomicOr(&w.status->err_internal, 1);
-                        } else if (toa - w.s_toa[c] <= w.dt) {
+                        } else if (c >= tr.seg_start && toa - w.s_toa[c] <= dt) {
                             gunion(w.gparent, w.s_idx[c], w.s_idx[p], &w.status->err_internal);
                         }
                     }
@@ -508,13 +513,15 @@ __global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __res
     if (w.status->err_range) return;
     const int b = blockIdx.x;
     const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
-    const int64_t base = (int64_t)b * kScanBlock;
+    const TileRange tr = tile_range(w, kScanKind, b, kScanBlock);
+    const int64_t base = tr.start;
+    const int64_t end = tr.start + tr.count;
     uint32_t c = 0;
 #pragma unroll
     for (int q = 0; q < kScanBlock / kScanThreads; q++) {
         const int64_t i = base + q * kScanThreads + t;
         bool root = false;
-        if (i < w.n) {
+        if (i < end) {
             const int32_t r = gfind(w.gparent, (int32_t)i, &w.status->err_internal);
             labels[i] = r;
             root = (r == (int32_t)i);

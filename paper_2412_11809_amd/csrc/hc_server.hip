@@ -1,0 +1,528 @@
+// Served form: a request loop over many detector streams with continuous
+// batching.  Each stream has a host worker thread, a HIP stream and an
+// hc_stream (open clusters stay on the device and are stitched exactly across
+// chunks).  Chunks wait per stream in arrival order and are admitted when a
+// device slot is free and the memory they need fits the HBM budget; admitted
+// chunks of different streams run concurrently on the device.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hc_internal.h"
+
+using namespace hc;
+
+namespace {
+
+constexpr size_t kMinBlock = 64 << 10;
+
+size_t block_class(size_t bytes)
+{
+    size_t c = kMinBlock;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+
+struct Req {
+    bool flush;
+    uint64_t tag;
+    const hc_hit* hits;
+    int32_t n;
+    int32_t* labels;
+    uint64_t t_arrive;
+};
+
+struct Pending {
+    uint64_t tag;
+    int32_t n;
+    int32_t n_closed;
+    int32_t* labels_host;
+    void* labels_dev;
+    size_t labels_class;
+    uint64_t t_arrive, t_admit, t_processed;
+};
+
+struct StreamCtx {
+    int id = 0;
+    hc_stream* st = nullptr;
+    hipStream_t hs = nullptr;
+    std::thread th;
+    std::condition_variable cv;
+    std::deque<Req> q;                           // guarded by the server mutex
+    std::vector<hc_features> closed;             // guarded by the server mutex
+    std::unordered_map<uint64_t, Pending> pend;  // worker-only, keyed by internal sequence number
+    uint64_t seq = 0;
+    void* hits_dev = nullptr;
+    size_t hits_bytes = 0;
+    size_t state_bytes = 0;  // device bytes of the hc_stream counted in `used`
+};
+
+uint64_t now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+uint64_t quantile(std::vector<uint64_t> v, double q)
+{
+    if (v.empty()) return 0;
+    const size_t k = (size_t)(q * (double)(v.size() - 1) + 0.5);
+    std::nth_element(v.begin(), v.begin() + k, v.end());
+    return v[k];
+}
+
+}  // namespace
+
+struct hc_server {
+    hc_server_config cfg{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable budget_cv, idle_cv;
+    uint64_t used = 0, peak = 0, progress = 0;
+    int slots_used = 0, peak_slots = 0;
+    int64_t submitted = 0, completed = 0, rejected = 0, hits_completed = 0, queued = 0, pending_final = 0;
+    int working = 0;  // requests taken by a worker and not finished
+    bool stopping = false;
+    std::vector<StreamCtx*> streams;
+    std::deque<hc_completion> done;
+    std::vector<uint64_t> lat_proc, lat_final;
+    std::map<size_t, std::vector<void*>> free_blocks;  // label buffers ready for reuse (counted in used)
+
+    void account(int64_t delta)
+    {
+        used = (uint64_t)((int64_t)used + delta);
+        if (used > peak) peak = used;
+    }
+
+    // Release cached label blocks (lock held); returns bytes freed.
+    uint64_t trim_cache()
+    {
+        uint64_t freed = 0;
+        for (auto& kv : free_blocks)
+            for (void* p : kv.second) {
+                (void)hipFree(p);
+                freed += kv.first;
+            }
+        free_blocks.clear();
+        account(-(int64_t)freed);
+        return freed;
+    }
+
+    void complete(const hc_completion& c)
+    {
+        done.push_back(c);
+        completed++;
+        if (c.status == HC_OK) {
+            hits_completed += c.n_hits;
+            lat_final.push_back(c.t_final_ns - c.t_arrive_ns);
+        } else {
+            rejected++;
+        }
+        progress++;
+        budget_cv.notify_all();
+    }
+
+    void worker(StreamCtx* cx);
+    int run_chunk(StreamCtx* cx, const Req& r);
+    void drain(StreamCtx* cx, int32_t* n_closed_out);
+    void finalize(StreamCtx* cx, uint64_t seq);
+};
+
+// Copy a chunk's final labels to the caller and emit its completion.
+void hc_server::finalize(StreamCtx* cx, uint64_t seq)
+{
+    auto it = cx->pend.find(seq);
+    if (it == cx->pend.end()) return;
+    Pending p = it->second;
+    cx->pend.erase(it);
+    int status = HC_OK;
+    if (p.n > 0) {
+        hipError_t e = hipMemcpyAsync(p.labels_host, p.labels_dev, 4 * (size_t)p.n, hipMemcpyDeviceToHost, cx->hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(cx->hs);
+        if (e != hipSuccess) status = set_device_error(e, "server: label copy");
+    }
+    hc_completion c{};
+    c.tag = p.tag;
+    c.stream_id = cx->id;
+    c.status = status;
+    c.n_hits = p.n;
+    c.n_closed = p.n_closed;
+    c.t_arrive_ns = p.t_arrive;
+    c.t_admit_ns = p.t_admit;
+    c.t_processed_ns = p.t_processed;
+    c.t_final_ns = now_ns();
+    std::lock_guard<std::mutex> lk(mu);
+    if (p.labels_dev) free_blocks[p.labels_class].push_back(p.labels_dev);
+    pending_final--;
+    complete(c);
+}
+
+// Move closed clusters to the host and finalize the chunks that completed.
+void hc_server::drain(StreamCtx* cx, int32_t* n_closed_out)
+{
+    constexpr int kTags = 256, kFeats = 1 << 16;
+    std::vector<uint64_t> tags(kTags);
+    std::vector<hc_features> fb(kFeats);
+    int32_t total = 0;
+    for (;;) {
+        int32_t nd = 0, nc = 0;
+        if (hc_stream_poll(cx->st, tags.data(), kTags, &nd, fb.data(), kFeats, &nc) != HC_OK) break;
+        if (nc > 0) {
+            std::lock_guard<std::mutex> lk(mu);
+            cx->closed.insert(cx->closed.end(), fb.begin(), fb.begin() + nc);
+        }
+        total += nc;
+        for (int i = 0; i < nd; i++) finalize(cx, tags[i]);
+        if (nd < kTags && nc < kFeats) break;
+    }
+    if (n_closed_out) *n_closed_out = total;
+}
+
+int hc_server::run_chunk(StreamCtx* cx, const Req& r)
+{
+    const uint64_t seq = cx->seq++;
+    Pending p{r.tag, r.n, 0, r.labels, nullptr, 0, r.t_arrive, 0, 0};
+    const size_t hits_need = r.n > 0 ? block_class(sizeof(hc_hit) * (size_t)r.n) : 0;
+    const size_t hits_grow = hits_need > cx->hits_bytes ? hits_need - cx->hits_bytes : 0;
+    size_t transient = 0;
+    const size_t after = r.n > 0 ? stream_bytes_after_push(cx->st, r.n, &transient) : cx->state_bytes;
+    const size_t state_grow = after > cx->state_bytes ? after - cx->state_bytes : 0;
+    p.labels_class = r.n > 0 ? block_class(4 * (size_t)r.n) : 0;
+    // admission: a free slot and the memory of this push within the budget
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            auto fb = free_blocks.find(p.labels_class);
+            const bool reuse = r.n > 0 && fb != free_blocks.end() && !fb->second.empty();
+            const uint64_t need = hits_grow + state_grow + transient + (reuse || r.n == 0 ? 0 : p.labels_class);
+            if (slots_used < cfg.max_slots && used + need <= cfg.hbm_budget) {
+                if (reuse) {
+                    p.labels_dev = fb->second.back();
+                    fb->second.pop_back();
+                }
+                account((int64_t)need);
+                slots_used++;
+                peak_slots = std::max(peak_slots, slots_used);
+                queued--;
+                progress++;
+                break;
+            }
+            if (used + need > cfg.hbm_budget && !free_blocks.empty() && trim_cache() > 0) continue;
+            const uint64_t p0 = progress;
+            budget_cv.wait_for(lk, std::chrono::milliseconds(200));
+            if (progress == p0 && slots_used == 0 && used + need > cfg.hbm_budget) {
+                // nothing in flight can release memory: this chunk can never fit
+                queued--;
+                hc_completion c{};
+                c.tag = r.tag;
+                c.stream_id = cx->id;
+                c.status = HC_ERR_BUDGET;
+                c.n_hits = r.n;
+                c.t_arrive_ns = r.t_arrive;
+                c.t_admit_ns = c.t_processed_ns = c.t_final_ns = now_ns();
+                complete(c);
+                return HC_ERR_BUDGET;
+            }
+        }
+    }
+    p.t_admit = now_ns();
+    hipError_t e = hipSuccess;
+    int rc = HC_OK;
+    if (hits_grow > 0) {
+        (void)hipFree(cx->hits_dev);
+        cx->hits_dev = nullptr;
+        if ((e = hipMalloc(&cx->hits_dev, hits_need)) != hipSuccess) {
+            rc = set_device_error(e, "server: hits buffer");
+            std::lock_guard<std::mutex> lk(mu);
+            account(-(int64_t)cx->hits_bytes - (int64_t)hits_grow);
+            cx->hits_bytes = 0;
+        } else {
+            cx->hits_bytes = hits_need;
+        }
+    }
+    if (rc == HC_OK && r.n > 0 && !p.labels_dev) {
+        if ((e = hipMalloc(&p.labels_dev, p.labels_class)) != hipSuccess) {
+            p.labels_dev = nullptr;
+            rc = set_device_error(e, "server: labels buffer");
+            std::lock_guard<std::mutex> lk(mu);
+            account(-(int64_t)p.labels_class);
+        }
+    }
+    if (rc == HC_OK && r.n > 0 &&
+        (e = hipMemcpyAsync(cx->hits_dev, r.hits, sizeof(hc_hit) * (size_t)r.n, hipMemcpyHostToDevice, cx->hs)) !=
+            hipSuccess)
+        rc = set_device_error(e, "server: hits copy");
+    if (rc == HC_OK) rc = hc_stream_push(cx->st, (const hc_hit*)cx->hits_dev, r.n, (int32_t*)p.labels_dev, seq);
+    const size_t state_now = stream_device_bytes(cx->st);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        account((int64_t)state_now - (int64_t)(cx->state_bytes + state_grow) - (int64_t)transient);
+        cx->state_bytes = state_now;
+        slots_used--;
+        progress++;
+        budget_cv.notify_all();
+    }
+    if (rc != HC_OK) {
+        hc_completion c{};
+        c.tag = r.tag;
+        c.stream_id = cx->id;
+        c.status = rc;
+        c.n_hits = r.n;
+        c.t_arrive_ns = r.t_arrive;
+        c.t_admit_ns = p.t_admit;
+        c.t_processed_ns = c.t_final_ns = now_ns();
+        std::lock_guard<std::mutex> lk(mu);
+        if (p.labels_dev) free_blocks[p.labels_class].push_back(p.labels_dev);
+        complete(c);
+        return rc;
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        pending_final++;
+    }
+    cx->pend.emplace(seq, p);
+    int32_t n_closed = 0;
+    // closed clusters to the host first, then the processing stamp
+    {
+        constexpr int kFeats = 1 << 16;
+        std::vector<hc_features> fb(kFeats);
+        std::vector<uint64_t> tags(256);
+        std::vector<uint64_t> fin;
+        for (;;) {
+            int32_t nd = 0, nc = 0;
+            if (hc_stream_poll(cx->st, tags.data(), 256, &nd, fb.data(), kFeats, &nc) != HC_OK) break;
+            if (nc > 0) {
+                std::lock_guard<std::mutex> lk(mu);
+                cx->closed.insert(cx->closed.end(), fb.begin(), fb.begin() + nc);
+            }
+            n_closed += nc;
+            fin.insert(fin.end(), tags.begin(), tags.begin() + nd);
+            if (nd < 256 && nc < kFeats) break;
+        }
+        const uint64_t tp = now_ns();
+        auto it = cx->pend.find(seq);
+        if (it != cx->pend.end()) {
+            it->second.t_processed = tp;
+            it->second.n_closed = n_closed;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            lat_proc.push_back(tp - r.t_arrive);
+        }
+        for (uint64_t t : fin) finalize(cx, t);
+    }
+    return HC_OK;
+}
+
+void hc_server::worker(StreamCtx* cx)
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        Req r;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cx->cv.wait(lk, [&] { return stopping || !cx->q.empty(); });
+            if (cx->q.empty()) break;  // stopping and nothing left
+            r = cx->q.front();
+            cx->q.pop_front();
+            working++;
+            if (r.flush) queued--;
+        }
+        try {
+            if (r.flush) {
+                if (hc_stream_flush(cx->st) == HC_OK) drain(cx, nullptr);
+            } else {
+                run_chunk(cx, r);
+            }
+        } catch (...) {
+            (void)set_error(HC_ERR_DEVICE, "server worker: host exception");
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        working--;
+        progress++;
+        idle_cv.notify_all();
+        budget_cv.notify_all();
+    }
+}
+
+extern "C" {
+
+uint64_t hc_server_now_ns(void) { return now_ns(); }
+
+int hc_server_create(const hc_server_config* cfg, hc_server** out)
+{
+    if (!out || !cfg) return set_error(HC_ERR_ARG, "NULL config or out");
+    *out = nullptr;
+    hc_server_config c = *cfg;
+    if (!c.width) c.width = 256;
+    if (!c.height) c.height = 256;
+    if (c.width > 65535 || c.height > 65535 || c.flags || c.n_streams < 1 || c.n_streams > 256 || c.max_slots < 0)
+        return set_error(HC_ERR_ARG, "bad server configuration");
+    if (!c.max_slots) c.max_slots = c.n_streams;
+    if (!c.hbm_budget) c.hbm_budget = 16ull << 30;
+    if (!c.disorder_hint) c.disorder_hint = 4096;
+    hc_server* s = new hc_server();
+    s->cfg = c;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return set_device_error(e, "hipGetDevice");
+    }
+    int rc = HC_OK;
+    for (int i = 0; i < c.n_streams && rc == HC_OK; i++) {
+        StreamCtx* cx = new StreamCtx();
+        cx->id = i;
+        s->streams.push_back(cx);
+        if ((e = hipStreamCreateWithFlags(&cx->hs, hipStreamNonBlocking)) != hipSuccess) {
+            rc = set_device_error(e, "hipStreamCreate");
+            break;
+        }
+        hc_opts o{};
+        o.width = c.width;
+        o.height = c.height;
+        o.disorder_hint = c.disorder_hint;
+        o.stream = cx->hs;
+        if ((rc = hc_stream_create(&o, c.dt, c.max_disorder_ticks, &cx->st)) != HC_OK) break;
+        cx->state_bytes = stream_device_bytes(cx->st);
+        s->account((int64_t)cx->state_bytes);
+    }
+    if (rc == HC_OK && s->used > c.hbm_budget) rc = set_error(HC_ERR_BUDGET, "budget below the streams' base state");
+    if (rc != HC_OK) {
+        for (StreamCtx* cx : s->streams) {
+            if (cx->st) hc_stream_destroy(cx->st);
+            if (cx->hs) (void)hipStreamDestroy(cx->hs);
+            delete cx;
+        }
+        delete s;
+        return rc;
+    }
+    for (StreamCtx* cx : s->streams) cx->th = std::thread([s, cx] { s->worker(cx); });
+    *out = s;
+    return HC_OK;
+}
+
+int hc_server_submit(hc_server* s, int32_t stream_id, const hc_hit* hits, int32_t n, int32_t* labels, uint64_t tag,
+                     uint64_t t_arrive_ns)
+{
+    if (!s || stream_id < 0 || stream_id >= s->cfg.n_streams) return set_error(HC_ERR_ARG, "bad server or stream id");
+    if (n < 0 || (n > 0 && (!hits || !labels))) return set_error(HC_ERR_ARG, "bad chunk arguments");
+    if (block_class(sizeof(hc_hit) * (size_t)n) + block_class(4 * (size_t)n) > s->cfg.hbm_budget)
+        return set_error(HC_ERR_BUDGET, "chunk larger than the memory budget");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return set_error(HC_ERR_BUSY, "server is shutting down");
+    StreamCtx* cx = s->streams[stream_id];
+    cx->q.push_back(Req{false, tag, hits, n, labels, t_arrive_ns});
+    s->submitted++;
+    s->queued++;
+    cx->cv.notify_one();
+    return HC_OK;
+}
+
+int hc_server_flush(hc_server* s, int32_t stream_id)
+{
+    if (!s || stream_id < 0 || stream_id >= s->cfg.n_streams) return set_error(HC_ERR_ARG, "bad server or stream id");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return set_error(HC_ERR_BUSY, "server is shutting down");
+    StreamCtx* cx = s->streams[stream_id];
+    cx->q.push_back(Req{true, 0, nullptr, 0, nullptr, 0});
+    s->queued++;
+    cx->cv.notify_one();
+    return HC_OK;
+}
+
+int hc_server_poll(hc_server* s, hc_completion* out, int32_t cap, int32_t* n_out)
+{
+    if (!s || !n_out || (cap > 0 && !out)) return set_error(HC_ERR_ARG, "bad poll arguments");
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t k = 0;
+    while (k < cap && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n_out = k;
+    return HC_OK;
+}
+
+int hc_server_closed(hc_server* s, int32_t stream_id, hc_features* out, int32_t cap, int32_t* n_out)
+{
+    if (!s || !n_out || stream_id < 0 || stream_id >= s->cfg.n_streams || (cap > 0 && !out))
+        return set_error(HC_ERR_ARG, "bad arguments");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<hc_features>& v = s->streams[stream_id]->closed;
+    const int32_t k = (int32_t)std::min<size_t>((size_t)std::max(cap, 0), v.size());
+    if (k > 0) {
+        ::memcpy(out, v.data(), sizeof(hc_features) * (size_t)k);
+        v.erase(v.begin(), v.begin() + k);
+    }
+    *n_out = k;
+    return HC_OK;
+}
+
+int hc_server_wait_idle(hc_server* s, int32_t timeout_ms)
+{
+    if (!s) return set_error(HC_ERR_ARG, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    const bool ok = s->idle_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms),
+                                        [&] { return s->queued == 0 && s->working == 0; });
+    return ok ? HC_OK : set_error(HC_ERR_BUSY, "server still busy");
+}
+
+int hc_server_stats_read(hc_server* s, hc_server_stats* out)
+{
+    if (!s || !out) return set_error(HC_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    hc_server_stats st{};
+    st.submitted = s->submitted;
+    st.completed = s->completed;
+    st.rejected = s->rejected;
+    st.hits_completed = s->hits_completed;
+    st.queued = s->queued;
+    st.pending_final = s->pending_final;
+    st.hbm_budget = s->cfg.hbm_budget;
+    st.hbm_in_use = s->used;
+    st.hbm_peak = s->peak;
+    st.max_slots = s->cfg.max_slots;
+    st.peak_slots_in_use = s->peak_slots;
+    st.processing_p50 = quantile(s->lat_proc, 0.50);
+    st.processing_p99 = quantile(s->lat_proc, 0.99);
+    st.final_p50 = quantile(s->lat_final, 0.50);
+    st.final_p99 = quantile(s->lat_final, 0.99);
+    *out = st;
+    return HC_OK;
+}
+
+void hc_server_destroy(hc_server* s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        for (StreamCtx* cx : s->streams) cx->cv.notify_all();
+        s->budget_cv.notify_all();
+    }
+    for (StreamCtx* cx : s->streams)
+        if (cx->th.joinable()) cx->th.join();
+    for (StreamCtx* cx : s->streams) {
+        (void)hipStreamSynchronize(cx->hs);
+        for (auto& kv : cx->pend)
+            if (kv.second.labels_dev) (void)hipFree(kv.second.labels_dev);
+        hc_stream_destroy(cx->st);
+        (void)hipFree(cx->hits_dev);
+        (void)hipStreamDestroy(cx->hs);
+        delete cx;
+    }
+    for (auto& kv : s->free_blocks)
+        for (void* p : kv.second) (void)hipFree(p);
+    delete s;
+}
+
+}  // extern "C"

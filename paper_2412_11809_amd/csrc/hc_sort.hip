@@ -32,6 +32,8 @@ __global__ void k_init(Work w)
     int32_t* s = reinterpret_cast<int32_t*>(w.status);
     for (int i = t; i < (int)(sizeof(Status) / 4); i += stride) s[i] = 0;
     if (t == 0 && w.force_fallback) w.status->sort_fallback = 1;
+    if (w.n_seg > 1)
+        for (int i = t; i < w.n_seg; i += stride) w.segs[i].toa_min = ~0ull;
 }
 
 hipError_t launch_init(const Work& w, hipStream_t s)
@@ -52,11 +54,12 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __rest
     __shared__ uint32_t wsum[kSortThreads / kWave];
     __shared__ uint64_t red[kSortThreads / kWave];
 
-    const int tile = xcd_tile(w.n_sort_tiles);
+    const int tile = xcd_tile(w.n_sort_tiles, w.xcd_map);
     if (tile < 0) return;
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)tile * T;
-    const int cnt_e = (int)((w.n - base) < T ? (w.n - base) : T);
+    const TileRange tr = tile_range(w, kSortKind, tile, T);
+    const int64_t base = tr.start;
+    const int cnt_e = tr.count;
 
     uint64_t toa[IPT];
     uint64_t tmin = ~0ull, tmax = 0;
@@ -76,6 +79,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __rest
     if (bad) atomicOr(&w.status->err_range, 1);
     tmin = block_min_u64<kSortThreads>(tmin, red);
     tmax = block_max_u64<kSortThreads>(tmax, red);
+    if (w.n_seg > 1 && t == 0) atomicMin((unsigned long long*)&w.segs[tr.seg].toa_min, (unsigned long long)tmin);
     const uint64_t range = tmax - tmin;
     if (range > 0xFFFFFFFFull) {
         if (t == 0) {
@@ -173,11 +177,14 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
     constexpr int T = kSortThreads * IPT;
     __shared__ uint32_t nk[T];
     if (w.status->sort_fallback) return;  // a wide tile: everything is re-sorted later
-    const int j = xcd_tile(w.n_sort_tiles);
+    const int j = xcd_tile(w.n_sort_tiles, w.xcd_map);
     if (j < 0) return;
     const int t = threadIdx.x;
-    const int nt = w.n_sort_tiles, m = w.sort_m;
+    const int m = w.sort_m;
     const TileInfo tj = w.tiles[j];
+    // only tiles of the same chunk are merged; ranks are chunk-relative
+    const TileRange jr = tile_range(w, kSortKind, j, T);
+    const int t0 = jr.tile0, nt = jr.tile1;
 
     if (t == 0) {
         bool bad = false;
@@ -193,23 +200,24 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
         if (bad) atomicOr(&w.status->sort_fallback, 1);
     }
 
-    const int64_t base = (int64_t)j * T;
+    const int64_t base = jr.start;
     const int r0 = t * IPT;
     uint64_t toa[IPT];
     uint32_t rank[IPT];
-    const int first_tile = j - m < 0 ? 0 : j - m;
+    const int first_tile = j - m < t0 ? t0 : j - m;
 #pragma unroll
     for (int q = 0; q < IPT; q++) {
         const int r = r0 + q;
         toa[q] = r < tj.count ? tj.base + w.ts_rel[base + r] : ~0ull;
-        rank[q] = (uint32_t)((int64_t)first_tile * T + r);
+        rank[q] = (uint32_t)((int64_t)(first_tile - t0) * T + r);
     }
     const int last_tile = j + m >= nt ? nt - 1 : j + m;
     for (int i = first_tile; i <= last_tile; i++) {
         if (i == j) continue;
         const TileInfo ti = w.tiles[i];
+        const int64_t ibase = jr.seg_start + (int64_t)(i - t0) * T;
         __syncthreads();
-        for (int e = t; e < ti.count; e += kSortThreads) nk[e] = w.ts_rel[(int64_t)i * T + e];
+        for (int e = t; e < ti.count; e += kSortThreads) nk[e] = w.ts_rel[ibase + e];
         __syncthreads();
         int lo = 0;
 #pragma unroll
@@ -234,20 +242,24 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_gather(Work w)
     constexpr int T = kSortThreads * IPT;
     __shared__ uint32_t slot[T];
     if (w.status->sort_fallback) return;
-    const int k = xcd_tile(w.n_sort_tiles);
+    const int k = xcd_tile(w.n_sort_tiles, w.xcd_map);
     if (k < 0) return;
     const int t = threadIdx.x;
-    const int nt = w.n_sort_tiles, m = w.sort_m;
-    const int64_t out0 = (int64_t)k * T;
-    const int cnt_out = (int)((w.n - out0) < T ? (w.n - out0) : T);
+    const int m = w.sort_m;
+    const TileRange kr = tile_range(w, kSortKind, k, T);
+    const int t0 = kr.tile0, nt = kr.tile1;
+    const int64_t out0 = kr.start;                  // global position of the output tile
+    const int64_t rel0 = (int64_t)(k - t0) * T;     // its chunk-relative position
+    const int cnt_out = kr.count;
     for (int r = t; r < T; r += kSortThreads) slot[r] = 0xFFFFFFFFu;
     __syncthreads();
-    const int first_tile = k - m < 0 ? 0 : k - m;
+    const int first_tile = k - m < t0 ? t0 : k - m;
     const int last_tile = k + m >= nt ? nt - 1 : k + m;
     for (int i = first_tile; i <= last_tile; i++) {
         const int ci = w.tiles[i].count;
+        const int64_t ibase = kr.seg_start + (int64_t)(i - t0) * T;
         for (int e = t; e < ci; e += kSortThreads) {
-            const int64_t r = (int64_t)w.ts_rank[(int64_t)i * T + e] - out0;
+            const int64_t r = (int64_t)w.ts_rank[ibase + e] - rel0;
             if (r >= 0 && r < cnt_out) slot[r] = ((uint32_t)(i - first_tile) << 16) | (uint32_t)e;
         }
     }
@@ -259,11 +271,12 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_gather(Work w)
             continue;
         }
         const int i = first_tile + (int)(v >> 16);
-        const int64_t src = (int64_t)i * T + (v & 0xFFFFu);
+        const int64_t ibase = kr.seg_start + (int64_t)(i - t0) * T;
+        const int64_t src = ibase + (v & 0xFFFFu);
         const uint2 pay = w.ts_pay[src];
         const int64_t dst = out0 + r;
         w.s_toa[dst] = w.tiles[i].base + w.ts_rel[src];
-        w.s_idx[dst] = (int32_t)((int64_t)i * T + (pay.x & 0xFFFFu));
+        w.s_idx[dst] = (int32_t)(ibase + (pay.x & 0xFFFFu));
         w.s_tot[dst] = (uint16_t)(pay.x >> 16);
         w.s_xy[dst] = pay.y;
     }
@@ -294,33 +307,69 @@ hipError_t launch_tile_merge(const Work& w, hipStream_t s)
 }
 
 // ------------------------------------------------------ sort fallback
+// Sort key of the fallback: the ToA, or -- for a batch of chunks -- the chunk
+// id above the ToA relative to the chunk's minimum, so chunks stay apart and
+// in order.  Ties keep input order (the sort is stable), i.e. (toa, index).
 struct ToaSortJob {
     static constexpr bool kKeepSorted = false;
     const hc_hit* hits;
     Work w;
     __device__ int64_t count() const { return w.n; }
+    __device__ int seg_of(int64_t i) const
+    {
+        int a = 0, b = w.n_seg - 1;
+        while (a < b) {
+            const int m = (a + b + 1) >> 1;
+            if (w.segs[m].start <= i) a = m; else b = m - 1;
+        }
+        return a;
+    }
     __device__ void load(int64_t i, uint64_t& k, uint32_t& v) const
     {
-        k = hits[i].toa;
+        const uint64_t toa = hits[i].toa;
         v = (uint32_t)i;
+        if (w.n_seg <= 1) {
+            k = toa;
+        } else {
+            const int sg = seg_of(i);
+            k = ((uint64_t)sg << w.status->rs[0].shift) | (toa - w.segs[sg].toa_min);
+        }
     }
     __device__ int plan(RadixState& st, RadixLds& L)
     {
-        // global ToA range from the tile minima / maxima
         __shared__ uint64_t red[kFbThreads / kWave];
         uint64_t mn = ~0ull, mx = 0;
         for (int i = threadIdx.x; i < w.n_sort_tiles; i += kFbThreads) {
             const TileInfo ti = w.tiles[i];
-            mn = ti.base < mn ? ti.base : mn;
-            mx = ti.max_toa > mx ? ti.max_toa : mx;
+            if (w.n_seg <= 1) {
+                mn = ti.base < mn ? ti.base : mn;
+                mx = ti.max_toa > mx ? ti.max_toa : mx;
+            } else {  // largest span of a chunk
+                const uint64_t span = ti.max_toa - w.segs[w.tile_seg[kSortKind][i]].toa_min;
+                mx = span > mx ? span : mx;
+            }
         }
         mn = block_min_u64<kFbThreads>(mn, red);
         mx = block_max_u64<kFbThreads>(mx, red);
         if (threadIdx.x == 0) {
-            const bool on = w.status->sort_fallback != 0 && w.status->err_range == 0;
+            bool on = w.status->sort_fallback != 0 && w.status->err_range == 0;
+            uint64_t range;
+            if (w.n_seg <= 1) {
+                st.key_min = mn;
+                range = mx - mn;
+                st.shift = 0;
+            } else {
+                const int sb = 32 - __builtin_clz((uint32_t)(w.n_seg - 1));
+                const int tb = mx == 0 ? 0 : 64 - __builtin_clzll(mx);
+                if (sb + tb > 64) {
+                    atomicOr(&w.status->err_span, 1);
+                    on = false;
+                }
+                st.key_min = 0;
+                st.shift = tb;
+                range = ((uint64_t)(w.n_seg - 1) << tb) | mx;
+            }
             st.active = on ? 1 : 0;
-            st.key_min = mn;
-            const uint64_t range = mx - mn;
             const int bits = range == 0 ? 0 : 64 - __builtin_clzll(range);
             st.passes = bits <= 8 ? 1 : (bits + 7) / 8;
         }

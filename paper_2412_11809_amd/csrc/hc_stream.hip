@@ -320,6 +320,15 @@ static int ensure_capacity(hc_stream* st, int64_t n_all)
     return HC_OK;
 }
 
+// Device bytes a stream holds with buffers for `cap` hits, a workspace of
+// `ws` bytes, a closed-cluster queue of `q` records and `chunks` chunk slots.
+static size_t footprint(int64_t cap, size_t ws, int64_t q, int chunks)
+{
+    const size_t per_hit = 2 * (sizeof(hc_hit) + 4 + 4) + 1 + 4 + sizeof(hc_features);
+    return (size_t)cap * per_hit + 4 * (size_t)((cap + kCmpBlock - 1) / kCmpBlock + 1) + ws +
+           sizeof(hc_features) * (size_t)q + sizeof(ChunkRec) * (size_t)chunks + sizeof(StreamDev);
+}
+
 static int grow_chunks(hc_stream* st)
 {
     hipError_t e;
@@ -392,6 +401,45 @@ static int process(hc_stream* st, int64_t n_all, uint64_t wmark, int flush)
     }
     return HC_OK;
 }
+
+namespace hc {
+
+size_t stream_device_bytes(const hc_stream* st) { return footprint(st->cap, st->ws_bytes, st->q_cap, st->chunk_cap); }
+
+// What the stream will hold after pushing a chunk of n hits (the growth rules
+// of ensure_capacity and grow_chunks); *transient: bytes of old buffers that
+// are alive together with their replacements while growing.
+size_t stream_bytes_after_push(const hc_stream* st, int64_t n, size_t* transient)
+{
+    const int64_t n_all = st->n_open + n;
+    int64_t cap = st->cap;
+    size_t tr = 0;
+    if (n_all > cap) {
+        cap = st->cap * 2 > n_all ? st->cap * 2 : n_all;
+        if (cap < 4096) cap = 4096;
+        tr += footprint(st->cap, 0, 0, 0);
+    }
+    const size_t need = plan_workspace(n_all, st->W, st->H, sort_hint(st, st->n_open), nullptr, nullptr);
+    const size_t ws = need > st->ws_bytes ? need + need / 4 : st->ws_bytes;
+    int64_t q = st->q_cap;
+    if (st->q_count + n_all > q) {
+        q = st->q_cap * 2 > st->q_count + n_all ? st->q_cap * 2 : st->q_count + n_all;
+        tr += sizeof(hc_features) * (size_t)st->q_cap;
+    }
+    int chunks = st->chunk_cap;
+    bool free_slot = false;
+    for (int c = 0; c < st->chunk_cap && !free_slot; c++) free_slot = !st->chunks[c].active;
+    if (!free_slot) {
+        chunks = st->chunk_cap ? st->chunk_cap * 2 : 64;
+        tr += sizeof(ChunkRec) * (size_t)st->chunk_cap;
+    }
+    if (transient) *transient = tr;
+    return footprint(cap, ws, q, chunks);
+}
+
+int64_t stream_open_hits(const hc_stream* st) { return st->n_open; }
+
+}  // namespace hc
 
 extern "C" {
 
