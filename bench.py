@@ -66,6 +66,256 @@ def cpu_baseline(hits, p, budget_s):
             "sample": "the full %d-hit workload, one sequential run (%.1f s)" % (n, dt_s)}
 
 
+def bench_batch(hc, torch, dev, reps):
+    """64 chunks of log-uniform size (~27M hits, 4 detectors, dt per chunk in
+    {100, 200, 500} ns): the plain path chunk after chunk vs one batched launch
+    sequence (default plan, autotuned plan, and its HIP-graph replay)."""
+    import numpy as np
+    import hitgen
+    chunks, dts, _ = hitgen.config3()
+    sizes = np.array([c.size for c in chunks], dtype=np.int64)
+    offsets = np.zeros(len(chunks) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    n = int(offsets[-1])
+    dts = np.asarray(dts, dtype=np.uint64)
+    d_hits = hc.hits_to_device(np.concatenate(chunks), dev)
+    del chunks
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    feats = torch.empty((n, 64), dtype=torch.uint8, device=dev)
+    k = torch.empty(len(sizes), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    hint = 512
+    ws = torch.empty(hc.hc_workspace_size(int(sizes.max()), 256, 256, hint), dtype=torch.uint8, device=dev)
+    views = [(d_hits[16 * offsets[c]:16 * offsets[c + 1]], labels[offsets[c]:offsets[c + 1]],
+              feats[offsets[c]:offsets[c + 1]], k[c:c + 1]) for c in range(len(sizes))]
+
+    def sequential():
+        for c, (h, l, f, kk) in enumerate(views):
+            hc.hc_cluster(h, int(sizes[c]), int(dts[c]), l, f, kk, 256, 256, hint, ws, stream)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize(dev)
+        return (time.perf_counter() - t0) / reps
+
+    t_seq = timed(sequential)
+    k_seq = k.cpu().numpy().copy()
+    t_def = timed(lambda: hc.hc_cluster_batch(d_hits, offsets, dts, labels, feats, k, None, 256, 256, hint,
+                                              None, stream))
+    assert np.array_equal(k.cpu().numpy(), k_seq), "batched and sequential cluster counts differ"
+    t0 = time.perf_counter()
+    plan = hc.hc_batch_autotune(d_hits, offsets, dts, labels, feats, k, 256, 256, hint, stream)
+    torch.cuda.synchronize(dev)
+    t_tune = time.perf_counter() - t0
+    t_plan = timed(lambda: hc.hc_cluster_batch(d_hits, offsets, dts, labels, feats, k, plan, 256, 256, hint,
+                                               None, stream))
+    graph = hc.hc_batch_graph_create(d_hits, offsets, dts, labels, feats, k, plan, 256, 256, hint)
+    t_graph = timed(lambda: graph.launch(stream))
+    assert np.array_equal(k.cpu().numpy(), k_seq), "graph replay cluster counts differ"
+    desc = plan.describe()
+    graph.close()
+    plan.close()
+    mh = lambda t: round(n / t / 1e6, 1)
+    return {"workload": "64 chunks, log-uniform sizes in [1k, 2M] (%d hits), 4 detectors of 256x256, "
+                        "dt per chunk in {100, 200, 500} ns, local shuffle <= 512" % n,
+            "n_hits": n, "n_clusters": int(k_seq.sum()), "reps": reps,
+            "plain_sequential_mhits": mh(t_seq), "batched_mhits": mh(t_def),
+            "batched_autotuned_mhits": mh(t_plan), "batched_graph_mhits": mh(t_graph),
+            "speedup_vs_plain": round(t_seq / min(t_plan, t_graph, t_def), 2),
+            "plan": desc, "autotune_s": round(t_tune, 2),
+            "ms": {"plain_sequential": round(t_seq * 1e3, 3), "batched": round(t_def * 1e3, 3),
+                   "autotuned": round(t_plan * 1e3, 3), "graph": round(t_graph * 1e3, 3)}}
+
+
+def _served_pools(n_streams, pool, seed):
+    """One config-1 style pool at 37.5 Mhit/s per stream; stream s sees it
+    under the s-th symmetry of the square sensor (so the streams differ)."""
+    import numpy as np
+    import hitgen
+    span = int(round(pool / 37.5e6 * 1e9 / hitgen.TPX3_TICK_NS))
+    base = hitgen.blob_stream(pool, seed, 256, 256, span_ticks=span, jitter=hitgen.ns_to_ticks(100, hitgen.TPX3_TICK_NS),
+                              disorder=512)
+    pools = []
+    for s in range(n_streams):
+        h = base.copy()
+        x, y = base["x"].astype(np.int32), base["y"].astype(np.int32)
+        if s & 1:
+            x = 255 - x
+        if s & 2:
+            y = 255 - y
+        if s & 4:
+            x, y = y, x
+        h["x"], h["y"] = x, y
+        pools.append(h)
+    return pools, int(base["toa"].max()) + 1, hitgen.realised_disorder_ticks(base) + 1
+
+
+def _chunk_plan(rng, n, lo=4000, hi=1_000_000):
+    import numpy as np
+    sizes = []
+    left = n
+    while left > 0:
+        m = min(left, int(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        sizes.append(m)
+        left -= m
+    return sizes
+
+
+def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhits=300.0):
+    """8 detector streams (256x256, 37.5 Mhit/s each), chunks of log-uniform
+    size in [4k, 1M] hits arriving as independent Poisson processes at an
+    aggregate 300 Mhit/s, HBM budget 16 GiB, dt = 200 ns.  Each stream replays
+    its pool with a ToA offset per pass (two pinned copies, re-offset in place
+    once a pass has completed).  Also: the saturated rate (every chunk of one
+    pass submitted at once) against the same chunks pushed one by one through
+    one stream at a time."""
+    import heapq
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    import hitgen
+    seed = hitgen.BASE_SEED + 5
+    pools, span, tdis = _served_pools(n_streams, pool, seed)
+    period = span + tdis + 4096  # ToA offset between passes
+    dt = 128
+    rng = np.random.default_rng([seed, 9])
+    mean_chunk = (1_000_000 - 4000) / np.log(1_000_000 / 4000)
+    lam = rate_mhits * 1e6 / n_streams / mean_chunk  # chunks per second per stream
+
+    def pinned_hits(a):
+        t = torch.empty(a.nbytes, dtype=torch.uint8, pin_memory=True)
+        v = t.numpy().view(hitgen.HIT_DTYPE)
+        v[:] = a
+        return t, v
+
+    copies = [[pinned_hits(p) for _ in range(2)] for p in pools]
+    labels = [[torch.empty(pool, dtype=torch.int32, pin_memory=True) for _ in range(2)] for _ in pools]
+
+    # -- saturated: one pass of every stream submitted at once
+    srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
+    plans = [_chunk_plan(rng, pool) for _ in range(n_streams)]
+    t0 = hc.hc_server_now_ns()
+    for s in range(n_streams):
+        at = 0
+        for c, m in enumerate(plans[s]):
+            srv.submit(s, copies[s][0][0][16 * at:16 * (at + m)], labels[s][0][at:at + m], c, t0)
+            at += m
+    for s in range(n_streams):
+        srv.flush(s)
+    srv.wait_idle(600000)
+    t1 = hc.hc_server_now_ns()
+    comp = srv.poll(1 << 16)
+    sat = srv.stats()
+    srv.close()
+    assert (comp["status"] == 0).all()
+    sat_mhits = n_streams * pool / ((t1 - t0) / 1e9) / 1e6
+
+    # -- the same chunks through one hc_stream at a time, no overlap
+    t0 = time.perf_counter()
+    for s in range(n_streams):
+        st = hc.HcStream(dt, tdis, 256, 256, 512)
+        st.reserve(1_000_000)
+        d_hits = torch.empty(16 * 1_000_000, dtype=torch.uint8, device=dev)
+        d_lab = [torch.empty(1_000_000, dtype=torch.int32, device=dev) for _ in range(len(plans[s]))]
+        at = 0
+        for c, m in enumerate(plans[s]):
+            d_hits[:16 * m].copy_(copies[s][0][0][16 * at:16 * (at + m)], non_blocking=True)
+            st.hc_stream_push(d_hits, m, d_lab[c], c)
+            st.poll()
+            at += m
+        st.flush()
+        st.poll()
+        torch.cuda.synchronize(dev)
+        st.close()
+    seq_mhits = n_streams * pool / (time.perf_counter() - t0) / 1e6
+
+    # -- rate-limited: Poisson arrivals at the aggregate rate for `seconds`
+    srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
+    ex = ThreadPoolExecutor(max_workers=4)
+    ready = [[None, None] for _ in range(n_streams)]   # future of the in-place re-offset
+    passes = [[0, 1] for _ in range(n_streams)]        # pass held by each copy
+    outstanding = [[0, 0] for _ in range(n_streams)]
+    state = [{"pass": 0, "plan": _chunk_plan(rng, pool), "c": 0, "at": 0} for _ in range(n_streams)]
+    # the second copy starts one period later
+    for s in range(n_streams):
+        copies[s][1][1]["toa"] += np.uint64(period)
+    start = hc.hc_server_now_ns() + 20_000_000
+    end = start + int(seconds * 1e9)
+    events = [(start + int(rng.exponential(1e9 / lam)), s) for s in range(n_streams)]
+    heapq.heapify(events)
+    key_of = {}
+    n_sub = 0
+    comps = []
+
+    def collect():
+        for c in srv.poll(1 << 14):
+            s, cp = key_of.pop((int(c["stream_id"]), int(c["tag"])))
+            outstanding[s][cp] -= 1
+            comps.append(c)
+
+    while events and events[0][0] < end:
+        t_arr, s = heapq.heappop(events)
+        while hc.hc_server_now_ns() < t_arr:
+            collect()
+            time.sleep(0.0002)
+        stt = state[s]
+        cp = stt["pass"] % 2
+        if passes[s][cp] != stt["pass"]:
+            # wait until this copy's previous pass has completed, then re-offset it
+            while outstanding[s][cp] > 0:
+                collect()
+                time.sleep(0.0002)
+            if ready[s][cp] is None:
+                v = copies[s][cp][1]
+                ready[s][cp] = ex.submit(lambda v=v: v["toa"].__iadd__(np.uint64(2 * period)))
+            ready[s][cp].result()
+            ready[s][cp] = None
+            passes[s][cp] = stt["pass"]
+        m = stt["plan"][stt["c"]]
+        at = stt["at"]
+        tag = n_sub
+        key_of[(s, tag)] = (s, cp)
+        outstanding[s][cp] += 1
+        srv.submit(s, copies[s][cp][0][16 * at:16 * (at + m)], labels[s][cp][at:at + m], tag, t_arr)
+        n_sub += 1
+        stt["c"] += 1
+        stt["at"] += m
+        if stt["c"] == len(stt["plan"]):
+            stt.update({"pass": stt["pass"] + 1, "plan": _chunk_plan(rng, pool), "c": 0, "at": 0})
+        heapq.heappush(events, (t_arr + int(rng.exponential(1e9 / lam)), s))
+    t_last_arrival = hc.hc_server_now_ns()
+    srv.wait_idle(600000)
+    for s in range(n_streams):
+        srv.flush(s)
+    srv.wait_idle(600000)
+    collect()
+    stats = srv.stats()
+    srv.close()
+    ex.shutdown()
+    comps = np.array(comps, dtype=hc.COMPLETION_DTYPE) if comps else np.empty(0, dtype=hc.COMPLETION_DTYPE)
+    ok = comps[comps["status"] == 0]
+    hits_done = int(ok["n_hits"].sum())
+    t_span = (int(ok["t_final_ns"].max()) - start) / 1e9 if ok.size else float("nan")
+    proc = (ok["t_processed_ns"] - ok["t_arrive_ns"]) / 1e6
+    fin = (ok["t_final_ns"] - ok["t_arrive_ns"]) / 1e6
+    q = lambda a, f: round(float(np.quantile(a, f)), 3) if a.size else None
+    return {"workload": "%d streams of 256x256 at %.1f Mhit/s each, Poisson chunk arrivals (aggregate %.0f Mhit/s), "
+                        "chunks log-uniform in [4k, 1M] hits, dt = 200 ns, HBM budget 16 GiB, pools of %d hits "
+                        "replayed with a ToA offset per pass" % (n_streams, rate_mhits / n_streams, rate_mhits, pool),
+            "seconds": seconds, "chunks": int(comps.size), "rejected": int((comps["status"] != 0).sum()),
+            "offered_mhits": rate_mhits, "achieved_mhits": round(hits_done / t_span / 1e6, 1),
+            "processing_latency_ms": {"p50": q(proc, 0.5), "p99": q(proc, 0.99)},
+            "final_latency_ms": {"p50": q(fin, 0.5), "p99": q(fin, 0.99)},
+            "hbm_peak_bytes": int(stats["hbm_peak"]), "peak_slots_in_use": int(stats["peak_slots_in_use"]),
+            "saturated_mhits": round(sat_mhits, 1), "one_stream_at_a_time_mhits": round(seq_mhits, 1),
+            "saturated_speedup": round(sat_mhits / seq_mhits, 2),
+            "saturated_hbm_peak_bytes": int(sat["hbm_peak"]),
+            "note": "end-to-end from pinned host memory (H2D hits, D2H labels and closed features)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +323,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--hits", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch-form measurement")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--served-seconds", type=float, default=1.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -162,6 +415,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize(dev)
         out["copy_calibration_bytes"] = 1 << 30
+    if not args.no_batch:
+        del d_hits, ws, labels, feats
+        torch.cuda.empty_cache()
+        out["batch"] = bench_batch(hc, torch, dev, reps=5)
+        print("batch done", file=sys.stderr, flush=True)
+    if not args.no_served:
+        torch.cuda.empty_cache()
+        out["served"] = bench_served(hc, torch, dev, args.served_seconds)
+        print("served done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(hits, p, 30.0)
     print(json.dumps(out), flush=True)

@@ -146,6 +146,11 @@ int hc_stream_push(hc_stream* s, const hc_hit* hits, int32_t n, int32_t* labels,
 int hc_stream_poll(hc_stream* s, uint64_t* done_tags, int32_t cap, int32_t* n_done, hc_features* closed,
                    int32_t closed_cap, int32_t* n_closed);
 
+/* Pre-allocate the stream's device buffers for chunks of up to max_chunk
+ * hits (plus a margin of open hits), so that later pushes allocate nothing
+ * unless a chunk is larger or unusually many clusters stay open. */
+int hc_stream_reserve(hc_stream* s, int32_t max_chunk);
+
 /* Close every open cluster (end of stream); afterwards all pushed chunks are
  * complete. */
 int hc_stream_flush(hc_stream* s);
@@ -234,6 +239,8 @@ typedef struct {
     uint64_t hbm_budget;         /* bytes of device memory the server may hold (0 => 16 GiB) */
     uint32_t disorder_hint;      /* positional displacement hint (0 => 4096) */
     uint32_t flags;              /* must be 0 */
+    int32_t max_chunk_hits;      /* buffers are reserved up front for chunks this large (0 => 2^20) */
+    int32_t reserved;            /* must be 0 */
 } hc_server_config;
 
 typedef struct {

@@ -186,6 +186,8 @@ def _bind_stream(lib):
     lib.hc_stream_poll.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32)]
+    lib.hc_stream_reserve.restype = ctypes.c_int
+    lib.hc_stream_reserve.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.hc_stream_flush.restype = ctypes.c_int
     lib.hc_stream_flush.argtypes = [ctypes.c_void_p]
     lib.hc_stream_destroy.restype = None
@@ -215,13 +217,24 @@ class HcStream:
     def push(self, hits, labels, tag):
         self.hc_stream_push(hits, hits.numel() // 16, labels, tag)
 
-    def poll(self, cap=1 << 16, closed_cap=1 << 20):
-        tags = np.empty(max(cap, 1), dtype=np.uint64)
-        feats = np.empty(max(closed_cap, 1), dtype=FEATURE_DTYPE)
+    def poll(self, cap=1 << 12, closed_cap=1 << 16):
+        """All completed tags and closed features (drains in rounds of the caps)."""
+        if getattr(self, "_tags", None) is None or self._tags.size < cap or self._feats.size < closed_cap:
+            self._tags = np.empty(max(cap, 1), dtype=np.uint64)
+            self._feats = np.empty(max(closed_cap, 1), dtype=FEATURE_DTYPE)
+        done, feats = [], []
         nd, nc = ctypes.c_int32(), ctypes.c_int32()
-        _check(self._lib.hc_stream_poll(self._h, tags.ctypes.data, cap, ctypes.byref(nd),
-                                        feats.ctypes.data, closed_cap, ctypes.byref(nc)))
-        return tags[: nd.value].tolist(), feats[: nc.value].copy()
+        while True:
+            _check(self._lib.hc_stream_poll(self._h, self._tags.ctypes.data, cap, ctypes.byref(nd),
+                                            self._feats.ctypes.data, closed_cap, ctypes.byref(nc)))
+            done += self._tags[: nd.value].tolist()
+            feats.append(self._feats[: nc.value].copy())
+            if nd.value < cap and nc.value < closed_cap:
+                break
+        return done, np.concatenate(feats)
+
+    def reserve(self, max_chunk):
+        _check(self._lib.hc_stream_reserve(self._h, int(max_chunk)))
 
     def flush(self):
         _check(self._lib.hc_stream_flush(self._h))
@@ -404,7 +417,8 @@ def cluster_batch(hits, offsets, dts, width=256, height=256, disorder_hint=0, fe
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("width", ctypes.c_uint32), ("height", ctypes.c_uint32), ("n_streams", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("dt", ctypes.c_uint64), ("max_disorder_ticks", ctypes.c_uint64),
-                ("hbm_budget", ctypes.c_uint64), ("disorder_hint", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("hbm_budget", ctypes.c_uint64), ("disorder_hint", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("max_chunk_hits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 COMPLETION_DTYPE = np.dtype([
@@ -459,12 +473,13 @@ class HcServer:
     (this wrapper keeps a reference until then)."""
 
     def __init__(self, n_streams, dt, max_disorder_ticks, width=256, height=256, max_slots=0,
-                 hbm_budget=0, disorder_hint=0):
+                 hbm_budget=0, disorder_hint=0, max_chunk_hits=0):
         self._lib = _bind_server(load_library())
         c = _ServerConfig()
         c.width, c.height, c.n_streams, c.max_slots = width, height, n_streams, max_slots
         c.dt, c.max_disorder_ticks, c.hbm_budget = int(dt), int(max_disorder_ticks), int(hbm_budget)
         c.disorder_hint, c.flags = disorder_hint, 0
+        c.max_chunk_hits, c.reserved = int(max_chunk_hits), 0
         h = ctypes.c_void_p()
         _check(self._lib.hc_server_create(ctypes.byref(c), ctypes.byref(h)))
         self._h = h

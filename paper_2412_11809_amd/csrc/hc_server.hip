@@ -63,7 +63,11 @@ struct StreamCtx {
     void* hits_dev = nullptr;
     size_t hits_bytes = 0;
     size_t state_bytes = 0;  // device bytes of the hc_stream counted in `used`
+    uint64_t* tags_pin = nullptr;      // pinned drain buffers (completed chunk tags,
+    hc_features* feats_pin = nullptr;  // closed-cluster features)
 };
+
+constexpr int kDrainTags = 256, kDrainFeats = 1 << 16;
 
 uint64_t now_ns()
 {
@@ -133,7 +137,7 @@ struct hc_server {
 
     void worker(StreamCtx* cx);
     int run_chunk(StreamCtx* cx, const Req& r);
-    void drain(StreamCtx* cx, int32_t* n_closed_out);
+    void drain(StreamCtx* cx, int32_t* n_closed_out, std::vector<uint64_t>* fin);
     void finalize(StreamCtx* cx, uint64_t seq);
 };
 
@@ -166,23 +170,20 @@ void hc_server::finalize(StreamCtx* cx, uint64_t seq)
     complete(c);
 }
 
-// Move closed clusters to the host and finalize the chunks that completed.
-void hc_server::drain(StreamCtx* cx, int32_t* n_closed_out)
+// Move closed clusters to the host and collect the chunks that completed.
+void hc_server::drain(StreamCtx* cx, int32_t* n_closed_out, std::vector<uint64_t>* fin)
 {
-    constexpr int kTags = 256, kFeats = 1 << 16;
-    std::vector<uint64_t> tags(kTags);
-    std::vector<hc_features> fb(kFeats);
     int32_t total = 0;
     for (;;) {
         int32_t nd = 0, nc = 0;
-        if (hc_stream_poll(cx->st, tags.data(), kTags, &nd, fb.data(), kFeats, &nc) != HC_OK) break;
+        if (hc_stream_poll(cx->st, cx->tags_pin, kDrainTags, &nd, cx->feats_pin, kDrainFeats, &nc) != HC_OK) break;
         if (nc > 0) {
             std::lock_guard<std::mutex> lk(mu);
-            cx->closed.insert(cx->closed.end(), fb.begin(), fb.begin() + nc);
+            cx->closed.insert(cx->closed.end(), cx->feats_pin, cx->feats_pin + nc);
         }
         total += nc;
-        for (int i = 0; i < nd; i++) finalize(cx, tags[i]);
-        if (nd < kTags && nc < kFeats) break;
+        fin->insert(fin->end(), cx->tags_pin, cx->tags_pin + nd);
+        if (nd < kDrainTags && nc < kDrainFeats) break;
     }
     if (n_closed_out) *n_closed_out = total;
 }
@@ -201,12 +202,15 @@ int hc_server::run_chunk(StreamCtx* cx, const Req& r)
     {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
-            auto fb = free_blocks.find(p.labels_class);
-            const bool reuse = r.n > 0 && fb != free_blocks.end() && !fb->second.empty();
+            // the smallest cached label block that is large enough
+            auto fb = free_blocks.lower_bound(p.labels_class);
+            while (fb != free_blocks.end() && fb->second.empty()) ++fb;
+            const bool reuse = r.n > 0 && fb != free_blocks.end();
             const uint64_t need = hits_grow + state_grow + transient + (reuse || r.n == 0 ? 0 : p.labels_class);
             if (slots_used < cfg.max_slots && used + need <= cfg.hbm_budget) {
                 if (reuse) {
                     p.labels_dev = fb->second.back();
+                    p.labels_class = fb->first;
                     fb->second.pop_back();
                 }
                 account((int64_t)need);
@@ -290,36 +294,21 @@ int hc_server::run_chunk(StreamCtx* cx, const Req& r)
         pending_final++;
     }
     cx->pend.emplace(seq, p);
-    int32_t n_closed = 0;
     // closed clusters to the host first, then the processing stamp
-    {
-        constexpr int kFeats = 1 << 16;
-        std::vector<hc_features> fb(kFeats);
-        std::vector<uint64_t> tags(256);
-        std::vector<uint64_t> fin;
-        for (;;) {
-            int32_t nd = 0, nc = 0;
-            if (hc_stream_poll(cx->st, tags.data(), 256, &nd, fb.data(), kFeats, &nc) != HC_OK) break;
-            if (nc > 0) {
-                std::lock_guard<std::mutex> lk(mu);
-                cx->closed.insert(cx->closed.end(), fb.begin(), fb.begin() + nc);
-            }
-            n_closed += nc;
-            fin.insert(fin.end(), tags.begin(), tags.begin() + nd);
-            if (nd < 256 && nc < kFeats) break;
-        }
-        const uint64_t tp = now_ns();
-        auto it = cx->pend.find(seq);
-        if (it != cx->pend.end()) {
-            it->second.t_processed = tp;
-            it->second.n_closed = n_closed;
-        }
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            lat_proc.push_back(tp - r.t_arrive);
-        }
-        for (uint64_t t : fin) finalize(cx, t);
+    int32_t n_closed = 0;
+    std::vector<uint64_t> fin;
+    drain(cx, &n_closed, &fin);
+    const uint64_t tp = now_ns();
+    auto it = cx->pend.find(seq);
+    if (it != cx->pend.end()) {
+        it->second.t_processed = tp;
+        it->second.n_closed = n_closed;
     }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        lat_proc.push_back(tp - r.t_arrive);
+    }
+    for (uint64_t t : fin) finalize(cx, t);
     return HC_OK;
 }
 
@@ -339,7 +328,9 @@ void hc_server::worker(StreamCtx* cx)
         }
         try {
             if (r.flush) {
-                if (hc_stream_flush(cx->st) == HC_OK) drain(cx, nullptr);
+                std::vector<uint64_t> fin;
+                if (hc_stream_flush(cx->st) == HC_OK) drain(cx, nullptr, &fin);
+                for (uint64_t t : fin) finalize(cx, t);
             } else {
                 run_chunk(cx, r);
             }
@@ -365,8 +356,10 @@ int hc_server_create(const hc_server_config* cfg, hc_server** out)
     hc_server_config c = *cfg;
     if (!c.width) c.width = 256;
     if (!c.height) c.height = 256;
-    if (c.width > 65535 || c.height > 65535 || c.flags || c.n_streams < 1 || c.n_streams > 256 || c.max_slots < 0)
+    if (c.width > 65535 || c.height > 65535 || c.flags || c.reserved || c.n_streams < 1 || c.n_streams > 256 ||
+        c.max_slots < 0 || c.max_chunk_hits < 0)
         return set_error(HC_ERR_ARG, "bad server configuration");
+    if (!c.max_chunk_hits) c.max_chunk_hits = 1 << 20;
     if (!c.max_slots) c.max_slots = c.n_streams;
     if (!c.hbm_budget) c.hbm_budget = 16ull << 30;
     if (!c.disorder_hint) c.disorder_hint = 4096;
@@ -392,13 +385,49 @@ int hc_server_create(const hc_server_config* cfg, hc_server** out)
         o.disorder_hint = c.disorder_hint;
         o.stream = cx->hs;
         if ((rc = hc_stream_create(&o, c.dt, c.max_disorder_ticks, &cx->st)) != HC_OK) break;
+        // everything a chunk of max_chunk_hits needs, allocated once
+        if ((rc = hc_stream_reserve(cx->st, c.max_chunk_hits)) != HC_OK) break;
         cx->state_bytes = stream_device_bytes(cx->st);
         s->account((int64_t)cx->state_bytes);
+        cx->hits_bytes = block_class(sizeof(hc_hit) * (size_t)c.max_chunk_hits);
+        if ((e = hipMalloc(&cx->hits_dev, cx->hits_bytes)) != hipSuccess) {
+            cx->hits_bytes = 0;
+            rc = set_device_error(e, "hipMalloc(server hits)");
+            break;
+        }
+        s->account((int64_t)cx->hits_bytes);
+        if ((e = hipHostMalloc((void**)&cx->tags_pin, sizeof(uint64_t) * kDrainTags, hipHostMallocDefault)) !=
+                hipSuccess ||
+            (e = hipHostMalloc((void**)&cx->feats_pin, sizeof(hc_features) * kDrainFeats, hipHostMallocDefault)) !=
+                hipSuccess) {
+            rc = set_device_error(e, "hipHostMalloc(server drain)");
+            break;
+        }
+        // two label blocks per stream: the chunk in flight and one awaiting finality
+        const size_t lc = block_class(4 * (size_t)c.max_chunk_hits);
+        for (int b = 0; b < 2 && rc == HC_OK; b++) {
+            void* p = nullptr;
+            if ((e = hipMalloc(&p, lc)) != hipSuccess) {
+                rc = set_device_error(e, "hipMalloc(server labels)");
+                break;
+            }
+            s->free_blocks[lc].push_back(p);
+            s->account((int64_t)lc);
+        }
+        if (rc != HC_OK) break;
+        if (s->used > c.hbm_budget) {
+            rc = set_error(HC_ERR_BUDGET, "budget below the streams' reserved state");
+            break;
+        }
     }
-    if (rc == HC_OK && s->used > c.hbm_budget) rc = set_error(HC_ERR_BUDGET, "budget below the streams' base state");
     if (rc != HC_OK) {
+        for (auto& kv : s->free_blocks)
+            for (void* p : kv.second) (void)hipFree(p);
         for (StreamCtx* cx : s->streams) {
             if (cx->st) hc_stream_destroy(cx->st);
+            (void)hipFree(cx->hits_dev);
+            if (cx->tags_pin) (void)hipHostFree(cx->tags_pin);
+            if (cx->feats_pin) (void)hipHostFree(cx->feats_pin);
             if (cx->hs) (void)hipStreamDestroy(cx->hs);
             delete cx;
         }
@@ -517,6 +546,8 @@ void hc_server_destroy(hc_server* s)
             if (kv.second.labels_dev) (void)hipFree(kv.second.labels_dev);
         hc_stream_destroy(cx->st);
         (void)hipFree(cx->hits_dev);
+        (void)hipHostFree(cx->tags_pin);
+        (void)hipHostFree(cx->feats_pin);
         (void)hipStreamDestroy(cx->hs);
         delete cx;
     }

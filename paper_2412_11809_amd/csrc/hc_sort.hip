@@ -12,9 +12,11 @@
 //                 sides, the number of smaller keys there (binary search in
 //                 LDS).  This is exact whenever tiles more than m apart do not
 //                 interleave, which the kernel verifies from the tile min/max
-//                 keys (monotone tile minima and maxima, max of tile i below
-//                 min of tile i+m+1); a displacement of at most m*T/2 positions
-//                 guarantees it.
+//                 keys: tile minima ascend and the max of tile i lies below
+//                 the min of tile i+m+1 (then every element of a tile more
+//                 than m tiles away is smaller, resp. larger, than every
+//                 element of this one); a displacement of at most m*T/2
+//                 positions guarantees it.
 //   k_sort_fallback  if any check failed (or a tile's ToA range exceeds 32
 //                 bits), re-sorts everything with a ticketed LSD radix sort;
 //                 otherwise it exits at once.
@@ -188,10 +190,9 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
 
     if (t == 0) {
         bool bad = false;
-        if (j + 1 < nt) {
+        if (j + 1 < nt) {  // tile minima ascend (maxima need not: a short last tile may end early)
             const TileInfo tn = w.tiles[j + 1];
             bad |= key_less(tn.base, tn.min_idx, tj.base, tj.min_idx);
-            bad |= key_less(tn.max_toa, tn.max_idx, tj.max_toa, tj.max_idx);
         }
         if (j + m + 1 < nt) {
             const TileInfo tf = w.tiles[j + m + 1];
@@ -361,8 +362,9 @@ struct ToaSortJob {
             } else {
                 const int sb = 32 - __builtin_clz((uint32_t)(w.n_seg - 1));
                 const int tb = mx == 0 ? 0 : 64 - __builtin_clzll(mx);
-                if (sb + tb > 64) {
-                    atomicOr(&w.status->err_span, 1);
+                if (sb + tb > 64) {  // the chunk field does not fit beside the span:
+                    atomicOr(&w.status->err_span, 1);  // nothing is sorted, so every
+                    atomicOr(&w.status->err_range, 1);  // later stage must stand down
                     on = false;
                 }
                 st.key_min = 0;

@@ -533,6 +533,31 @@ int hc_stream_push(hc_stream* st, const hc_hit* hits, int32_t n, int32_t* labels
     return HC_OK;
 }
 
+int hc_stream_reserve(hc_stream* st, int32_t max_chunk)
+{
+    if (!st || max_chunk < 0) return set_error(HC_ERR_ARG, "bad stream or size");
+    if (st->failed) return set_error(HC_ERR_DEVICE, "stream failed earlier");
+    const int64_t margin = max_chunk / 4 + 4096;  // open hits carried between pushes
+    const int64_t n_all = (int64_t)max_chunk + (st->n_open > margin ? st->n_open : margin);
+    // size the workspace for the sort hint a push with `margin` open hits uses
+    const int64_t keep = st->n_open;
+    st->n_open = st->n_open > margin ? st->n_open : margin;
+    const size_t need = plan_workspace(n_all, st->W, st->H, sort_hint(st, st->n_open), nullptr, nullptr);
+    st->n_open = keep;
+    int rc = ensure_capacity(st, n_all);
+    if (rc != HC_OK) return rc;
+    if (need > st->ws_bytes) {
+        hipError_t e;
+        if ((e = hipStreamSynchronize(st->s)) != hipSuccess) return set_device_error(e, "hipStreamSynchronize");
+        (void)hipFree(st->ws);
+        st->ws = nullptr;
+        st->ws_bytes = 0;
+        if ((e = hipMalloc(&st->ws, need)) != hipSuccess) return set_device_error(e, "hipMalloc(stream workspace)");
+        st->ws_bytes = need;
+    }
+    return HC_OK;
+}
+
 int hc_stream_flush(hc_stream* st)
 {
     if (!st) return set_error(HC_ERR_ARG, "stream is NULL");

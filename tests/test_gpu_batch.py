@@ -108,10 +108,18 @@ def test_batch_all_empty(hc):
     assert list(k) == [0, 0, 0]
 
 
-def test_batch_range_error(hc):
+def test_batch_wide_chunk_and_range_error(hc):
     a = hitgen.blob_stream(1000, 41, span_ticks=64_000)
     b = hitgen.blob_stream(1000, 42, span_ticks=64_000)
-    b["toa"][5] = np.uint64(1 << 63) + np.uint64(7)  # chunk span above 2^63 with a 1-bit chunk field
+    # a chunk whose ToA span needs 63 bits: sorted by the fallback beside a
+    # 1-bit chunk field, still exact
+    b["toa"][5] = np.uint64(1 << 63) + np.uint64(7)
+    assert int(b["toa"].max()) - int(b["toa"].min()) < 1 << 63
+    got, k = run(hc, [a, b], [128, 128], hint=512)
+    compare(got, k, expect([a, b], [128, 128]), "wide chunk")
+    # a span of 2^64 - 1 ticks leaves no room for the chunk field
+    b["toa"][6] = np.uint64(0)
+    b["toa"][5] = np.uint64((1 << 64) - 1)
     got, k = run(hc, [a, b], [128, 128], hint=512)
     assert list(k) == [hc.HC_ERR_RANGE, hc.HC_ERR_RANGE]
 

@@ -1,0 +1,84 @@
+"""CPU emulation of the tiled ToA ordering (sort tiles of T hits, rank every
+element against the m neighbour tiles on each side): whenever the check on
+the tile minimum/maximum keys passes, the ranks are exactly the positions in
+(toa, index) order, and a displacement of at most m*T/2 always passes it --
+also when the last tile is short."""
+import numpy as np
+import pytest
+
+import hitgen
+
+
+def tile_ranks(toa, T, m):
+    """Returns (ranks or None if the check fails)."""
+    n = toa.size
+    idx = np.arange(n)
+    nt = (n + T - 1) // T
+    tiles = []
+    for j in range(nt):
+        a, b = j * T, min(n, (j + 1) * T)
+        o = np.lexsort((idx[a:b], toa[a:b]))
+        keys = list(zip(toa[a:b][o].tolist(), (a + o).tolist()))
+        tiles.append(keys)
+    for j in range(nt):
+        if j + 1 < nt and tiles[j + 1][0] < tiles[j][0]:
+            return None
+        if j + m + 1 < nt and not tiles[j][-1] < tiles[j + m + 1][0]:
+            return None
+    ranks = np.empty(n, dtype=np.int64)
+    for j in range(nt):
+        lo_t, hi_t = max(0, j - m), min(nt - 1, j + m)
+        for r, key in enumerate(tiles[j]):
+            rank = lo_t * T + r
+            for i in range(lo_t, hi_t + 1):
+                if i != j:
+                    rank += sum(1 for k in tiles[i] if k < key)
+            ranks[key[1]] = rank
+    return ranks
+
+
+def true_ranks(toa):
+    order = np.lexsort((np.arange(toa.size), toa))
+    r = np.empty(toa.size, dtype=np.int64)
+    r[order] = np.arange(toa.size)
+    return r
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_ranks_exact_when_check_passes(seed):
+    rng = np.random.default_rng(seed)
+    T = int(rng.choice([8, 16, 32]))
+    n = int(rng.integers(1, 6 * T))
+    D = int(rng.integers(0, 2 * T))
+    m = max(1, -(-2 * D // T))
+    toa = np.sort(rng.integers(0, 3 * n, n)).astype(np.int64)
+    key = np.arange(n) + rng.integers(0, D + 1, n)
+    toa = toa[np.argsort(key, kind="stable")]
+    r = tile_ranks(toa, T, m)
+    if D <= m * T // 2:
+        assert r is not None, "displacement within the bound must pass the check"
+    if r is not None:
+        assert np.array_equal(r, true_ranks(toa))
+
+
+def test_short_last_tile_passes():
+    # T = 16, 51 hits: the last tile holds 3.  Swapping positions 40 and 50
+    # (displacement 10) leaves the last tile's maximum below tile 2's; tile
+    # minima still ascend and the gap rule holds, and the ranks are exact.
+    T, D = 16, 10
+    toa = np.arange(3 * T + 3, dtype=np.int64)
+    toa[40], toa[50] = 50, 40
+    m = max(1, -(-2 * D // T))
+    r = tile_ranks(toa, T, m)
+    assert r is not None
+    assert np.array_equal(r, true_ranks(toa))
+
+
+def test_blob_stream_ranks():
+    h = hitgen.blob_stream(700, 3, span_ticks=700 * 64, disorder=24)
+    toa = h["toa"].astype(np.int64)
+    for T in (64, 128):
+        m = max(1, -(-2 * 24 // T))
+        r = tile_ranks(toa, T, m)
+        assert r is not None
+        assert np.array_equal(r, true_ranks(toa))
