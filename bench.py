@@ -33,26 +33,87 @@ ALG_BYTES = {
 }
 
 
-def kernel_sources_digest():
+# Source files each kernel is built from (its counter record is void once any changes).
+_COMMON = ["hc_device.h", "hc_internal.h", "hc_radix.h"]
+KERNEL_SOURCES = {
+    "tile_sort": ["hc_sort.hip"] + _COMMON, "tile_rank": ["hc_sort.hip"] + _COMMON,
+    "tile_gather": ["hc_sort.hip"] + _COMMON, "link": ["hc_link.hip"] + _COMMON,
+    "flatten": ["hc_link.hip"] + _COMMON, "features": ["hc_feat.hip"] + _COMMON,
+    "compact": ["hc_feat.hip"] + _COMMON,
+}
+# Device function of each timed launch, as rocprofv3 names it.
+KERNEL_FUNCS = {
+    "tile_sort": "hc::k_tile_sort<", "tile_rank": "hc::k_tile_rank<", "tile_gather": "hc::k_tile_gather<",
+    "link": "hc::k_link(", "flatten": "hc::k_flatten(", "features": "hc::k_features(",
+    "compact": "hc::k_compact(",
+}
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_config2.json")
+
+
+def kernel_sources_digest(kernel=None):
+    """Digest of a kernel's source files (all of csrc when kernel is None)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2412_11809_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    files = KERNEL_SOURCES.get(kernel) if kernel else None
+    for f in sorted(files or os.listdir(csrc)):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, digest):
+def measured_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_config2.json")
+    was taken on the kernel's current sources; else None."""
     try:
-        data = json.load(open(path))
+        data = json.load(open(TRAFFIC_JSON))
     except (OSError, ValueError):
         return None
-    if data.get("sources") != digest:
-        return None
     rec = data.get("kernels", {}).get(kernel)
-    return rec.get("hbm_bytes_per_launch") if rec else None
+    if not rec or rec.get("sources") != kernel_sources_digest(kernel):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def _counter_means(path):
+    """Mean counter value per (kernel name, counter) over dispatches, from the
+    counter_collection.csv files rocprofv3 writes under `path`."""
+    import csv
+    import glob
+    acc = {}
+    for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        for row in csv.DictReader(open(f)):
+            low = {k.lower(): v for k, v in row.items()}
+            key = (low["kernel_name"], low["counter_name"])
+            acc.setdefault(key, []).append(float(low["counter_value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic_from(fetch_dir, write_dir, command):
+    """Writes the counter summary: FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
+    per timed kernel, each scaled by what the counter reads for a plain 1 GiB
+    device copy in the same run (bench.py --copy-calibration)."""
+    fetch, write = _counter_means(fetch_dir), _counter_means(write_dir)
+
+    def copy_reading(means, counter):
+        vals = [v for (k, c), v in means.items() if c == counter and "copyBuffer" in k]
+        return max(vals) if vals else None
+
+    f_copy, w_copy = copy_reading(fetch, "FETCH_SIZE"), copy_reading(write, "WRITE_SIZE")
+    if not f_copy or not w_copy:
+        raise SystemExit("no copy-kernel counter readings; run the profiled bench with --copy-calibration")
+    f_scale, w_scale = (1 << 30) / (f_copy * 1024), (1 << 30) / (w_copy * 1024)
+    out = {"command": command, "calibration": {"copy_bytes": 1 << 30, "fetch_kib": f_copy, "write_kib": w_copy,
+                                               "fetch_scale": round(f_scale, 3), "write_scale": round(w_scale, 3)},
+           "kernels": {}}
+    for name, func in KERNEL_FUNCS.items():
+        fk = [v for (k, c), v in fetch.items() if c == "FETCH_SIZE" and func in k]
+        wk = [v for (k, c), v in write.items() if c == "WRITE_SIZE" and func in k]
+        if not fk or not wk:
+            continue
+        fb, wb = fk[0] * 1024 * f_scale, wk[0] * 1024 * w_scale
+        out["kernels"][name] = {"sources": kernel_sources_digest(name), "fetch_kib": round(fk[0], 1),
+                                "write_kib": round(wk[0], 1), "hbm_bytes_per_launch": int(fb + wb)}
+    json.dump(out, open(TRAFFIC_JSON, "w"), indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(hits, p, budget_s):
@@ -328,7 +389,21 @@ def main():
     ap.add_argument("--served-seconds", type=float, default=1.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--only", choices=["plain", "batch", "served"],
+                    help="run one form only (profiling runs); the plain line is still printed")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_config2.json from two rocprofv3 --pmc runs (CSV output) "
+                         "of this bench with --copy-calibration, then exit")
+    ap.add_argument("--traffic-command", default="", help="the profiling command, recorded in the summary")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(args.traffic_from[0], args.traffic_from[1], args.traffic_command)
+        return
+    if args.only == "plain":
+        args.no_batch = args.no_served = True
+    elif args.only in ("batch", "served"):
+        args.steps, args.warmup = 1, 0
+        args.no_batch, args.no_served = args.only != "batch", args.only != "served"
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
@@ -374,14 +449,13 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step / 1e3) / 1e6
 
-    digest = kernel_sources_digest()
     dom = max(times, key=lambda name: times[name][1])
     launches, total_ms = times[dom]
     avg_ms = total_ms / launches
     per_hit, per_cluster = ALG_BYTES.get(dom, (0, 0))
     alg = per_hit * n + per_cluster * n_clusters
     achieved = alg / (avg_ms / 1e3) / 1e9
-    traffic = measured_traffic(dom, digest)
+    traffic = measured_traffic(dom)
     path_bytes = 20 * n + 64 * n_clusters
     out = {
         "metric": METRIC,
@@ -407,7 +481,7 @@ def main():
                           "frac": round(path_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                           "bytes_per_step": path_bytes},
         "kernels_ms_per_step": {name: round(v[1] / max(1, args.steps), 4) for name, v in sorted(times.items())},
-        "sources": digest,
+        "sources": kernel_sources_digest(),
     }
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

@@ -218,7 +218,17 @@ __device__ inline int32_t ld_acquire(const int32_t* p)
 __device__ inline void wait_at_least(const int32_t* p, int32_t target, int32_t* lds_flag)
 {
     if (threadIdx.x == 0) {
-        while (ld_acquire(p) < target) __builtin_amdgcn_s_sleep(4);
+        // back off: hundreds of waiting work-groups polling one counter at a
+        // high rate would crowd out the memory traffic of the task they wait for
+        int spins = 0;
+        while (ld_acquire(p) < target) {
+            if (spins < 16) {
+                __builtin_amdgcn_s_sleep(8);
+                spins++;
+            } else {
+                __builtin_amdgcn_s_sleep(127);
+            }
+        }
     }
     __syncthreads();
     __threadfence();

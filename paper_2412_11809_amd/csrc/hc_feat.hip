@@ -18,11 +18,11 @@
 
 namespace hc {
 
-__device__ inline uint32_t root_hash(uint32_t key) { return (key * 0x9E3779B1u) >> 22; }  // 10 bits
+__device__ inline uint32_t root_hash(uint32_t key) { return (key * 0x9E3779B1u) >> 23; }  // 9 bits
 
 __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t* __restrict__ labels)
 {
-    static_assert(kFeatHash == 1024, "root_hash yields 10 bits");
+    static_assert(kFeatHash == 512 && kFeatHash >= kFeatTile, "root_hash yields 9 bits; a tile never fills the table");
     __shared__ uint32_t h_key[kFeatHash];
     __shared__ uint32_t a_size[kFeatHash], a_st[kFeatHash], a_sx[kFeatHash], a_sy[kFeatHash], a_own[kFeatHash];
     __shared__ unsigned long long a_sxt[kFeatHash], a_syt[kFeatHash], a_tmin[kFeatHash], a_tmax[kFeatHash];

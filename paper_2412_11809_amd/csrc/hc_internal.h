@@ -20,7 +20,7 @@ constexpr int kLinkThreads = 512;
 
 constexpr int kFeatTile = 512;        // sorted hits per feature work-group
 constexpr int kFeatThreads = 256;
-constexpr int kFeatHash = 1024;       // root hash slots (>= 2 x tile)
+constexpr int kFeatHash = 512;        // root hash slots (>= tile: a tile never fills it)
 constexpr int kScanBlock = 2048;      // input indices per compaction block
 constexpr int kScanThreads = 256;
 constexpr int kFbBlock = 2048;        // elements per fallback radix block

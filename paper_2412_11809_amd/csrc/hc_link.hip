@@ -8,19 +8,18 @@
 // Here each work-group takes a tile of kLinkTile consecutive sorted hits plus
 // the "halo" of earlier hits whose ToA lies within dt of the tile's first hit,
 // and works entirely in LDS:
-//   * a pixel hash (open addressing) maps each occupied pixel of the tile and
-//     halo to the list of its hits -- the tile-sized replacement of the
-//     paper's dense matrix;
-//   * each tile hit b probes its 9 pixels and joins ONE earlier hit at each
-//     pixel that is within dt of it.  Any such hit will do: the hits of one
-//     pixel whose consecutive ToAs differ by <= dt are already chained by
-//     their own-pixel probes, so joining any of them joins the one the
-//     paper's "latest hit" rule would have picked;
-//   * joins go into an LDS union-find that links the root with the larger
-//     input index under the smaller one, so every tree's root is its smallest
-//     input index -- the canonical label;
-//   * the tile's forest is written to the global parent array; halo hits that
-//     the tile joined together are queued as cross-tile edges.
+//   * an occupancy bitmap of the sensor and the popcount prefix of its words
+//     give every occupied pixel of the tile a dense rank, and a CSR lists the
+//     tile's hits per pixel rank in time order -- the tile-sized replacement
+//     of the paper's dense matrix;
+//   * each tile hit joins, at each of its 9 pixels, the latest earlier hit if
+//     it lies within dt (the hit the paper's matrix holds).  Hits of one pixel
+//     whose consecutive ToAs differ by <= dt are chained by their own-pixel
+//     probes, so this reaches every earlier hit within dt;
+//   * the joins are applied in bulk rounds in an LDS forest whose roots are
+//     the earliest slots (the paper's time-ordered roots); the smallest input
+//     index of every tree is the label candidate written to the global parent
+//     array, and halo hits joined by the tile are queued as cross-tile edges.
 // A tile whose halo does not fit (or whose ToA span exceeds 32 bits) is
 // handled by k_link_fallback: a pixel-sorted copy of all hits plus binary
 // searches.  k_union_edges applies the queued cross-tile edges with atomic
@@ -29,46 +28,6 @@
 #include "hc_radix.h"
 
 namespace hc {
-
-
-// ---- LDS union-find over local slots; a tree's root is its smallest slot
-__device__ inline int32_t ld_lds(const int32_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ inline void st_lds(int32_t* p, int32_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ inline int32_t lfind(int32_t* par, int32_t x)
-{
-    while (true) {
-        const int32_t p = ld_lds(par + x);
-        if (p == x) return x;
-        const int32_t g = ld_lds(par + p);
-        if (g != p) st_lds(par + x, g);
-        x = g;
-    }
-}
-
-__device__ inline void lunion(int32_t* par, int32_t a, int32_t b)
-{
-    while (true) {
-        a = lfind(par, a);
-        b = lfind(par, b);
-        if (a == b) return;
-        if (a > b) {
-            const int32_t t = a;
-            a = b;
-            b = t;
-        }
-        int32_t expected = b;
-        if (__hip_atomic_compare_exchange_strong(par + b, &expected, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
-            return;
-    }
-}
 
 // First halo position of every link tile: the earliest sorted position p
 // with toa(p) >= toa(p0) - dt (a suffix of the positions before p0, so a
@@ -122,24 +81,27 @@ hipError_t launch_link_halo(const Work& w, hipStream_t s)
 // time-ordered forest.  The smallest input index of every local tree is then
 // published as the label candidate of its tile hits; halo hits joined by the
 // tile become cross-tile edges.
-// Dynamic LDS: bitmap (bm_words words) followed by the word prefix counts.
+// Dynamic LDS: bitmap (bm_words words) followed by the 16-bit word prefix
+// counts.  LDS is kept near 53 KiB (256 x 256 sensor) so three work-groups
+// share a CU.
 __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
 {
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
     constexpr int PER = kLinkTile / kLinkThreads;
     constexpr int LPER = LCAP / kLinkThreads;
-    constexpr uint32_t kUnsorted = 0x80000000u;
+    constexpr uint16_t kUnsorted = 0x8000u;
     __shared__ uint32_t l_toa[LCAP];
     __shared__ uint32_t l_xy[LCAP];
     __shared__ int32_t l_par[LCAP];
     __shared__ uint16_t l_rank[LCAP];     // hit's rank among its pixel's hits, then root
     __shared__ uint16_t l_pixr[LCAP];     // hit's pixel rank
     __shared__ uint16_t csr[LCAP];        // slots grouped by pixel rank
-    __shared__ uint32_t pstart[LCAP + 1]; // count, then first CSR position per pixel rank [| kUnsorted]
+    __shared__ uint16_t pstart[LCAP + 2]; // count (packed in pairs), then first CSR position per pixel rank [| kUnsorted]
     __shared__ uint32_t wsum[kLinkThreads / kWave];
     extern __shared__ uint32_t dyn[];
     uint32_t* bm = dyn;
-    uint32_t* wpre = dyn + bm_words;
+    uint16_t* wpre = reinterpret_cast<uint16_t*>(dyn + bm_words);
+    uint32_t* pcount = reinterpret_cast<uint32_t*>(pstart);  // two 16-bit counters per word
 
     if (w.status->err_range) return;
     const int tile = xcd_tile(w.n_link_tiles, w.xcd_map);
@@ -184,7 +146,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         }
     }
     for (int i = t; i < bm_words; i += kLinkThreads) bm[i] = 0u;
-    for (int i = t; i <= LCAP; i += kLinkThreads) pstart[i] = 0u;
+    for (int i = t; i < (LCAP + 2) / 2; i += kLinkThreads) pcount[i] = 0u;
     __syncthreads();
 
     // ---- occupancy bitmap
@@ -204,7 +166,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         uint32_t run = block_exclusive_scan<kLinkThreads>(c, wsum, nullptr);
         for (int k = 0; k < per; k++)
             if (w0 + k < bm_words) {
-                wpre[w0 + k] = run;
+                wpre[w0 + k] = (uint16_t)run;
                 run += __popc(bm[w0 + k]);
             }
     }
@@ -216,7 +178,8 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         const uint32_t wd = pix >> 5;
         const uint32_t r = wpre[wd] + __popc(bm[wd] & ((1u << (pix & 31u)) - 1u));
         l_pixr[i] = (uint16_t)r;
-        l_rank[i] = (uint16_t)atomicAdd(&pstart[r], 1u);
+        const uint32_t half = 16u * (r & 1u);  // counts stay below 2^16: no carry into the neighbour
+        l_rank[i] = (uint16_t)(atomicAdd(&pcount[r >> 1], 1u << half) >> half);
     }
     __syncthreads();
     // ---- exclusive scan of the counts -> first CSR position per pixel rank
@@ -231,10 +194,10 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         uint32_t run = block_exclusive_scan<kLinkThreads>(sum, wsum, nullptr);
 #pragma unroll
         for (int k = 0; k < LPER; k++) {
-            pstart[t * LPER + k] = run;
+            pstart[t * LPER + k] = (uint16_t)run;
             run += c[k];
         }
-        if (t == kLinkThreads - 1) pstart[LCAP] = run;
+        if (t == kLinkThreads - 1) pstart[LCAP] = (uint16_t)run;
     }
     __syncthreads();
     for (int i = t; i < L; i += kLinkThreads) csr[pstart[l_pixr[i]] + l_rank[i]] = (uint16_t)i;
@@ -247,7 +210,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         const int cnt = s1 - s0;
         if (cnt < 2) continue;
         if (cnt > 64) {
-            pstart[r] = (uint32_t)s0 | kUnsorted;
+            pstart[r] = (uint16_t)(s0 | kUnsorted);
             continue;
         }
         for (int a = s0 + 1; a < s1; a++) {
@@ -293,7 +256,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
 #pragma unroll
             for (int k = 0; k < 3; k++) {
                 if (!(occ & (1u << k))) continue;
-                const uint32_t st = pstart[rk];
+                const uint32_t st = pstart[rk];  // (16-bit entry)
                 const int s0 = (int)(st & ~kUnsorted), s1 = (int)(pstart[rk + 1] & ~kUnsorted);
                 rk++;
                 int a = -1;
@@ -350,7 +313,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
     }
 
     // ---- smallest input index per local tree, then publish
-    int32_t* minidx = reinterpret_cast<int32_t*>(pstart);  // reused: L <= LCAP
+    int32_t* minidx = reinterpret_cast<int32_t*>(l_toa);  // reused: L <= LCAP, ToAs no longer read
     for (int i = t; i < L; i += kLinkThreads) minidx[i] = 0x7FFFFFFF;
     __syncthreads();
     int32_t root[LPER];
@@ -380,8 +343,8 @@ hipError_t launch_link(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("link", s);
     const int bm_words = link_bitmap_words(w.width, w.height);
-    hipLaunchKernelGGL(k_link, dim3(xcd_grid(w.n_link_tiles)), dim3(kLinkThreads), (size_t)bm_words * 8, s, w,
-                       bm_words);
+    const size_t dyn = (size_t)bm_words * 4 + (((size_t)bm_words * 2 + 3) & ~(size_t)3);
+    hipLaunchKernelGGL(k_link, dim3(xcd_grid(w.n_link_tiles)), dim3(kLinkThreads), dyn, s, w, bm_words);
     return hipGetLastError();
 }
 

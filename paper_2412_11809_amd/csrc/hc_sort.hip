@@ -46,15 +46,17 @@ hipError_t launch_init(const Work& w, hipStream_t s)
 }
 
 // ---------------------------------------------------------- tile sort
-template <int IPT>
-__global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __restrict__ hits, Work w)
+// NT threads sort a tile of T = NT * IPT hits (8192-hit tiles use 1024
+// threads: their LDS allows one work-group per CU, so it gets more waves).
+template <int NT, int IPT>
+__global__ __launch_bounds__(NT) void k_tile_sort(const hc_hit* __restrict__ hits, Work w)
 {
-    constexpr int T = kSortThreads * IPT;
+    constexpr int T = NT * IPT;
     __shared__ uint32_t k0[T], k1[T];
     __shared__ uint16_t v0[T], v1[T];
-    __shared__ uint16_t cnt[16 * kSortThreads];
-    __shared__ uint32_t wsum[kSortThreads / kWave];
-    __shared__ uint64_t red[kSortThreads / kWave];
+    __shared__ uint16_t cnt[16 * NT];
+    __shared__ uint32_t wsum[NT / kWave];
+    __shared__ uint64_t red[NT / kWave];
 
     const int tile = xcd_tile(w.n_sort_tiles, w.xcd_map);
     if (tile < 0) return;
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __rest
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
-        const int e = t + j * kSortThreads;
+        const int e = t + j * NT;
         toa[j] = 0;
         if (e < cnt_e) {
             const hc_hit h = hits[base + e];
@@ -79,8 +81,8 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __rest
         }
     }
     if (bad) atomicOr(&w.status->err_range, 1);
-    tmin = block_min_u64<kSortThreads>(tmin, red);
-    tmax = block_max_u64<kSortThreads>(tmax, red);
+    tmin = block_min_u64<NT>(tmin, red);
+    tmax = block_max_u64<NT>(tmax, red);
     if (w.n_seg > 1 && t == 0) atomicMin((unsigned long long*)&w.segs[tr.seg].toa_min, (unsigned long long)tmin);
     const uint64_t range = tmax - tmin;
     if (range > 0xFFFFFFFFull) {
@@ -99,18 +101,18 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __rest
     }
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
-        const int e = t + j * kSortThreads;
+        const int e = t + j * NT;
         k0[e] = e < cnt_e ? (uint32_t)(toa[j] - tmin) : 0xFFFFFFFFu;
         v0[e] = (uint16_t)e;
     }
     __syncthreads();
     const int bits = range == 0 ? 0 : 32 - __builtin_clz((uint32_t)range);
-    const int which = block_radix_sort<kSortThreads, IPT>(k0, v0, k1, v1, cnt, wsum, bits);
+    const int which = block_radix_sort<NT, IPT>(k0, v0, k1, v1, cnt, wsum, bits);
     const uint32_t* sk = which ? k1 : k0;
     const uint16_t* sv = which ? v1 : v0;
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
-        const int e = t + j * kSortThreads;
+        const int e = t + j * NT;
         if (e < cnt_e) {
             uint16_t l = sv[e];
             if (l >= cnt_e) {
@@ -138,11 +140,11 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(const hc_hit* __rest
 hipError_t launch_tile_sort(const hc_hit* hits, const Work& w, hipStream_t s)
 {
     TimedLaunch tl("tile_sort", s);
-    dim3 grid(xcd_grid(w.n_sort_tiles)), block(kSortThreads);
-    switch (w.sort_ipt) {
-    case 4: hipLaunchKernelGGL(k_tile_sort<4>, grid, block, 0, s, hits, w); break;
-    case 8: hipLaunchKernelGGL(k_tile_sort<8>, grid, block, 0, s, hits, w); break;
-    case 16: hipLaunchKernelGGL(k_tile_sort<16>, grid, block, 0, s, hits, w); break;
+    const dim3 grid(xcd_grid(w.n_sort_tiles));
+    switch (w.sort_tile) {
+    case 2048: hipLaunchKernelGGL((k_tile_sort<512, 4>), grid, dim3(512), 0, s, hits, w); break;
+    case 4096: hipLaunchKernelGGL((k_tile_sort<512, 8>), grid, dim3(512), 0, s, hits, w); break;
+    case 8192: hipLaunchKernelGGL((k_tile_sort<1024, 8>), grid, dim3(1024), 0, s, hits, w); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
