@@ -75,13 +75,18 @@ typedef struct {
                                 partial orderliness, Section 3.1).  A tuning
                                 hint only: wrong values cost speed, never
                                 exactness. 0 = 4096. */
-    uint32_t flags;          /* reserved, 0 */
+    uint32_t flags;          /* 0, or HC_FLAG_LINK_PIXEL_INDEX */
     void* workspace;         /* device scratch of >= hc_workspace_size bytes,
                                 or NULL: the library then keeps a cached
                                 per-device buffer (grown with hipMalloc) */
     size_t workspace_bytes;
     void* stream;            /* hipStream_t to run on; NULL = null stream */
 } hc_opts;
+
+/* Neighbour search variant (same results): by default each hit scans the
+ * earlier hits of its dt window (sensors up to 16384 x 16384); with this flag
+ * every tile builds a pixel index (occupancy bitmap + per-pixel lists). */
+#define HC_FLAG_LINK_PIXEL_INDEX 1u
 
 enum {
     HC_OK = 0,

@@ -75,9 +75,12 @@ def load_library(path=LIB_PATH):
     return lib
 
 
-def _opts(width, height, disorder_hint, workspace, stream):
+HC_FLAG_LINK_PIXEL_INDEX = 1
+
+
+def _opts(width, height, disorder_hint, workspace, stream, flags=0):
     o = _Opts()
-    o.width, o.height, o.disorder_hint, o.flags = width, height, disorder_hint, 0
+    o.width, o.height, o.disorder_hint, o.flags = width, height, disorder_hint, flags
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -109,7 +112,7 @@ def hc_workspace_size(n, width=256, height=256, disorder_hint=0):
 
 
 def hc_cluster(hits, n, dt, labels, features, n_clusters, width=256, height=256, disorder_hint=0,
-               workspace=None, stream=None):
+               workspace=None, stream=None, flags=0):
     """Direct call of the C entry point on device tensors (no allocation).
 
     hits: uint8 tensor of n*16 bytes; labels: int32[n]; features: uint8 tensor
@@ -117,7 +120,7 @@ def hc_cluster(hits, n, dt, labels, features, n_clusters, width=256, height=256,
     import torch
     if stream is None:
         stream = torch.cuda.current_stream(hits.device)
-    o = _opts(width, height, disorder_hint, workspace, stream)
+    o = _opts(width, height, disorder_hint, workspace, stream, flags)
     rc = load_library().hc_cluster(_ptr(hits), int(n), int(dt), _ptr(labels), _ptr(features),
                                    _ptr(n_clusters), ctypes.byref(o))
     _check(rc)
@@ -131,7 +134,7 @@ def hits_to_device(hits, device="cuda"):
 
 
 def cluster(hits, dt, width=256, height=256, disorder_hint=0, features=True, workspace=None,
-            stream=None):
+            stream=None, flags=0):
     """Cluster a device tensor of hits; returns (labels, features_bytes, n_clusters)
     as device tensors (features_bytes is uint8 [n, 64] or None)."""
     import torch
@@ -140,7 +143,7 @@ def cluster(hits, dt, width=256, height=256, disorder_hint=0, features=True, wor
     labels = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     feats = torch.empty((max(n, 1), 64), dtype=torch.uint8, device=dev) if features else None
     k = torch.empty(1, dtype=torch.int32, device=dev)
-    hc_cluster(hits, n, dt, labels, feats, k, width, height, disorder_hint, workspace, stream)
+    hc_cluster(hits, n, dt, labels, feats, k, width, height, disorder_hint, workspace, stream, flags)
     return labels[:n], feats, k
 
 
@@ -199,13 +202,13 @@ def _bind_stream(lib):
 class HcStream:
     """One detector stream (hc_stream_*): push device chunks, poll completions."""
 
-    def __init__(self, dt, max_disorder_ticks, width=256, height=256, disorder_hint=0, stream=None):
+    def __init__(self, dt, max_disorder_ticks, width=256, height=256, disorder_hint=0, stream=None, flags=0):
         import torch
         self._lib = _bind_stream(load_library())
         if stream is None:
             stream = torch.cuda.current_stream()
         self._torch_stream = stream
-        o = _opts(width, height, disorder_hint, None, stream)
+        o = _opts(width, height, disorder_hint, None, stream, flags)
         h = ctypes.c_void_p()
         _check(self._lib.hc_stream_create(ctypes.byref(o), int(dt), int(max_disorder_ticks), ctypes.byref(h)))
         self._h = h

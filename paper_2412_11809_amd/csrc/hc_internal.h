@@ -15,6 +15,7 @@ namespace hc {
 constexpr int kSortThreads = 512;     // threads of the tile-sort / merge kernels
 constexpr int kLinkTile = 1024;       // sorted hits per link work-group
 constexpr int kLinkHaloCap = 1024;    // earlier hits a link work-group can hold
+constexpr uint32_t kLinkWindowMaxDim = 16384;  // window scan: coordinates fit 14 bits
 constexpr int kLinkThreads = 512;
 
 
@@ -102,6 +103,7 @@ struct Work {
     uint32_t width, height;
     uint64_t dt;
     int32_t xcd_map;         // 1: contiguous tile ranges per XCD, 0: round-robin
+    int32_t link_mode;       // 0: time-window scan, 1: pixel index (bitmap + CSR)
     int32_t n_seg;           // 1: one chunk, tile ranges computed arithmetically
     SegInfo* segs;           // n_seg > 1: chunk table
     int32_t* tile_seg[4];    // n_seg > 1: chunk of every tile, per kind

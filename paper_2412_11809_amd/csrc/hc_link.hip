@@ -29,6 +29,13 @@
 
 namespace hc {
 
+// Which neighbour search launch_link runs (the pixel index needs its bitmap
+// in LDS; the window scan needs coordinates below 2^14).
+__host__ __device__ inline bool link_uses_pixel_index(const Work& w)
+{
+    return w.link_mode != 0 || w.width > kLinkWindowMaxDim || w.height > kLinkWindowMaxDim;
+}
+
 // First halo position of every link tile: the earliest sorted position p
 // with toa(p) >= toa(p0) - dt (a suffix of the positions before p0, so a
 // binary search), or -1 when the halo exceeds kLinkHaloCap, the tile's ToA
@@ -51,7 +58,7 @@ __global__ void k_link_halo(Work w)
     }
     bool overflow = (a == lim && lim > tr.seg_start && w.s_toa[lim - 1] >= lo);
     overflow |= (w.s_toa[p1 - 1] - w.s_toa[a]) > 0xFFFFFFFFull;
-    overflow |= (uint64_t)w.width * w.height > kLinkMaxPixels;  // no room for the pixel bitmap
+    overflow |= link_uses_pixel_index(w) && (uint64_t)w.width * w.height > kLinkMaxPixels;  // no room for its bitmap
     w.link_h0[k] = overflow ? -1 : (int32_t)a;
 }
 
@@ -60,6 +67,74 @@ hipError_t launch_link_halo(const Work& w, hipStream_t s)
     TimedLaunch tl("link_halo", s);
     hipLaunchKernelGGL(k_link_halo, dim3((w.n_link_tiles + 255) / 256), dim3(256), 0, s, w);
     return hipGetLastError();
+}
+
+// Joins of one tile (cand: per tile hit, the slot joined at each of its 9
+// pixels, or -1) applied in bulk rounds in the LDS forest l_par: hook every
+// edge's larger root under the smaller (atomic minimum), then jump pointers
+// until every tree is a star; repeat until no edge joins two roots.  Then the
+// smallest input index of every local tree is published: as the parent of
+// the tree's tile hits, and as cross-tile edges for its halo hits.
+// minidx: LDS scratch of L words (the caller's ToA array, no longer read).
+template <int PER, int LPER>
+__device__ inline void link_union_publish(const Work& w, int32_t* l_par, int (&cand)[PER][9],
+                                          const int32_t (&ids)[LPER], int hl, int L, int32_t* minidx)
+{
+    const int t = threadIdx.x;
+    while (true) {
+        bool changed = false;
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int i = hl + t + q * kLinkThreads;
+            if (i >= L) continue;
+            const int pi = l_par[i];
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                if (cand[q][k] < 0) continue;
+                const int pc = l_par[cand[q][k]];
+                if (pc != pi) {
+                    atomicMin(&l_par[pc > pi ? pc : pi], pc > pi ? pi : pc);
+                    changed = true;
+                }
+            }
+        }
+        __syncthreads();
+        for (int x = t; x < L; x += kLinkThreads) {
+            int p = l_par[x];
+            while (true) {
+                const int g = l_par[p];
+                if (g == p) break;
+                p = g;
+            }
+            l_par[x] = p;
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+
+    // ---- smallest input index per local tree, then publish
+    for (int i = t; i < L; i += kLinkThreads) minidx[i] = 0x7FFFFFFF;
+    __syncthreads();
+    int32_t root[LPER];
+#pragma unroll
+    for (int q = 0; q < LPER; q++) {
+        const int i = t + q * kLinkThreads;
+        root[q] = i < L ? l_par[i] : -1;
+        if (root[q] >= 0) atomicMin(&minidx[root[q]], ids[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < LPER; q++) {
+        const int i = t + q * kLinkThreads;
+        if (i >= L) continue;
+        const int32_t m = minidx[root[q]];
+        if (i >= hl) {
+            w.gparent[ids[q]] = m;
+        } else if (ids[q] != m) {
+            const int e = atomicAdd(&w.status->n_edges, 1);
+            if (e < w.edge_cap) w.edges[e] = make_int2(ids[q], m);
+            else atomicOr(&w.status->err_internal, 1);
+        }
+    }
 }
 
 // One work-group per tile of kLinkTile sorted hits (+ halo), all in LDS.
@@ -279,72 +354,126 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         }
     }
 
-    // ---- union-find in bulk rounds: hook every edge's larger root under the
-    // smaller (atomic minimum), then jump pointers until every tree is a
-    // star; repeat until no edge joins two different roots
-    while (true) {
-        bool changed = false;
-#pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const int i = hl + t + q * kLinkThreads;
-            if (i >= L) continue;
-            const int pi = l_par[i];
-#pragma unroll
-            for (int k = 0; k < 9; k++) {
-                if (cand[q][k] < 0) continue;
-                const int pc = l_par[cand[q][k]];
-                if (pc != pi) {
-                    atomicMin(&l_par[pc > pi ? pc : pi], pc > pi ? pi : pc);
-                    changed = true;
-                }
-            }
-        }
-        __syncthreads();
-        for (int x = t; x < L; x += kLinkThreads) {
-            int p = l_par[x];
-            while (true) {
-                const int g = l_par[p];
-                if (g == p) break;
-                p = g;
-            }
-            l_par[x] = p;
-        }
-        if (!__syncthreads_or(changed)) break;
-    }
-
-    // ---- smallest input index per local tree, then publish
-    int32_t* minidx = reinterpret_cast<int32_t*>(l_toa);  // reused: L <= LCAP, ToAs no longer read
-    for (int i = t; i < L; i += kLinkThreads) minidx[i] = 0x7FFFFFFF;
-    __syncthreads();
-    int32_t root[LPER];
-#pragma unroll
-    for (int q = 0; q < LPER; q++) {
-        const int i = t + q * kLinkThreads;
-        root[q] = i < L ? l_par[i] : -1;
-        if (root[q] >= 0) atomicMin(&minidx[root[q]], ids[q]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < LPER; q++) {
-        const int i = t + q * kLinkThreads;
-        if (i >= L) continue;
-        const int32_t m = minidx[root[q]];
-        if (i >= hl) {
-            w.gparent[ids[q]] = m;
-        } else if (ids[q] != m) {
-            const int e = atomicAdd(&w.status->n_edges, 1);
-            if (e < w.edge_cap) w.edges[e] = make_int2(ids[q], m);
-            else atomicOr(&w.status->err_internal, 1);
-        }
-    }
+    link_union_publish(w, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
+// Same contract as k_link, without a pixel index: the latest earlier hit at
+// each neighbour pixel is found by scanning the tile's time window backwards.
+// Every earlier hit within dt of hit i sits in the slots [lo_i, i), because
+// the slots are in (ToA, index) order; walking them from i - 1 down, the first
+// hit met at each of the 9 pixels is the latest one there.  The spatial test
+// is two 16-bit lanes in one 32-bit word: with x and y below 2^14 and guard
+// bit 14 set in both lanes of the earlier hit's word, the difference
+// g_j - (e_i - 0x10001) holds 0x4000 + dx + 1 per lane with no borrow between
+// lanes, so (diff & 0xFFFCFFFC) == 0x40004000 keeps dx, dy in -1..2; dx or dy
+// of 2 (low bits 3) is rejected inside the rarely taken branch.
+// Sparse input gives short windows (a few slots); inside a dense shower the
+// window holds every hit of the last dt.
+__global__ __launch_bounds__(kLinkThreads) void k_link_window(Work w)
+{
+    constexpr int LCAP = kLinkTile + kLinkHaloCap;
+    constexpr int PER = kLinkTile / kLinkThreads;
+    constexpr int LPER = LCAP / kLinkThreads;
+    constexpr uint32_t kGuard = 0x40004000u, kMask = 0xFFFCFFFCu;
+    __shared__ uint32_t l_toa[LCAP];
+    __shared__ uint32_t l_g[LCAP];  // (y << 16 | x) | kGuard
+    __shared__ int32_t l_par[LCAP];
+
+    if (w.status->err_range) return;
+    const int tile = xcd_tile(w.n_link_tiles, w.xcd_map);
+    if (tile < 0) return;
+    const int t = threadIdx.x;
+    const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
+    const int64_t p0 = tr.start;
+    const int64_t p1 = tr.start + tr.count;
+    const int64_t h0 = w.link_h0[tile];
+    if (h0 < 0) {  // halo too large: every hit is its own root here, the fallback joins them
+        for (int64_t p = p0 + t; p < p1; p += kLinkThreads) {
+            const int32_t id = w.s_idx[p];
+            if (id >= 0 && id < w.n) w.gparent[id] = id;
+            else atomicOr(&w.status->err_internal, 1);
+        }
+        if (t == 0) {
+            const int k = atomicAdd(&w.status->n_overflow, 1);
+            w.overflow_tiles[k] = tile;
+        }
+        return;
+    }
+    const int L = (int)(p1 - h0);
+    const int hl = (int)(p0 - h0);
+    const uint64_t tbase = w.s_toa[h0];
+    int32_t ids[LPER];
+#pragma unroll
+    for (int q = 0; q < LPER; q++) {
+        const int i = t + q * kLinkThreads;
+        ids[q] = -1;
+        if (i < L) {
+            const int64_t p = h0 + i;
+            l_toa[i] = (uint32_t)(w.s_toa[p] - tbase);
+            l_g[i] = w.s_xy[p] | kGuard;
+            l_par[i] = i;
+            int32_t id = w.s_idx[p];
+            if (id < 0 || id >= w.n) {
+                atomicOr(&w.status->err_internal, 1);
+                id = 0;
+            }
+            ids[q] = id;
+        }
+    }
+    __syncthreads();
+
+    const uint64_t dt = seg_dt(w, tr.seg);
+    int cand[PER][9];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) cand[q][k] = -1;
+        const int i = hl + t + q * kLinkThreads;
+        if (i >= L) continue;
+        const uint32_t ti = l_toa[i];
+        // first slot of the window: toa >= ti - dt (ToAs ascend with the slot)
+        int lo = 0;
+        if (dt < (uint64_t)ti) {
+            const uint32_t th = ti - (uint32_t)dt;
+            int hi = i;
+            while (lo < hi) {
+                const int m = (lo + hi) >> 1;
+                if (l_toa[m] < th) lo = m + 1; else hi = m;
+            }
+        }
+        const uint32_t c = (l_g[i] & ~kGuard) - 0x00010001u;
+        uint32_t found = 0;
+        for (int j = i - 1; j >= lo; j--) {
+            const uint32_t r = l_g[j] - c;
+            if ((r & kMask) == kGuard) {
+                const uint32_t ax = r & 3u, ay = (r >> 16) & 3u;
+                if (ax == 3u || ay == 3u) continue;
+                const int dir = (int)(ay * 3u + ax);
+                if ((found >> dir) & 1u) continue;
+                found |= 1u << dir;
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    if (k == dir) cand[q][k] = j;
+                if (found == 0x1FFu) break;
+            }
+        }
+    }
+    link_union_publish(w, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
+}
+
+// Window scan unless the sensor is too wide for the 16-bit lanes (or the
+// pixel-index kernel was chosen).
 hipError_t launch_link(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("link", s);
-    const int bm_words = link_bitmap_words(w.width, w.height);
-    const size_t dyn = (size_t)bm_words * 4 + (((size_t)bm_words * 2 + 3) & ~(size_t)3);
-    hipLaunchKernelGGL(k_link, dim3(xcd_grid(w.n_link_tiles)), dim3(kLinkThreads), dyn, s, w, bm_words);
+    const dim3 grid(xcd_grid(w.n_link_tiles));
+    if (!link_uses_pixel_index(w)) {
+        hipLaunchKernelGGL(k_link_window, grid, dim3(kLinkThreads), 0, s, w);
+    } else {
+        const int bm_words = link_bitmap_words(w.width, w.height);
+        const size_t dyn = (size_t)bm_words * 4 + (((size_t)bm_words * 2 + 3) & ~(size_t)3);
+        hipLaunchKernelGGL(k_link, grid, dim3(kLinkThreads), dyn, s, w, bm_words);
+    }
     return hipGetLastError();
 }
 

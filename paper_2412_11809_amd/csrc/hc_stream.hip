@@ -196,6 +196,7 @@ struct ChunkHost {
 struct hc_stream {
     hipStream_t s = nullptr;
     uint32_t W = 256, H = 256, D = 4096;
+    int32_t link_mode = 0;
     uint64_t dt = 0, tdis = 0;
     // open buffer (ping-pong) and per-push scratch, capacity `cap` hits
     int64_t cap = 0;
@@ -362,6 +363,7 @@ static int process(hc_stream* st, int64_t n_all, uint64_t wmark, int flush)
     Work w;
     plan_workspace(n_all, st->W, st->H, sort_hint(st, st->n_open), &w, (char*)st->ws);
     w.dt = st->dt;
+    w.link_mode = st->link_mode;
     int rc = enqueue_cluster(st->buf[st->cur], w, st->lab, st->feats, &st->sd->n_clusters, st->s);
     if (rc != HC_OK) return rc;
     const int blocks = (n + 255) / 256;
@@ -454,7 +456,8 @@ int hc_stream_create(const hc_opts* opts, uint64_t dt, uint64_t max_disorder_tic
     st->s = opts ? (hipStream_t)opts->stream : nullptr;
     st->dt = dt;
     st->tdis = max_disorder_ticks;
-    if (st->W > 65535 || st->H > 65535 || (opts && opts->flags)) {
+    st->link_mode = opts && (opts->flags & HC_FLAG_LINK_PIXEL_INDEX) ? 1 : 0;
+    if (st->W > 65535 || st->H > 65535 || (opts && (opts->flags & ~HC_FLAG_LINK_PIXEL_INDEX))) {
         delete st;
         return set_error(HC_ERR_ARG, "bad stream options");
     }

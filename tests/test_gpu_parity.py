@@ -23,19 +23,19 @@ def hc():
     return hc
 
 
-def run_gpu(hc, hits, w, h, dt, hint=0, features=True, stream=None, workspace=None):
+def run_gpu(hc, hits, w, h, dt, hint=0, features=True, stream=None, workspace=None, flags=0):
     import torch
-    print("case: n=%d %dx%d dt=%d hint=%d" % (hits.size, w, h, dt, hint), flush=True)
+    print("case: n=%d %dx%d dt=%d hint=%d flags=%d" % (hits.size, w, h, dt, hint, flags), flush=True)
     d = hc.hits_to_device(hits)
     labels, feats, k = hc.cluster(d, dt, w, h, disorder_hint=hint, features=features, stream=stream,
-                                  workspace=workspace)
+                                  workspace=workspace, flags=flags)
     torch.cuda.synchronize()
     kk = int(k.item())
     return labels.cpu().numpy(), (hc.features_to_numpy(feats, kk) if features else None), kk
 
 
-def assert_parity(hc, hits, w, h, dt, hint=0):
-    got_l, got_f, k = run_gpu(hc, hits, w, h, dt, hint)
+def assert_parity(hc, hits, w, h, dt, hint=0, flags=0):
+    got_l, got_f, k = run_gpu(hc, hits, w, h, dt, hint, flags=flags)
     want_l, want_f = oracle.cluster(hits, w, h, dt)
     assert k == want_f.size, "cluster count %d, oracle %d" % (k, want_f.size)
     bad = np.nonzero(got_l != want_l)[0]
@@ -188,3 +188,45 @@ def test_config2_full_size(hc):
     hits, p = hitgen.config2()
     got = assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
     assert (got <= np.arange(got.size)).all()
+
+
+# ---- the pixel-index neighbour search (HC_FLAG_LINK_PIXEL_INDEX) on the
+# same inputs, and sensors at and beyond the window scan's 14-bit limit
+@pytest.mark.parametrize("case", ["config1", "config2", "single_pixel", "dense", "timepix4", "same_toa"])
+def test_pixel_index_variant(hc, case):
+    flag = hc.HC_FLAG_LINK_PIXEL_INDEX
+    if case == "config1":
+        hits, p = hitgen.config1()
+        assert_parity(hc, hits, 256, 256, p["dt"], p["disorder"], flags=flag)
+    elif case == "config2":
+        hits, p = hitgen.config2(n=1_000_000, seed=98)
+        assert_parity(hc, hits, 256, 256, p["dt"], p["disorder"], flags=flag)
+    elif case == "single_pixel":
+        rng = np.random.default_rng(20)
+        hits = np.zeros(30_000, dtype=oracle.HIT_DTYPE)
+        hits["x"], hits["y"] = 255, 0
+        hits["toa"] = np.sort(rng.integers(0, 3_000_000, hits.size))
+        assert_parity(hc, hits, 256, 256, 128, 512, flags=flag)
+    elif case == "dense":
+        hits = hitgen.uniform_hits(100_000, 21, 8, 8, 2_000_000, disorder=50)
+        assert_parity(hc, hits, 8, 8, 30, 64, flags=flag)
+    elif case == "timepix4":
+        hits, p = hitgen.config4(n=1_000_000, seed=22)
+        assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"], flags=flag)
+    else:
+        hits = hitgen.uniform_hits(20_000, 23, 100, 100, 1)
+        assert_parity(hc, hits, 100, 100, 5, 512, flags=flag)
+
+
+@pytest.mark.parametrize("w,h", [(16384, 8), (8, 16384), (16385, 3), (3, 40000)])
+def test_large_sensor_coordinates(hc, w, h):
+    # clusters at the far corners: window scan up to 16384, pixel index beyond
+    rng = np.random.default_rng(w + h)
+    n = 40_000
+    hits = np.zeros(n, dtype=oracle.HIT_DTYPE)
+    cx = rng.choice([0, 1, w - 2, w - 1], n)
+    cy = rng.choice([0, 1, h - 2, h - 1], n)
+    hits["x"], hits["y"] = cx, cy
+    hits["toa"] = np.sort(rng.integers(0, 4_000_000, n))
+    hits["tot"] = rng.integers(1, 100, n)
+    assert_parity(hc, hits, w, h, 100, 512)

@@ -66,3 +66,102 @@ def test_tiled_latest_hit_rule_matches_oracle(case):
     want, _ = oracle.cluster(hits, w, h, dt)
     got = tiled_rule_labels(hits, w, h, dt, tile=64)
     assert (got == want).all()
+
+
+# ---- the time-window form of the same rule (the default link kernel)
+GUARD, MASK = np.uint32(0x40004000), np.uint32(0xFFFCFFFC)
+
+
+def swar_adjacent(gx, gy, ix, iy):
+    """The kernel's two-lane test: returns (adjacent, direction 0..8) for
+    earlier hit (gx, gy) and hit (ix, iy), coordinates below 2^14."""
+    g = (np.uint32(gy) << np.uint32(16) | np.uint32(gx)) | GUARD
+    c = np.uint32((int(iy) << 16 | int(ix)) - 0x00010001 & 0xFFFFFFFF)
+    r = np.uint32((int(g) - int(c)) & 0xFFFFFFFF)
+    if (r & MASK) != GUARD:
+        return False, -1
+    ax, ay = int(r & 3), int((r >> 16) & 3)
+    if ax == 3 or ay == 3:
+        return False, -1
+    return True, ay * 3 + ax
+
+
+def test_swar_adjacency_predicate():
+    rng = np.random.default_rng(5)
+    pts = [(0, 0), (16383, 16383), (0, 16383), (16383, 0), (1, 1)] + \
+          [tuple(rng.integers(0, 16384, 2)) for _ in range(200)]
+    for ix, iy in pts:
+        for dy in range(-3, 4):
+            for dx in range(-3, 4):
+                gx, gy = ix + dx, iy + dy
+                if not (0 <= gx < 16384 and 0 <= gy < 16384):
+                    continue
+                adj, d = swar_adjacent(gx, gy, ix, iy)
+                assert adj == (abs(dx) <= 1 and abs(dy) <= 1), (ix, iy, dx, dy)
+                if adj:
+                    assert d == (dy + 1) * 3 + (dx + 1)
+    # far apart in both lanes, including differences that would borrow
+    for _ in range(2000):
+        ix, iy, gx, gy = rng.integers(0, 16384, 4)
+        adj, _ = swar_adjacent(gx, gy, ix, iy)
+        assert adj == (abs(int(gx) - int(ix)) <= 1 and abs(int(gy) - int(iy)) <= 1)
+
+
+def window_rule_labels(hits, width, height, dt, tile=64):
+    n = hits.size
+    order = np.lexsort((np.arange(n), hits["toa"]))
+    toa = hits["toa"][order].astype(np.uint64)
+    x = hits["x"][order].astype(np.int64)
+    y = hits["y"][order].astype(np.int64)
+    g_all = ((y << 16) | x).astype(np.uint64) | np.uint64(0x40004000)
+    parent = list(range(n))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for p0 in range(0, n, tile):
+        p1 = min(n, p0 + tile)
+        lo0 = int(toa[p0]) - dt if int(toa[p0]) > dt else 0
+        h0 = int(np.searchsorted(toa[:p0], np.uint64(lo0), side="left"))
+        for i in range(p0, p1):
+            lo_t = int(toa[i]) - dt if int(toa[i]) > dt else 0
+            lo = h0 + int(np.searchsorted(toa[h0:i], np.uint64(lo_t), side="left"))
+            if lo >= i:
+                continue
+            c = (int((y[i] << 16) | x[i]) - 0x00010001) & 0xFFFFFFFF
+            r = ((g_all[lo:i] - np.uint64(c)) & np.uint64(0xFFFFFFFF))[::-1]  # j = i-1 down to lo
+            ok = (r & np.uint64(0xFFFCFFFC)) == np.uint64(0x40004000)
+            ax, ay = r & np.uint64(3), (r >> np.uint64(16)) & np.uint64(3)
+            ok &= (ax != 3) & (ay != 3)
+            seen = set()
+            for k in np.nonzero(ok)[0]:
+                d = int(ay[k]) * 3 + int(ax[k])
+                if d in seen:
+                    continue
+                seen.add(d)
+                j = i - 1 - int(k)
+                ra, rb = find(j), find(i)
+                if ra != rb:
+                    parent[max(ra, rb)] = min(ra, rb)
+    lab = np.empty(n, dtype=np.int64)
+    lab[order] = [find(i) for i in range(n)]
+    return canonical(lab)
+
+
+@pytest.mark.parametrize("case", ["blobs", "mixed", "dense"])
+def test_window_rule_matches_oracle(case):
+    if case == "blobs":
+        hits, p = hitgen.config1(n=20_000, seed=41)
+        w, h, dt = 256, 256, p["dt"]
+    elif case == "mixed":
+        hits, p = hitgen.config2(n=30_000, seed=42)
+        w, h, dt = 256, 256, p["dt"]
+    else:
+        hits = hitgen.uniform_hits(5_000, 43, 12, 12, 20_000, disorder=40)
+        w, h, dt = 12, 12, 25
+    want, _ = oracle.cluster(hits, w, h, dt)
+    got = window_rule_labels(hits, w, h, dt, tile=64)
+    assert (got == want).all()
