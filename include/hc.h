@@ -75,7 +75,7 @@ typedef struct {
                                 partial orderliness, Section 3.1).  A tuning
                                 hint only: wrong values cost speed, never
                                 exactness. 0 = 4096. */
-    uint32_t flags;          /* 0, or HC_FLAG_LINK_PIXEL_INDEX */
+    uint32_t flags;          /* 0, or one HC_FLAG_LINK_* value */
     void* workspace;         /* device scratch of >= hc_workspace_size bytes,
                                 or NULL: the library then keeps a cached
                                 per-device buffer (grown with hipMalloc) */
@@ -83,10 +83,14 @@ typedef struct {
     void* stream;            /* hipStream_t to run on; NULL = null stream */
 } hc_opts;
 
-/* Neighbour search variant (same results): by default each hit scans the
- * earlier hits of its dt window (sensors up to 16384 x 16384); with this flag
- * every tile builds a pixel index (occupancy bitmap + per-pixel lists). */
+/* Neighbour search variant (results are identical).  By default each tile
+ * picks by its hits' dt windows: short windows are scanned backwards, long
+ * ones (dense showers) go through a pixel index (occupancy bitmap + per-pixel
+ * lists).  The flags force one of the two for every tile.  The window scan
+ * needs sensors up to 16384 x 16384, the pixel index one of at most
+ * 448 x 512 pixels' worth of bitmap (larger sensors take a slower path). */
 #define HC_FLAG_LINK_PIXEL_INDEX 1u
+#define HC_FLAG_LINK_WINDOW 2u
 
 enum {
     HC_OK = 0,

@@ -76,6 +76,7 @@ def load_library(path=LIB_PATH):
 
 
 HC_FLAG_LINK_PIXEL_INDEX = 1
+HC_FLAG_LINK_WINDOW = 2
 
 
 def _opts(width, height, disorder_hint, workspace, stream, flags=0):
@@ -358,14 +359,14 @@ def hc_batch_workspace_size(offsets, plan=None, width=256, height=256, disorder_
 
 
 def hc_cluster_batch(hits, offsets, dts, labels, features, n_clusters, plan=None, width=256, height=256,
-                     disorder_hint=0, workspace=None, stream=None):
+                     disorder_hint=0, workspace=None, stream=None, flags=0):
     """Direct call of hc_cluster_batch on device tensors; offsets/dts are host arrays."""
     import torch
     lib = _bind_batch(load_library())
     offsets, dts, n_chunks = _batch_tables(offsets, dts)
     if stream is None:
         stream = torch.cuda.current_stream(hits.device)
-    o = _opts(width, height, disorder_hint, workspace, stream)
+    o = _opts(width, height, disorder_hint, workspace, stream, flags)
     _check(lib.hc_cluster_batch(_ptr(hits), offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_chunks,
                                 dts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _ptr(labels),
                                 _ptr(features), _ptr(n_clusters), _plan_ptr(plan), ctypes.byref(o)))

@@ -298,7 +298,7 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_f
     const uint32_t W = opts && opts->width ? opts->width : 256;
     const uint32_t H = opts && opts->height ? opts->height : 256;
     if (W > 65535 || H > 65535) return fail(HC_ERR_ARG, "sensor dimensions must be 1..65535");
-    if (opts && (opts->flags & ~HC_FLAG_LINK_PIXEL_INDEX)) return fail(HC_ERR_ARG, "unknown flags");
+    if (opts && !link_flags_valid(opts->flags)) return fail(HC_ERR_ARG, "unknown flags");
     hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
     hipError_t e;
     if (n == 0) {
@@ -319,7 +319,7 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_f
     }
     plan_workspace(n, W, H, D, &w, (char*)ws);
     w.dt = dt;
-    w.link_mode = opts && (opts->flags & HC_FLAG_LINK_PIXEL_INDEX) ? 1 : 0;
+    w.link_mode = link_mode_of(opts);
 
     return enqueue_cluster(hits, w, labels, features, n_clusters, s);
 }

@@ -46,7 +46,7 @@ using namespace hc;
 struct hc_batch_plan {
     uint32_t disorder_hint;
     int32_t xcd_map;
-    int32_t link_mode;  // 0: time-window scan, 1: pixel index
+    int32_t link_mode;  // 0: per tile by window length, 1: pixel index, 2: window scan
     double time_ms;
 };
 
@@ -97,13 +97,13 @@ int plan_batch(const int64_t* offsets, int32_t n_chunks, const uint64_t* dts, co
 {
     const uint32_t W = opts && opts->width ? opts->width : 256;
     const uint32_t H = opts && opts->height ? opts->height : 256;
-    if (W > 65535 || H > 65535 || (opts && (opts->flags & ~HC_FLAG_LINK_PIXEL_INDEX)))
+    if (W > 65535 || H > 65535 || (opts && !link_flags_valid(opts->flags)))
         return set_error(HC_ERR_ARG, "bad options");
     segs = make_segs(offsets, n_chunks, dts);
     *bytes = plan_workspace(offsets[n_chunks], W, H, plan_hint(plan, opts), w, base, segs.data(), n_chunks);
     if (w) {
         w->xcd_map = plan ? plan->xcd_map : 1;
-        w->link_mode = plan ? plan->link_mode : (opts && (opts->flags & HC_FLAG_LINK_PIXEL_INDEX) ? 1 : 0);
+        w->link_mode = plan ? plan->link_mode : (link_mode_of(opts));
         if (n_chunks == 1) w->dt = dts[0];  // a one-chunk batch is the plain path
     }
     return HC_OK;
@@ -189,7 +189,8 @@ int hc_batch_plan_describe(const hc_batch_plan* plan, char* buf, size_t cap)
     if (!plan || !buf || cap == 0) return set_error(HC_ERR_ARG, "NULL plan or buffer");
     const int T = 2 * (int64_t)plan->disorder_hint <= 2048 ? 2048 : 2 * (int64_t)plan->disorder_hint <= 4096 ? 4096 : 8192;
     snprintf(buf, cap, "disorder_hint=%u sort_tile=%d xcd_map=%d link=%s time_ms=%.4f", plan->disorder_hint, T,
-             plan->xcd_map, plan->link_mode ? "index" : "window", plan->time_ms);
+             plan->xcd_map, plan->link_mode == 1 ? "index" : plan->link_mode == 2 ? "window" : "hybrid",
+             plan->time_ms);
     return HC_OK;
 }
 
@@ -258,7 +259,7 @@ int hc_batch_autotune(const hc_hit* hits, const int64_t* offsets, int32_t n_chun
     const uint32_t hints[] = {512, 1024, 2048, 4096, 8192, 16384};
     hc_batch_plan best{0, 0, 0, 1e30};
     for (uint32_t h : hints) {
-        for (int cfg = 0; cfg < 4; cfg++) {
+        for (int cfg = 0; cfg < 6; cfg++) {
             hc_batch_plan cand{h, 1 - (cfg & 1), cfg >> 1, 0.0};
             if ((rc = run(&cand)) != HC_OK) break;  // warm-up (and the parity check below)
             unsigned long long nd = 0;

@@ -16,6 +16,7 @@ constexpr int kSortThreads = 512;     // threads of the tile-sort / merge kernel
 constexpr int kLinkTile = 1024;       // sorted hits per link work-group
 constexpr int kLinkHaloCap = 1024;    // earlier hits a link work-group can hold
 constexpr uint32_t kLinkWindowMaxDim = 16384;  // window scan: coordinates fit 14 bits
+constexpr int kLinkWindowMeanCost = 16;        // a tile scans its windows below this many slots per hit
 constexpr int kLinkThreads = 512;
 
 
@@ -103,7 +104,8 @@ struct Work {
     uint32_t width, height;
     uint64_t dt;
     int32_t xcd_map;         // 1: contiguous tile ranges per XCD, 0: round-robin
-    int32_t link_mode;       // 0: time-window scan, 1: pixel index (bitmap + CSR)
+    int32_t link_mode;       // 0: per tile, window scan or pixel index by window length;
+                             // 1: pixel index (bitmap + CSR) only; 2: window scan only
     int32_t n_seg;           // 1: one chunk, tile ranges computed arithmetically
     SegInfo* segs;           // n_seg > 1: chunk table
     int32_t* tile_seg[4];    // n_seg > 1: chunk of every tile, per kind
@@ -172,6 +174,16 @@ int enqueue_cluster(const hc_hit* hits, const Work& w, int32_t* labels, hc_featu
                     int32_t* n_clusters, hipStream_t s);
 // Record an error for hc_last_error and return its code.
 int set_error(int code, const std::string& msg);
+// hc_opts.flags: at most one HC_FLAG_LINK_* value; the Work.link_mode it selects.
+inline bool link_flags_valid(uint32_t f)
+{
+    return f == 0 || f == HC_FLAG_LINK_PIXEL_INDEX || f == HC_FLAG_LINK_WINDOW;
+}
+inline int32_t link_mode_of(const hc_opts* o)
+{
+    if (!o) return 0;
+    return o->flags == HC_FLAG_LINK_PIXEL_INDEX ? 1 : o->flags == HC_FLAG_LINK_WINDOW ? 2 : 0;
+}
 // Cached per-device workspace for callers that pass none (grown on demand).
 int cached_workspace(size_t need, void** out);
 // Switch per-kernel event timing on or off; returns the previous state.

@@ -29,11 +29,18 @@
 
 namespace hc {
 
-// Which neighbour search launch_link runs (the pixel index needs its bitmap
-// in LDS; the window scan needs coordinates below 2^14).
-__host__ __device__ inline bool link_uses_pixel_index(const Work& w)
+// Which neighbour search runs: 0 = window scan only (k_link_window),
+// 1 = per tile, window scan or pixel index (k_link), 2 = pixel index only
+// (k_link).  The window scan needs coordinates below 2^14, the pixel index
+// room for the sensor's occupancy bitmap in LDS.
+enum { kLinkWindowOnly = 0, kLinkHybrid = 1, kLinkIndexOnly = 2 };
+__host__ __device__ inline int link_kernel(const Work& w)
 {
-    return w.link_mode != 0 || w.width > kLinkWindowMaxDim || w.height > kLinkWindowMaxDim;
+    const bool win_ok = w.width <= kLinkWindowMaxDim && w.height <= kLinkWindowMaxDim;
+    const bool idx_ok = (uint64_t)w.width * w.height <= kLinkMaxPixels;
+    if (w.link_mode == 1 || !win_ok) return kLinkIndexOnly;
+    if (w.link_mode == 2 || !idx_ok) return kLinkWindowOnly;
+    return kLinkHybrid;
 }
 
 // First halo position of every link tile: the earliest sorted position p
@@ -58,7 +65,7 @@ __global__ void k_link_halo(Work w)
     }
     bool overflow = (a == lim && lim > tr.seg_start && w.s_toa[lim - 1] >= lo);
     overflow |= (w.s_toa[p1 - 1] - w.s_toa[a]) > 0xFFFFFFFFull;
-    overflow |= link_uses_pixel_index(w) && (uint64_t)w.width * w.height > kLinkMaxPixels;  // no room for its bitmap
+    overflow |= link_kernel(w) != kLinkWindowOnly && (uint64_t)w.width * w.height > kLinkMaxPixels;  // no bitmap room
     w.link_h0[k] = overflow ? -1 : (int32_t)a;
 }
 
@@ -137,6 +144,42 @@ __device__ inline void link_union_publish(const Work& w, int32_t* l_par, int (&c
     }
 }
 
+// Window scan of the tile hits (see k_link_window): for tile hit i, the
+// earlier slots [lo[q], i) hold every earlier hit within dt; walking them
+// backwards, the first hit met at each of the 9 pixels is the latest there.
+// l_xy: packed (y << 16 | x), both below 2^14.
+template <int PER>
+__device__ inline void link_window_search(const uint32_t* l_toa, const uint32_t* l_xy, int hl, int L,
+                                          const int (&lo)[PER], int (&cand)[PER][9])
+{
+    constexpr uint32_t kGuard = 0x40004000u, kMask = 0xFFFCFFFCu;
+    const int t = threadIdx.x;
+    (void)l_toa;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) cand[q][k] = -1;
+        const int i = hl + t + q * kLinkThreads;
+        if (i >= L) continue;
+        const uint32_t c = l_xy[i] - 0x00010001u;
+        uint32_t found = 0;
+        for (int j = i - 1; j >= lo[q]; j--) {
+            const uint32_t r = (l_xy[j] | kGuard) - c;
+            if ((r & kMask) == kGuard) {
+                const uint32_t ax = r & 3u, ay = (r >> 16) & 3u;
+                if (ax == 3u || ay == 3u) continue;
+                const int dir = (int)(ay * 3u + ax);
+                if ((found >> dir) & 1u) continue;
+                found |= 1u << dir;
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    if (k == dir) cand[q][k] = j;
+                if (found == 0x1FFu) break;
+            }
+        }
+    }
+}
+
 // One work-group per tile of kLinkTile sorted hits (+ halo), all in LDS.
 //
 // Local slots 0..L-1 are the sorted positions h0..p1-1, so a smaller slot is
@@ -173,6 +216,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
     __shared__ uint16_t csr[LCAP];        // slots grouped by pixel rank
     __shared__ uint16_t pstart[LCAP + 2]; // count (packed in pairs), then first CSR position per pixel rank [| kUnsorted]
     __shared__ uint32_t wsum[kLinkThreads / kWave];
+    __shared__ uint32_t s_cost;
     extern __shared__ uint32_t dyn[];
     uint32_t* bm = dyn;
     uint16_t* wpre = reinterpret_cast<uint16_t*>(dyn + bm_words);
@@ -220,6 +264,48 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
             ids[q] = id;
         }
     }
+    if (t == 0) s_cost = 0u;
+    __syncthreads();
+
+    // ---- the dt window of every tile hit (slots [lo, i)) and what scanning
+    // the windows would cost: per wave, the longest window of each step
+    const uint64_t dt = seg_dt(w, tr.seg);
+    const int lane = t & (kWave - 1);
+    int lo[PER];
+    uint32_t cost = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = hl + t + q * kLinkThreads;
+        lo[q] = i;
+        if (i < L) {
+            const uint32_t ti = l_toa[i];
+            int a = 0;
+            if (dt < (uint64_t)ti) {
+                const uint32_t th = ti - (uint32_t)dt;
+                int b = i;
+                while (a < b) {
+                    const int m = (a + b) >> 1;
+                    if (l_toa[m] < th) a = m + 1; else b = m;
+                }
+            }
+            lo[q] = a;
+        }
+        uint32_t win = (uint32_t)(i < L ? i - lo[q] : 0);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t v = __shfl_xor(win, o, kWave);
+            win = v > win ? v : win;
+        }
+        cost += win;
+    }
+    if (lane == 0) atomicAdd(&s_cost, cost * kWave);
+    __syncthreads();
+    // short windows (sparse hits): scan them; long ones (showers): pixel index
+    const bool window = link_kernel(w) == kLinkHybrid && s_cost <= (uint32_t)(kLinkWindowMeanCost * (L - hl));
+    int cand[PER][9];
+    if (window) {
+        link_window_search<PER>(l_toa, l_xy, hl, L, lo, cand);
+    } else {
     for (int i = t; i < bm_words; i += kLinkThreads) bm[i] = 0u;
     for (int i = t; i < (LCAP + 2) / 2; i += kLinkThreads) pcount[i] = 0u;
     __syncthreads();
@@ -301,9 +387,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
     __syncthreads();
 
     // ---- neighbour search: latest earlier hit per neighbour pixel
-    const uint64_t dt = seg_dt(w, tr.seg);
     const int H = (int)w.height;
-    int cand[PER][9];
 #pragma unroll
     for (int q = 0; q < PER; q++) {
 #pragma unroll
@@ -354,6 +438,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         }
     }
 
+    }  // pixel index
     link_union_publish(w, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
@@ -374,9 +459,8 @@ __global__ __launch_bounds__(kLinkThreads) void k_link_window(Work w)
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
     constexpr int PER = kLinkTile / kLinkThreads;
     constexpr int LPER = LCAP / kLinkThreads;
-    constexpr uint32_t kGuard = 0x40004000u, kMask = 0xFFFCFFFCu;
     __shared__ uint32_t l_toa[LCAP];
-    __shared__ uint32_t l_g[LCAP];  // (y << 16 | x) | kGuard
+    __shared__ uint32_t l_xy[LCAP];
     __shared__ int32_t l_par[LCAP];
 
     if (w.status->err_range) return;
@@ -410,7 +494,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link_window(Work w)
         if (i < L) {
             const int64_t p = h0 + i;
             l_toa[i] = (uint32_t)(w.s_toa[p] - tbase);
-            l_g[i] = w.s_xy[p] | kGuard;
+            l_xy[i] = w.s_xy[p];
             l_par[i] = i;
             int32_t id = w.s_idx[p];
             if (id < 0 || id >= w.n) {
@@ -423,51 +507,35 @@ __global__ __launch_bounds__(kLinkThreads) void k_link_window(Work w)
     __syncthreads();
 
     const uint64_t dt = seg_dt(w, tr.seg);
-    int cand[PER][9];
+    int lo[PER];
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) cand[q][k] = -1;
         const int i = hl + t + q * kLinkThreads;
+        lo[q] = i;
         if (i >= L) continue;
         const uint32_t ti = l_toa[i];
-        // first slot of the window: toa >= ti - dt (ToAs ascend with the slot)
-        int lo = 0;
-        if (dt < (uint64_t)ti) {
+        int a = 0;
+        if (dt < (uint64_t)ti) {  // first slot with toa >= ti - dt (ToAs ascend with the slot)
             const uint32_t th = ti - (uint32_t)dt;
-            int hi = i;
-            while (lo < hi) {
-                const int m = (lo + hi) >> 1;
-                if (l_toa[m] < th) lo = m + 1; else hi = m;
+            int b = i;
+            while (a < b) {
+                const int m = (a + b) >> 1;
+                if (l_toa[m] < th) a = m + 1; else b = m;
             }
         }
-        const uint32_t c = (l_g[i] & ~kGuard) - 0x00010001u;
-        uint32_t found = 0;
-        for (int j = i - 1; j >= lo; j--) {
-            const uint32_t r = l_g[j] - c;
-            if ((r & kMask) == kGuard) {
-                const uint32_t ax = r & 3u, ay = (r >> 16) & 3u;
-                if (ax == 3u || ay == 3u) continue;
-                const int dir = (int)(ay * 3u + ax);
-                if ((found >> dir) & 1u) continue;
-                found |= 1u << dir;
-#pragma unroll
-                for (int k = 0; k < 9; k++)
-                    if (k == dir) cand[q][k] = j;
-                if (found == 0x1FFu) break;
-            }
-        }
+        lo[q] = a;
     }
+    int cand[PER][9];
+    link_window_search<PER>(l_toa, l_xy, hl, L, lo, cand);
     link_union_publish(w, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
-// Window scan unless the sensor is too wide for the 16-bit lanes (or the
-// pixel-index kernel was chosen).
+// The window-scan kernel, or the per-tile hybrid / pixel-index kernel.
 hipError_t launch_link(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("link", s);
     const dim3 grid(xcd_grid(w.n_link_tiles));
-    if (!link_uses_pixel_index(w)) {
+    if (link_kernel(w) == kLinkWindowOnly) {
         hipLaunchKernelGGL(k_link_window, grid, dim3(kLinkThreads), 0, s, w);
     } else {
         const int bm_words = link_bitmap_words(w.width, w.height);

@@ -75,15 +75,29 @@ __global__ void k_stream_close_hits(int n_all, const int32_t* __restrict__ lab, 
                                     ChunkRec* chunks, uint64_t wmark, uint64_t dt, int flush, uint8_t* keep)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_all) return;
-    const int32_t r = lab[i];
-    const bool closed = flush || sat_add_u64(slots[r].toa_max, dt) <= wmark;
-    if (closed) {
-        ChunkRec* ch = chunks + cslot[i];
-        ch->labels[gidx[i] - ch->base] = gidx[r];
-        atomicSub(&ch->open, 1);
+    const int lane = threadIdx.x & (kWave - 1);
+    bool closed = false;
+    int32_t slot = -1;
+    if (i < n_all) {
+        const int32_t r = lab[i];
+        closed = flush || sat_add_u64(slots[r].toa_max, dt) <= wmark;
+        if (closed) {
+            slot = cslot[i];
+            ChunkRec* ch = chunks + slot;
+            ch->labels[gidx[i] - ch->base] = gidx[r];
+        }
+        keep[i] = closed ? 0 : 1;
     }
-    keep[i] = closed ? 0 : 1;
+    // one decrement per chunk per wave (a wave's hits mostly share a chunk),
+    // not one atomic per hit on the same counter
+    unsigned long long pending = __ballot(closed);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int32_t s = __shfl(slot, leader, kWave);
+        const unsigned long long same = __ballot(closed && slot == s);
+        if (lane == leader) atomicSub(&chunks[s].open, (int32_t)__popcll(same));
+        pending &= ~same;
+    }
 }
 
 // flag[k] = 1 for clusters (feature rows, ascending label) that are closed
@@ -367,6 +381,7 @@ static int process(hc_stream* st, int64_t n_all, uint64_t wmark, int flush)
     int rc = enqueue_cluster(st->buf[st->cur], w, st->lab, st->feats, &st->sd->n_clusters, st->s);
     if (rc != HC_OK) return rc;
     const int blocks = (n + 255) / 256;
+    TimedLaunch tl("stream_close", st->s);  // the closing and compaction kernels below, together
     const int nb = (n + kCmpBlock - 1) / kCmpBlock;
     const int nxt = 1 - st->cur;
     hipLaunchKernelGGL(k_stream_close_hits, dim3(blocks), dim3(256), 0, st->s, n, st->lab, w.slots,
@@ -456,8 +471,8 @@ int hc_stream_create(const hc_opts* opts, uint64_t dt, uint64_t max_disorder_tic
     st->s = opts ? (hipStream_t)opts->stream : nullptr;
     st->dt = dt;
     st->tdis = max_disorder_ticks;
-    st->link_mode = opts && (opts->flags & HC_FLAG_LINK_PIXEL_INDEX) ? 1 : 0;
-    if (st->W > 65535 || st->H > 65535 || (opts && (opts->flags & ~HC_FLAG_LINK_PIXEL_INDEX))) {
+    st->link_mode = link_mode_of(opts);
+    if (st->W > 65535 || st->H > 65535 || (opts && !link_flags_valid(opts->flags))) {
         delete st;
         return set_error(HC_ERR_ARG, "bad stream options");
     }
@@ -509,9 +524,12 @@ int hc_stream_push(hc_stream* st, const hc_hit* hits, int32_t n, int32_t* labels
     ::memset(st->sd_pin, 0, sizeof(StreamDev));
     if ((e = hipMemcpyAsync(st->sd, st->sd_pin, sizeof(StreamDev), hipMemcpyHostToDevice, st->s)) != hipSuccess)
         return set_device_error(e, "stream reset");
-    hipLaunchKernelGGL(k_stream_append, dim3((n + 255) / 256), dim3(256), 0, st->s, hits, n, st->buf[st->cur],
-                       st->gidx[st->cur], st->cslot[st->cur], (int)st->n_open, (int32_t)st->next_g, slot, wmark,
-                       st->has_M ? 1 : 0, st->W, st->H, st->sd);
+    {
+        TimedLaunch tl("stream_append", st->s);
+        hipLaunchKernelGGL(k_stream_append, dim3((n + 255) / 256), dim3(256), 0, st->s, hits, n,
+                           st->buf[st->cur], st->gidx[st->cur], st->cslot[st->cur], (int)st->n_open,
+                           (int32_t)st->next_g, slot, wmark, st->has_M ? 1 : 0, st->W, st->H, st->sd);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return set_device_error(e, "stream append");
     if ((e = hipMemcpyAsync(st->sd_pin, st->sd, sizeof(StreamDev), hipMemcpyDeviceToHost, st->s)) != hipSuccess ||
         (e = hipStreamSynchronize(st->s)) != hipSuccess)

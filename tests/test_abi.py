@@ -60,6 +60,9 @@ def test_argument_errors_are_synchronous(lib):
     o = hc._Opts()
     o.width, o.height = 70000, 10
     assert lib.hc_cluster(None, 5, 10, None, None, ctypes.addressof(k), ctypes.byref(o)) == hc.HC_ERR_ARG
+    o.width, o.height, o.flags = 256, 256, hc.HC_FLAG_LINK_PIXEL_INDEX | hc.HC_FLAG_LINK_WINDOW
+    assert lib.hc_cluster(None, 0, 10, None, None, ctypes.addressof(k), ctypes.byref(o)) == hc.HC_ERR_ARG
+    assert "flags" in hc.hc_last_error()
 
 
 def test_batch_argument_errors_are_synchronous(lib):

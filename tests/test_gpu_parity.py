@@ -190,11 +190,12 @@ def test_config2_full_size(hc):
     assert (got <= np.arange(got.size)).all()
 
 
-# ---- the pixel-index neighbour search (HC_FLAG_LINK_PIXEL_INDEX) on the
-# same inputs, and sensors at and beyond the window scan's 14-bit limit
+# ---- each neighbour search forced on every tile (pixel index, window scan),
+# and sensors at and beyond the window scan's 14-bit limit
 @pytest.mark.parametrize("case", ["config1", "config2", "single_pixel", "dense", "timepix4", "same_toa"])
-def test_pixel_index_variant(hc, case):
-    flag = hc.HC_FLAG_LINK_PIXEL_INDEX
+@pytest.mark.parametrize("variant", ["index", "window"])
+def test_link_variants(hc, case, variant):
+    flag = hc.HC_FLAG_LINK_PIXEL_INDEX if variant == "index" else hc.HC_FLAG_LINK_WINDOW
     if case == "config1":
         hits, p = hitgen.config1()
         assert_parity(hc, hits, 256, 256, p["dt"], p["disorder"], flags=flag)
