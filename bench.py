@@ -374,6 +374,8 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
             "saturated_mhits": round(sat_mhits, 1), "one_stream_at_a_time_mhits": round(seq_mhits, 1),
             "saturated_speedup": round(sat_mhits / seq_mhits, 2),
             "saturated_hbm_peak_bytes": int(sat["hbm_peak"]),
+            "saturated_worker_ms": {k: round(sat[k] / 1e6, 2) for k in ("ns_admit_wait", "ns_push", "ns_drain",
+                                                                       "ns_final")},
             "note": "end-to-end from pinned host memory (H2D hits, D2H labels and closed features)"}
 
 

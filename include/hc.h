@@ -272,6 +272,9 @@ typedef struct {
     int32_t max_slots, peak_slots_in_use;
     /* latency quantiles over all completed chunks, ns */
     uint64_t processing_p50, processing_p99, final_p50, final_p99;
+    /* worker time summed over streams, ns: waiting for admission, copying
+     * hits in and pushing, moving closed clusters out, copying final labels */
+    uint64_t ns_admit_wait, ns_push, ns_drain, ns_final;
 } hc_server_stats;
 
 /* Monotonic clock (ns) for t_arrive stamps. */

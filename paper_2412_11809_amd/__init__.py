@@ -224,8 +224,12 @@ class HcStream:
     def poll(self, cap=1 << 12, closed_cap=1 << 16):
         """All completed tags and closed features (drains in rounds of the caps)."""
         if getattr(self, "_tags", None) is None or self._tags.size < cap or self._feats.size < closed_cap:
+            import torch
             self._tags = np.empty(max(cap, 1), dtype=np.uint64)
-            self._feats = np.empty(max(closed_cap, 1), dtype=FEATURE_DTYPE)
+            # pinned, so the device-to-host copy of closed features is a DMA
+            self._feats_t = torch.empty(max(closed_cap, 1) * FEATURE_DTYPE.itemsize, dtype=torch.uint8,
+                                        pin_memory=True)
+            self._feats = self._feats_t.numpy().view(FEATURE_DTYPE)
         done, feats = [], []
         nd, nc = ctypes.c_int32(), ctypes.c_int32()
         while True:
@@ -437,7 +441,9 @@ class _ServerStats(ctypes.Structure):
                 ("hbm_budget", ctypes.c_uint64), ("hbm_in_use", ctypes.c_uint64), ("hbm_peak", ctypes.c_uint64),
                 ("max_slots", ctypes.c_int32), ("peak_slots_in_use", ctypes.c_int32),
                 ("processing_p50", ctypes.c_uint64), ("processing_p99", ctypes.c_uint64),
-                ("final_p50", ctypes.c_uint64), ("final_p99", ctypes.c_uint64)]
+                ("final_p50", ctypes.c_uint64), ("final_p99", ctypes.c_uint64),
+                ("ns_admit_wait", ctypes.c_uint64), ("ns_push", ctypes.c_uint64), ("ns_drain", ctypes.c_uint64),
+                ("ns_final", ctypes.c_uint64)]
 
 
 def _bind_server(lib):

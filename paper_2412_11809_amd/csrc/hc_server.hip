@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -57,7 +58,9 @@ struct StreamCtx {
     std::thread th;
     std::condition_variable cv;
     std::deque<Req> q;                           // guarded by the server mutex
-    std::vector<hc_features> closed;             // guarded by the server mutex
+    std::mutex cmu;                              // guards closed / closed_head
+    std::deque<std::vector<hc_features>> closed; // closed-cluster features, one block per drain
+    size_t closed_head = 0;                      // rows of closed.front() already handed out
     std::unordered_map<uint64_t, Pending> pend;  // worker-only, keyed by internal sequence number
     uint64_t seq = 0;
     void* hits_dev = nullptr;
@@ -95,6 +98,7 @@ struct hc_server {
     int slots_used = 0, peak_slots = 0;
     int64_t submitted = 0, completed = 0, rejected = 0, hits_completed = 0, queued = 0, pending_final = 0;
     int working = 0;  // requests taken by a worker and not finished
+    std::atomic<uint64_t> ns_admit{0}, ns_push{0}, ns_drain{0}, ns_final{0};
     bool stopping = false;
     std::vector<StreamCtx*> streams;
     std::deque<hc_completion> done;
@@ -148,6 +152,7 @@ void hc_server::finalize(StreamCtx* cx, uint64_t seq)
     if (it == cx->pend.end()) return;
     Pending p = it->second;
     cx->pend.erase(it);
+    const uint64_t f0 = now_ns();
     int status = HC_OK;
     if (p.n > 0) {
         hipError_t e = hipMemcpyAsync(p.labels_host, p.labels_dev, 4 * (size_t)p.n, hipMemcpyDeviceToHost, cx->hs);
@@ -164,6 +169,7 @@ void hc_server::finalize(StreamCtx* cx, uint64_t seq)
     c.t_admit_ns = p.t_admit;
     c.t_processed_ns = p.t_processed;
     c.t_final_ns = now_ns();
+    ns_final += c.t_final_ns - f0;
     std::lock_guard<std::mutex> lk(mu);
     if (p.labels_dev) free_blocks[p.labels_class].push_back(p.labels_dev);
     pending_final--;
@@ -177,9 +183,10 @@ void hc_server::drain(StreamCtx* cx, int32_t* n_closed_out, std::vector<uint64_t
     for (;;) {
         int32_t nd = 0, nc = 0;
         if (hc_stream_poll(cx->st, cx->tags_pin, kDrainTags, &nd, cx->feats_pin, kDrainFeats, &nc) != HC_OK) break;
-        if (nc > 0) {
-            std::lock_guard<std::mutex> lk(mu);
-            cx->closed.insert(cx->closed.end(), cx->feats_pin, cx->feats_pin + nc);
+        if (nc > 0) {  // copied outside any lock; only the hand-over is guarded
+            std::vector<hc_features> blk(cx->feats_pin, cx->feats_pin + nc);
+            std::lock_guard<std::mutex> lk(cx->cmu);
+            cx->closed.push_back(std::move(blk));
         }
         total += nc;
         fin->insert(fin->end(), cx->tags_pin, cx->tags_pin + nd);
@@ -199,6 +206,7 @@ int hc_server::run_chunk(StreamCtx* cx, const Req& r)
     const size_t state_grow = after > cx->state_bytes ? after - cx->state_bytes : 0;
     p.labels_class = r.n > 0 ? block_class(4 * (size_t)r.n) : 0;
     // admission: a free slot and the memory of this push within the budget
+    const uint64_t a0 = now_ns();
     {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
@@ -239,6 +247,7 @@ int hc_server::run_chunk(StreamCtx* cx, const Req& r)
         }
     }
     p.t_admit = now_ns();
+    ns_admit += p.t_admit - a0;
     hipError_t e = hipSuccess;
     int rc = HC_OK;
     if (hits_grow > 0) {
@@ -266,6 +275,8 @@ int hc_server::run_chunk(StreamCtx* cx, const Req& r)
             hipSuccess)
         rc = set_device_error(e, "server: hits copy");
     if (rc == HC_OK) rc = hc_stream_push(cx->st, (const hc_hit*)cx->hits_dev, r.n, (int32_t*)p.labels_dev, seq);
+    const uint64_t d0 = now_ns();
+    ns_push += d0 - p.t_admit;
     const size_t state_now = stream_device_bytes(cx->st);
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -297,8 +308,10 @@ int hc_server::run_chunk(StreamCtx* cx, const Req& r)
     // closed clusters to the host first, then the processing stamp
     int32_t n_closed = 0;
     std::vector<uint64_t> fin;
+    const uint64_t dr0 = now_ns();
     drain(cx, &n_closed, &fin);
     const uint64_t tp = now_ns();
+    ns_drain += tp - dr0;
     auto it = cx->pend.find(seq);
     if (it != cx->pend.end()) {
         it->second.t_processed = tp;
@@ -485,12 +498,19 @@ int hc_server_closed(hc_server* s, int32_t stream_id, hc_features* out, int32_t 
 {
     if (!s || !n_out || stream_id < 0 || stream_id >= s->cfg.n_streams || (cap > 0 && !out))
         return set_error(HC_ERR_ARG, "bad arguments");
-    std::lock_guard<std::mutex> lk(s->mu);
-    std::vector<hc_features>& v = s->streams[stream_id]->closed;
-    const int32_t k = (int32_t)std::min<size_t>((size_t)std::max(cap, 0), v.size());
-    if (k > 0) {
-        ::memcpy(out, v.data(), sizeof(hc_features) * (size_t)k);
-        v.erase(v.begin(), v.begin() + k);
+    StreamCtx* cx = s->streams[stream_id];
+    std::lock_guard<std::mutex> lk(cx->cmu);
+    int32_t k = 0;
+    while (k < cap && !cx->closed.empty()) {
+        const std::vector<hc_features>& blk = cx->closed.front();
+        const size_t take = std::min<size_t>((size_t)(cap - k), blk.size() - cx->closed_head);
+        ::memcpy(out + k, blk.data() + cx->closed_head, sizeof(hc_features) * take);
+        k += (int32_t)take;
+        cx->closed_head += take;
+        if (cx->closed_head == blk.size()) {
+            cx->closed.pop_front();
+            cx->closed_head = 0;
+        }
     }
     *n_out = k;
     return HC_OK;
@@ -525,6 +545,10 @@ int hc_server_stats_read(hc_server* s, hc_server_stats* out)
     st.processing_p99 = quantile(s->lat_proc, 0.99);
     st.final_p50 = quantile(s->lat_final, 0.50);
     st.final_p99 = quantile(s->lat_final, 0.99);
+    st.ns_admit_wait = s->ns_admit;
+    st.ns_push = s->ns_push;
+    st.ns_drain = s->ns_drain;
+    st.ns_final = s->ns_final;
     *out = st;
     return HC_OK;
 }

@@ -113,7 +113,7 @@ int main(void) {
          sizeof(hc_server_stats));
   F(hc_opts, stream) F(hc_server_config, hbm_budget) F(hc_server_config, flags)
   F(hc_completion, t_arrive_ns) F(hc_completion, t_final_ns)
-  F(hc_server_stats, max_slots) F(hc_server_stats, final_p99)
+  F(hc_server_stats, max_slots) F(hc_server_stats, final_p99) F(hc_server_stats, ns_final)
   F(hc_features, cx) F(hc_hit, tot)
   return 0;
 }
@@ -135,6 +135,7 @@ int main(void) {
     assert got["hc_completion.t_final_ns"] == hc.COMPLETION_DTYPE.fields["t_final_ns"][1]
     assert got["hc_server_stats.max_slots"] == hc._ServerStats.max_slots.offset
     assert got["hc_server_stats.final_p99"] == hc._ServerStats.final_p99.offset
+    assert got["hc_server_stats.ns_final"] == hc._ServerStats.ns_final.offset
     assert got["hc_features.cx"] == hc.FEATURE_DTYPE.fields["cx"][1]
     assert got["hc_hit.tot"] == hc.HIT_DTYPE.fields["tot"][1]
 
