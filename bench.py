@@ -47,7 +47,7 @@ KERNEL_FUNCS = {
     "link": "hc::k_link(", "flatten": "hc::k_flatten(", "features": "hc::k_features(",
     "compact": "hc::k_compact(",
 }
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_config2.json")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_mixed10m.json")
 
 
 def kernel_sources_digest(kernel=None):
@@ -73,8 +73,8 @@ def measured_traffic(kernel):
     return rec.get("hbm_bytes_per_launch")
 
 
-def _counter_means(path):
-    """Mean counter value per (kernel name, counter) over dispatches, from the
+def _counter_values(path):
+    """Per-dispatch counter values per (kernel name, counter), from the
     counter_collection.csv files rocprofv3 writes under `path`."""
     import csv
     import glob
@@ -84,18 +84,19 @@ def _counter_means(path):
             low = {k.lower(): v for k, v in row.items()}
             key = (low["kernel_name"], low["counter_name"])
             acc.setdefault(key, []).append(float(low["counter_value"]))
-    return {k: sum(v) / len(v) for k, v in acc.items()}
+    return acc
 
 
 def traffic_from(fetch_dir, write_dir, command):
     """Writes the counter summary: FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
     per timed kernel, each scaled by what the counter reads for a plain 1 GiB
     device copy in the same run (bench.py --copy-calibration)."""
-    fetch, write = _counter_means(fetch_dir), _counter_means(write_dir)
+    fetch, write = _counter_values(fetch_dir), _counter_values(write_dir)
 
-    def copy_reading(means, counter):
-        vals = [v for (k, c), v in means.items() if c == counter and "copyBuffer" in k]
-        return max(vals) if vals else None
+    def copy_reading(vals, counter):
+        # the largest copy-kernel dispatch is the 1 GiB calibration copy
+        got = [max(v) for (k, c), v in vals.items() if c == counter and "copyBuffer" in k]
+        return max(got) if got else None
 
     f_copy, w_copy = copy_reading(fetch, "FETCH_SIZE"), copy_reading(write, "WRITE_SIZE")
     if not f_copy or not w_copy:
@@ -105,8 +106,8 @@ def traffic_from(fetch_dir, write_dir, command):
                                                "fetch_scale": round(f_scale, 3), "write_scale": round(w_scale, 3)},
            "kernels": {}}
     for name, func in KERNEL_FUNCS.items():
-        fk = [v for (k, c), v in fetch.items() if c == "FETCH_SIZE" and func in k]
-        wk = [v for (k, c), v in write.items() if c == "WRITE_SIZE" and func in k]
+        fk = [sum(v) / len(v) for (k, c), v in fetch.items() if c == "FETCH_SIZE" and func in k]
+        wk = [sum(v) / len(v) for (k, c), v in write.items() if c == "WRITE_SIZE" and func in k]
         if not fk or not wk:
             continue
         fb, wb = fk[0] * 1024 * f_scale, wk[0] * 1024 * w_scale
@@ -133,7 +134,7 @@ def bench_batch(hc, torch, dev, reps):
     sequence (default plan, autotuned plan, and its HIP-graph replay)."""
     import numpy as np
     import hitgen
-    chunks, dts, _ = hitgen.config3()
+    chunks, dts, _ = hitgen.batch_64_chunks()
     sizes = np.array([c.size for c in chunks], dtype=np.int64)
     offsets = np.zeros(len(chunks) + 1, dtype=np.int64)
     offsets[1:] = np.cumsum(sizes)
@@ -193,7 +194,7 @@ def bench_batch(hc, torch, dev, reps):
 
 
 def _served_pools(n_streams, pool, seed):
-    """One config-1 style pool at 37.5 Mhit/s per stream; stream s sees it
+    """One pool of random-walk blobs at 37.5 Mhit/s per stream; stream s sees it
     under the s-th symmetry of the square sensor (so the streams differ)."""
     import numpy as np
     import hitgen
@@ -394,7 +395,7 @@ def main():
     ap.add_argument("--only", choices=["plain", "batch", "served"],
                     help="run one form only (profiling runs); the plain line is still printed")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/traffic_config2.json from two rocprofv3 --pmc runs (CSV output) "
+                    help="write profiles/traffic_mixed10m.json from two rocprofv3 --pmc runs (CSV output) "
                          "of this bench with --copy-calibration, then exit")
     ap.add_argument("--traffic-command", default="", help="the profiling command, recorded in the summary")
     args = ap.parse_args()
@@ -417,7 +418,7 @@ def main():
     import paper_2412_11809_amd as hc
 
     hc.load_library()
-    hits, p = hitgen.config2(n=args.hits)
+    hits, p = hitgen.mixed_10m(n=args.hits)
     n = hits.size
     W, H, dt, D = p["width"], p["height"], p["dt"], p["disorder"]
     dev = torch.device("cuda:0")

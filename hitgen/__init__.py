@@ -206,7 +206,7 @@ def mixed_stream(n, seed, width=256, height=256, span_ticks=640_000_000, disorde
 # the named workloads
 
 
-def config1(n=100_000, seed=BASE_SEED + 1):
+def blobs_100k(n=100_000, seed=BASE_SEED + 1):
     """Single Timepix3 256x256 sensor, 100k hits of random-walk blobs
     (size min(40, Geom(mean 6))), seeds over 10 ms, ToA jitter 100 ns,
     displacement <= 512, dt = 200 ns.  Returns (hits, params)."""
@@ -216,7 +216,7 @@ def config1(n=100_000, seed=BASE_SEED + 1):
     return hits, dict(width=256, height=256, dt=ns_to_ticks(200, TPX3_TICK_NS), disorder=512)
 
 
-def config2(n=10_000_000, seed=BASE_SEED + 2, span_ticks=None):
+def mixed_10m(n=10_000_000, seed=BASE_SEED + 2, span_ticks=None):
     """Single 256x256 sensor, ~10 Mhit/s mixed blobs/tracks/heavy blobs over
     about 1 s, displacement <= 4096, dt = 200 ns.  Returns (hits, params)."""
     if span_ticks is None:
@@ -227,7 +227,7 @@ def config2(n=10_000_000, seed=BASE_SEED + 2, span_ticks=None):
     return hits, dict(width=256, height=256, dt=ns_to_ticks(200, TPX3_TICK_NS), disorder=4096)
 
 
-def config3_sizes(seed=BASE_SEED + 3, chunks=64, lo=1e3, hi=2e6, target=30e6, tol=0.10):
+def batch64_sizes(seed=BASE_SEED + 3, chunks=64, lo=1e3, hi=2e6, target=30e6, tol=0.10):
     """Log-uniform chunk sizes; the first sub-seed whose total lies within
     target +- tol is used (the plain log-uniform mean is ~16.8 M)."""
     for sub in range(100000):
@@ -238,11 +238,11 @@ def config3_sizes(seed=BASE_SEED + 3, chunks=64, lo=1e3, hi=2e6, target=30e6, to
     raise RuntimeError("no sub-seed found")
 
 
-def config3(seed=BASE_SEED + 3, scale=1.0):
-    """64 chunks from 4 detectors, each config-1 style with its own dt in
+def batch_64_chunks(seed=BASE_SEED + 3, scale=1.0):
+    """64 chunks from 4 detectors, each a blob stream with its own dt in
     {100, 200, 500} ns; ``scale`` shrinks every chunk (tests).  Returns
     (list of hit arrays, list of dt ticks, detector ids)."""
-    sizes, sub = config3_sizes(seed)
+    sizes, sub = batch64_sizes(seed)
     rng = np.random.default_rng([seed, sub, 1])
     dts_ns = rng.choice([100, 200, 500], size=sizes.size)
     chunks, dts = [], []
@@ -256,7 +256,7 @@ def config3(seed=BASE_SEED + 3, scale=1.0):
     return chunks, dts, [c % 4 for c in range(sizes.size)]
 
 
-def config4(n=200_000_000, seed=BASE_SEED + 4):
+def timepix4_200m(n=200_000_000, seed=BASE_SEED + 4):
     """Timepix4-shaped 448x512 sensor at 300 Mhit/s: random-walk blobs of
     size min(60, Geom(mean 9)), ToA ticks of 195.3125 ps, displacement <= 16384,
     dt = 200 ns = 1024 ticks.  Returns (hits, params)."""

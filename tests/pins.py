@@ -201,10 +201,10 @@ def pin_features(lib, seed=19):
     assert f.size == 1 and f[0]["cx"] == 2.0 and f[0]["cy"] == 7.0 / 4.0
 
 
-def pin_config1_invariants(lib):
+def pin_blob_workload_invariants(lib):
     """The full 100k-hit blob workload: the independent window-scan partition
     and invariant checker agree, and the features recompute exactly."""
-    hits, p = hitgen.config1()
+    hits, p = hitgen.blobs_100k()
     lab, f = oracle.cluster(hits, p["width"], p["height"], p["dt"], lib=lib)
     assert (lab == partition_of(hits, p["dt"])).all()
     check_invariants(hits, lab, p["dt"])
@@ -212,4 +212,4 @@ def pin_config1_invariants(lib):
 
 
 PINS = [pin_golden, pin_bruteforce, pin_image_labelling, pin_closed_forms, pin_metamorphic,
-        pin_saturation, pin_features, pin_config1_invariants]
+        pin_saturation, pin_features, pin_blob_workload_invariants]

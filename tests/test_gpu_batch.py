@@ -63,15 +63,15 @@ def run(hc, chunks, dts, plan=None, hint=0, features=True):
     return fetch(hc, labels, feats, k, offsets)
 
 
-def config3_small(scale):
-    chunks, dts, _ = hitgen.config3(scale=scale)
+def batch_small(scale):
+    chunks, dts, _ = hitgen.batch_64_chunks(scale=scale)
     return chunks, dts
 
 
-def test_batch_config3_scaled(hc):
-    chunks, dts = config3_small(0.02)
+def test_batch_64_chunks_scaled(hc):
+    chunks, dts = batch_small(0.02)
     got, k = run(hc, chunks, dts, hint=512)
-    compare(got, k, expect(chunks, dts), "config3x0.02")
+    compare(got, k, expect(chunks, dts), "batch x0.02")
 
 
 def test_batch_uneven_sizes_and_tile_edges(hc):
@@ -126,7 +126,7 @@ def test_batch_wide_chunk_and_range_error(hc):
 
 def test_batch_autotune_plan(hc):
     import torch
-    chunks, dts = config3_small(0.01)
+    chunks, dts = batch_small(0.01)
     hits, offsets = pack(chunks)
     d = hc.hits_to_device(hits)
     n = hits.size
@@ -151,7 +151,7 @@ def test_batch_autotune_plan(hc):
 
 def test_batch_graph_replays(hc):
     import torch
-    chunks, dts = config3_small(0.01)
+    chunks, dts = batch_small(0.01)
     hits, offsets = pack(chunks)
     alt = [hitgen.blob_stream(c.size, 500 + i, span_ticks=max(1, c.size * 64)) for i, c in enumerate(chunks)]
     hits_alt, _ = pack(alt)

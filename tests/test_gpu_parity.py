@@ -45,13 +45,13 @@ def assert_parity(hc, hits, w, h, dt, hint=0, flags=0):
     return got_l
 
 
-def test_config1_full(hc):
-    hits, p = hitgen.config1()
+def test_blobs_100k_full(hc):
+    hits, p = hitgen.blobs_100k()
     assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
 
 
-def test_config2_slice(hc):
-    hits, p = hitgen.config2(n=1_000_000, seed=99)
+def test_mixed_slice(hc):
+    hits, p = hitgen.mixed_10m(n=1_000_000, seed=99)
     assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
 
 
@@ -81,7 +81,7 @@ def test_disorder_hints(hc, hint):
 
 
 def test_reversed_input(hc):
-    hits, p = hitgen.config1(n=50_000, seed=3)
+    hits, p = hitgen.blobs_100k(n=50_000, seed=3)
     hits = hits[np.argsort(hits["toa"], kind="stable")][::-1].copy()
     assert_parity(hc, hits, 256, 256, p["dt"], 512)
 
@@ -124,7 +124,7 @@ def test_dense_small_sensor(hc):
 
 
 def test_timepix4_sensor(hc):
-    hits, p = hitgen.config4(n=2_000_000)
+    hits, p = hitgen.timepix4_200m(n=2_000_000)
     assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
 
 
@@ -140,7 +140,7 @@ def test_edges_of_sensor(hc):
 
 
 def test_range_error_reported(hc):
-    hits, p = hitgen.config1(n=10_000, seed=4)
+    hits, p = hitgen.blobs_100k(n=10_000, seed=4)
     hits["x"][1234] = 256
     _, _, k = run_gpu(hc, hits, 256, 256, 128, 512)
     assert k == hc.HC_ERR_RANGE
@@ -148,7 +148,7 @@ def test_range_error_reported(hc):
 
 def test_repeatable(hc):
     """Labels are schedule-independent: 20 repetitions agree exactly."""
-    hits, p = hitgen.config2(n=400_000, seed=21)
+    hits, p = hitgen.mixed_10m(n=400_000, seed=21)
     want = assert_parity(hc, hits, 256, 256, p["dt"], p["disorder"])
     for _ in range(20):
         got, _, _ = run_gpu(hc, hits, 256, 256, p["dt"], p["disorder"])
@@ -157,7 +157,7 @@ def test_repeatable(hc):
 
 def test_side_stream_and_workspace(hc):
     import torch
-    hits, p = hitgen.config1(n=70_000, seed=5)
+    hits, p = hitgen.blobs_100k(n=70_000, seed=5)
     ws = torch.empty(hc.hc_workspace_size(hits.size, 256, 256, 512), dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
     got, gf, k = run_gpu(hc, hits, 256, 256, p["dt"], 512, stream=s, workspace=ws)
@@ -167,7 +167,7 @@ def test_side_stream_and_workspace(hc):
 
 def test_small_workspace_rejected(hc):
     import torch
-    d = hc.hits_to_device(hitgen.config1(n=5000)[0])
+    d = hc.hits_to_device(hitgen.blobs_100k(n=5000)[0])
     ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
     labels = torch.empty(5000, dtype=torch.int32, device="cuda")
     k = torch.empty(1, dtype=torch.int32, device="cuda")
@@ -177,30 +177,30 @@ def test_small_workspace_rejected(hc):
 
 
 def test_labels_only(hc):
-    hits, p = hitgen.config1(n=30_000, seed=6)
+    hits, p = hitgen.blobs_100k(n=30_000, seed=6)
     got, _, k = run_gpu(hc, hits, 256, 256, p["dt"], 512, features=False)
     want, wf = oracle.cluster(hits, 256, 256, p["dt"])
     assert (got == want).all() and k == wf.size
 
 
-def test_config2_full_size(hc):
+def test_mixed_10m_full_size(hc):
     """The benchmark's workload (10M hits) in the benchmark's configuration."""
-    hits, p = hitgen.config2()
+    hits, p = hitgen.mixed_10m()
     got = assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
     assert (got <= np.arange(got.size)).all()
 
 
 # ---- each neighbour search forced on every tile (pixel index, window scan),
 # and sensors at and beyond the window scan's 14-bit limit
-@pytest.mark.parametrize("case", ["config1", "config2", "single_pixel", "dense", "timepix4", "same_toa"])
+@pytest.mark.parametrize("case", ["blobs_100k", "mixed_10m", "single_pixel", "dense", "timepix4", "same_toa"])
 @pytest.mark.parametrize("variant", ["index", "window"])
 def test_link_variants(hc, case, variant):
     flag = hc.HC_FLAG_LINK_PIXEL_INDEX if variant == "index" else hc.HC_FLAG_LINK_WINDOW
-    if case == "config1":
-        hits, p = hitgen.config1()
+    if case == "blobs_100k":
+        hits, p = hitgen.blobs_100k()
         assert_parity(hc, hits, 256, 256, p["dt"], p["disorder"], flags=flag)
-    elif case == "config2":
-        hits, p = hitgen.config2(n=1_000_000, seed=98)
+    elif case == "mixed_10m":
+        hits, p = hitgen.mixed_10m(n=1_000_000, seed=98)
         assert_parity(hc, hits, 256, 256, p["dt"], p["disorder"], flags=flag)
     elif case == "single_pixel":
         rng = np.random.default_rng(20)
@@ -212,7 +212,7 @@ def test_link_variants(hc, case, variant):
         hits = hitgen.uniform_hits(100_000, 21, 8, 8, 2_000_000, disorder=50)
         assert_parity(hc, hits, 8, 8, 30, 64, flags=flag)
     elif case == "timepix4":
-        hits, p = hitgen.config4(n=1_000_000, seed=22)
+        hits, p = hitgen.timepix4_200m(n=1_000_000, seed=22)
         assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"], flags=flag)
     else:
         hits = hitgen.uniform_hits(20_000, 23, 100, 100, 1)

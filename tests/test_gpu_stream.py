@@ -58,12 +58,12 @@ def check(hc, hits, sizes, w, h, dt, hint):
 
 
 def test_stream_timepix4_chunks(hc):
-    hits, p = hitgen.config4(n=3_000_000)
+    hits, p = hitgen.timepix4_200m(n=3_000_000)
     check(hc, hits, [200_000] * 15, p["width"], p["height"], p["dt"], p["disorder"])
 
 
 def test_stream_random_chunking(hc):
-    hits, p = hitgen.config1(n=60_000, seed=77)
+    hits, p = hitgen.blobs_100k(n=60_000, seed=77)
     rng = np.random.default_rng(5)
     sizes = []
     left = hits.size
@@ -75,13 +75,13 @@ def test_stream_random_chunking(hc):
 
 
 def test_stream_mixed_workload(hc):
-    hits, p = hitgen.config2(n=2_000_000, seed=8)
+    hits, p = hitgen.mixed_10m(n=2_000_000, seed=8)
     check(hc, hits, [250_000] * 8, 256, 256, p["dt"], p["disorder"])
 
 
 def test_stream_rejects_disorder_and_continues(hc):
     import torch
-    hits, p = hitgen.config1(n=40_000, seed=9)
+    hits, p = hitgen.blobs_100k(n=40_000, seed=9)
     tdis = hitgen.realised_disorder_ticks(hits) + 1
     st = hc.HcStream(p["dt"], tdis, 256, 256, p["disorder"])
     a, b = hits[:20_000], hits[20_000:]

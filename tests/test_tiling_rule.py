@@ -55,10 +55,10 @@ def tiled_rule_labels(hits, width, height, dt, tile=64):
 @pytest.mark.parametrize("case", ["blobs", "mixed", "dense"])
 def test_tiled_latest_hit_rule_matches_oracle(case):
     if case == "blobs":
-        hits, p = hitgen.config1(n=20_000, seed=31)
+        hits, p = hitgen.blobs_100k(n=20_000, seed=31)
         w, h, dt = 256, 256, p["dt"]
     elif case == "mixed":
-        hits, p = hitgen.config2(n=30_000, seed=32)
+        hits, p = hitgen.mixed_10m(n=30_000, seed=32)
         w, h, dt = 256, 256, p["dt"]
     else:
         hits = hitgen.uniform_hits(5_000, 33, 12, 12, 20_000, disorder=40)
@@ -154,10 +154,10 @@ def window_rule_labels(hits, width, height, dt, tile=64):
 @pytest.mark.parametrize("case", ["blobs", "mixed", "dense"])
 def test_window_rule_matches_oracle(case):
     if case == "blobs":
-        hits, p = hitgen.config1(n=20_000, seed=41)
+        hits, p = hitgen.blobs_100k(n=20_000, seed=41)
         w, h, dt = 256, 256, p["dt"]
     elif case == "mixed":
-        hits, p = hitgen.config2(n=30_000, seed=42)
+        hits, p = hitgen.mixed_10m(n=30_000, seed=42)
         w, h, dt = 256, 256, p["dt"]
     else:
         hits = hitgen.uniform_hits(5_000, 43, 12, 12, 20_000, disorder=40)
