@@ -104,6 +104,41 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint
     return before + x - v;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves (no LDS
+// traffic): shifts of 1, 2, 4, 8 inside each row of 16 lanes, then the last
+// lane of row 0 / row 2 is added to rows 1 / 3, then lane 31 to rows 2 and 3.
+// Sources outside a row or disabled rows contribute 0.
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ inline uint64_t dpp_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROW_MASK, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROW_MASK, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t wave_incl_scan_u64(uint64_t v)
+{
+    v += dpp_u64<0x111, 0xF>(v);
+    v += dpp_u64<0x112, 0xF>(v);
+    v += dpp_u64<0x114, 0xF>(v);
+    v += dpp_u64<0x118, 0xF>(v);
+    v += dpp_u64<0x142, 0xA>(v);
+    v += dpp_u64<0x143, 0xC>(v);
+    return v;
+}
+
 // Work-group reductions of 64-bit minima / maxima (result valid in all threads).
 template <int NT>
 __device__ inline uint64_t block_min_u64(uint64_t v, uint64_t* red)

@@ -82,8 +82,11 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     }
     __syncthreads();
     // Consecutive sorted hits of one cluster sit in consecutive lanes: reduce
-    // each run of equal slots inside the wave first (segmented scans), so only
-    // the run's last lane touches the LDS accumulators.
+    // each run of equal slots inside the wave first, so only the run's last
+    // lane touches the LDS accumulators.  A run's sums are differences of
+    // wave-wide prefix sums (DPP scans, no LDS), its size is its length, and
+    // -- the lanes being in ToA order -- its ToA minimum is at its first lane
+    // and its maximum at its last.
     const int lane = t & (kWave - 1);
     const unsigned long long le_mask = lane == kWave - 1 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
 #pragma unroll
@@ -96,40 +99,34 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         const bool tail = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ull);
         const bool valid = s >= 0;
         const uint32_t x = valid ? (xy[q] & 0xFFFFu) : 0u, y = valid ? (xy[q] >> 16) : 0u;
-        uint32_t c = valid ? 1u : 0u, st = valid ? tot[q] : 0u, sx = x, sy = y;
-        uint32_t own = (valid && (uint32_t)idx[q] + 1u == h_key[s]) ? 1u : 0u;
-        unsigned long long sxt = (unsigned long long)x * st, syt = (unsigned long long)y * st;
-        unsigned long long tmn = valid ? (unsigned long long)toa[q] : ~0ull;
-        unsigned long long tmx = valid ? (unsigned long long)toa[q] : 0ull;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const uint32_t c2 = __shfl_up(c, o, kWave), st2 = __shfl_up(st, o, kWave);
-            const uint32_t sx2 = __shfl_up(sx, o, kWave), sy2 = __shfl_up(sy, o, kWave);
-            const uint32_t own2 = __shfl_up(own, o, kWave);
-            const unsigned long long sxt2 = __shfl_up(sxt, o, kWave), syt2 = __shfl_up(syt, o, kWave);
-            const unsigned long long tmn2 = __shfl_up(tmn, o, kWave), tmx2 = __shfl_up(tmx, o, kWave);
-            if (lane - o >= start) {
-                c += c2;
-                st += st2;
-                sx += sx2;
-                sy += sy2;
-                own |= own2;
-                sxt += sxt2;
-                syt += syt2;
-                tmn = tmn2 < tmn ? tmn2 : tmn;
-                tmx = tmx2 > tmx ? tmx2 : tmx;
-            }
-        }
+        const uint32_t st = valid ? tot[q] : 0u;
+        const bool own_lane = valid && (uint32_t)idx[q] + 1u == h_key[s];
+        const unsigned long long owners = __ballot(own_lane);
+        const uint32_t P_st = wave_incl_scan_u32(st);
+        const uint32_t P_sx = wave_incl_scan_u32(x);
+        const uint32_t P_sy = wave_incl_scan_u32(y);
+        const uint64_t P_sxt = wave_incl_scan_u64((uint64_t)x * st);
+        const uint64_t P_syt = wave_incl_scan_u64((uint64_t)y * st);
+        // prefix sums just before the run (lane start - 1; 0 for a run at lane
+        // 0).  Every lane takes part in each shuffle: a lane that sat one out
+        // would not supply its value to the lanes reading from it.
+        const int src = start > 0 ? start - 1 : 0;
+        const bool first = start == 0;
+        const uint32_t B_st = __shfl(P_st, src, kWave), B_sx = __shfl(P_sx, src, kWave);
+        const uint32_t B_sy = __shfl(P_sy, src, kWave);
+        const uint64_t B_sxt = __shfl(P_sxt, src, kWave), B_syt = __shfl(P_syt, src, kWave);
+        const uint64_t tmn = __shfl(valid ? toa[q] : 0ull, start, kWave);
         if (tail && valid) {
-            atomicAdd(&a_size[s], c);
-            atomicAdd(&a_st[s], st);
-            atomicAdd(&a_sx[s], sx);
-            atomicAdd(&a_sy[s], sy);
-            atomicAdd(&a_sxt[s], sxt);
-            atomicAdd(&a_syt[s], syt);
-            atomicMin(&a_tmin[s], tmn);
-            atomicMax(&a_tmax[s], tmx);
-            if (own) a_own[s] = 1u;
+            const unsigned long long run = le_mask & ~((1ull << start) - 1ull);
+            atomicAdd(&a_size[s], (uint32_t)(lane - start + 1));
+            atomicAdd(&a_st[s], P_st - (first ? 0u : B_st));
+            atomicAdd(&a_sx[s], P_sx - (first ? 0u : B_sx));
+            atomicAdd(&a_sy[s], P_sy - (first ? 0u : B_sy));
+            atomicAdd(&a_sxt[s], (unsigned long long)(P_sxt - (first ? 0ull : B_sxt)));
+            atomicAdd(&a_syt[s], (unsigned long long)(P_syt - (first ? 0ull : B_syt)));
+            atomicMin(&a_tmin[s], (unsigned long long)tmn);
+            atomicMax(&a_tmax[s], (unsigned long long)toa[q]);
+            if (owners & run) a_own[s] = 1u;
         }
     }
     __syncthreads();
