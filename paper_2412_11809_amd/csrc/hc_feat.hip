@@ -23,8 +23,12 @@ __device__ inline uint32_t root_hash(uint32_t key) { return (key * 0x9E3779B1u) 
 __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t* __restrict__ labels)
 {
     static_assert(kFeatHash == 512 && kFeatHash >= kFeatTile, "root_hash yields 9 bits; a tile never fills the table");
+    static_assert((uint64_t)kFeatTile * 65535u < (1ull << 32), "paired 32-bit sums must not carry");
     __shared__ uint32_t h_key[kFeatHash];
-    __shared__ uint32_t a_size[kFeatHash], a_st[kFeatHash], a_sx[kFeatHash], a_sy[kFeatHash], a_own[kFeatHash];
+    // two 32-bit sums per 64-bit word (size | sum ToT << 32, sum x | sum y << 32):
+    // a tile's sums stay below 2^32, so one atomic adds both without carry
+    __shared__ unsigned long long a_cs[kFeatHash], a_xy[kFeatHash];
+    __shared__ uint32_t a_own[kFeatHash];
     __shared__ unsigned long long a_sxt[kFeatHash], a_syt[kFeatHash], a_tmin[kFeatHash], a_tmax[kFeatHash];
     constexpr int PER = kFeatTile / kFeatThreads;
 
@@ -63,10 +67,8 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
             while (true) {
                 const uint32_t old = atomicCAS(&h_key[s], 0u, key);
                 if (old == 0u) {  // first hit of this cluster here: initialise
-                    a_size[s] = 0u;
-                    a_st[s] = 0u;
-                    a_sx[s] = 0u;
-                    a_sy[s] = 0u;
+                    a_cs[s] = 0ull;
+                    a_xy[s] = 0ull;
                     a_own[s] = 0u;
                     a_sxt[s] = 0ull;
                     a_syt[s] = 0ull;
@@ -118,10 +120,10 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         const uint64_t tmn = __shfl(valid ? toa[q] : 0ull, start, kWave);
         if (tail && valid) {
             const unsigned long long run = le_mask & ~((1ull << start) - 1ull);
-            atomicAdd(&a_size[s], (uint32_t)(lane - start + 1));
-            atomicAdd(&a_st[s], P_st - (first ? 0u : B_st));
-            atomicAdd(&a_sx[s], P_sx - (first ? 0u : B_sx));
-            atomicAdd(&a_sy[s], P_sy - (first ? 0u : B_sy));
+            const uint64_t n_st = P_st - (first ? 0u : B_st);
+            const uint64_t n_sx = P_sx - (first ? 0u : B_sx), n_sy = P_sy - (first ? 0u : B_sy);
+            atomicAdd(&a_cs[s], (unsigned long long)((uint64_t)(lane - start + 1) | (n_st << 32)));
+            atomicAdd(&a_xy[s], (unsigned long long)(n_sx | (n_sy << 32)));
             atomicAdd(&a_sxt[s], (unsigned long long)(P_sxt - (first ? 0ull : B_sxt)));
             atomicAdd(&a_syt[s], (unsigned long long)(P_syt - (first ? 0ull : B_syt)));
             atomicMin(&a_tmin[s], (unsigned long long)tmn);
@@ -130,23 +132,44 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         }
     }
     __syncthreads();
-    for (int s = t; s < kFeatHash; s += kFeatThreads) {
+    // Records: the owner tile writes the cluster's slot; every other tile
+    // queues a carry.  Carry positions come from one counter per work-group
+    // (a block scan of the per-thread counts, then a single global atomic),
+    // not one global atomic per carry.
+    constexpr int SPT = kFeatHash / kFeatThreads;  // hash entries per thread
+    uint32_t nc = 0;
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int s = t + k * kFeatThreads;
+        nc += (h_key[s] != 0u && !a_own[s]) ? 1u : 0u;
+    }
+    __shared__ uint32_t wsum[kFeatThreads / kWave];
+    __shared__ int32_t s_base;
+    uint32_t total;
+    uint32_t pos = block_exclusive_scan<kFeatThreads>(nc, wsum, &total);
+    if (t == 0) s_base = total ? atomicAdd(&w.status->n_carries, (int32_t)total) : 0;
+    __syncthreads();
+    const int64_t base = s_base;
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int s = t + k * kFeatThreads;
         const uint32_t key = h_key[s];
         if (key == 0u) continue;
         SlotRec r;
-        r.size = a_size[s];
+        const uint64_t cs = a_cs[s], sxy = a_xy[s];
+        r.size = (uint32_t)cs;
         r.root = (int32_t)(key - 1u);
-        r.sum_tot = a_st[s];
+        r.sum_tot = cs >> 32;
         r.toa_min = a_tmin[s];
         r.toa_max = a_tmax[s];
         r.sum_xt = a_sxt[s];
         r.sum_yt = a_syt[s];
-        r.sum_x = a_sx[s];
-        r.sum_y = a_sy[s];
+        r.sum_x = (uint32_t)sxy;
+        r.sum_y = sxy >> 32;
         if (a_own[s]) {
             w.slots[key - 1u] = r;
         } else {
-            const int c = atomicAdd(&w.status->n_carries, 1);
+            const int64_t c = base + pos++;
             if (c < w.carry_cap) w.carries[c] = r;
             else atomicOr(&w.status->err_internal, 1);
         }

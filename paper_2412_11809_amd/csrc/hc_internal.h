@@ -17,6 +17,7 @@ constexpr int kLinkTile = 1024;       // sorted hits per link work-group
 constexpr int kLinkHaloCap = 1024;    // earlier hits a link work-group can hold
 constexpr uint32_t kLinkWindowMaxDim = 16384;  // window scan: coordinates fit 14 bits
 constexpr int kLinkWindowMeanCost = 16;        // a tile scans its windows below this many slots per hit
+constexpr uint64_t kLinkHybridMaxPixels = 65536; // larger sensors: window scan (bitmap LDS would cut occupancy)
 constexpr int kLinkThreads = 512;
 
 

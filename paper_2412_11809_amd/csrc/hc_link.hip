@@ -40,6 +40,9 @@ __host__ __device__ inline int link_kernel(const Work& w)
     const bool idx_ok = (uint64_t)w.width * w.height <= kLinkMaxPixels;
     if (w.link_mode == 1 || !win_ok) return kLinkIndexOnly;
     if (w.link_mode == 2 || !idx_ok) return kLinkWindowOnly;
+    // beyond 256 x 256 pixels the bitmap leaves room for one work-group per
+    // CU, which costs every tile more than scanning its windows
+    if (w.link_mode == 0 && (uint64_t)w.width * w.height > kLinkHybridMaxPixels) return kLinkWindowOnly;
     return kLinkHybrid;
 }
 
@@ -129,16 +132,31 @@ __device__ inline void link_union_publish(const Work& w, int32_t* l_par, int (&c
         if (root[q] >= 0) atomicMin(&minidx[root[q]], ids[q]);
     }
     __syncthreads();
+    // halo hits joined by this tile become cross-tile edges; their positions
+    // come from one reservation per work-group (block scan + one atomic)
+    int32_t m[LPER];
+    uint32_t ne = 0;
+#pragma unroll
+    for (int q = 0; q < LPER; q++) {
+        const int i = t + q * kLinkThreads;
+        m[q] = i < L ? minidx[root[q]] : -1;
+        ne += (i < hl && ids[q] != m[q]) ? 1u : 0u;
+    }
+    __shared__ uint32_t e_wsum[kLinkThreads / kWave];
+    __shared__ int32_t e_base;
+    uint32_t n_tile_edges;
+    uint32_t pos = block_exclusive_scan<kLinkThreads>(ne, e_wsum, &n_tile_edges);
+    if (t == 0) e_base = n_tile_edges ? atomicAdd(&w.status->n_edges, (int32_t)n_tile_edges) : 0;
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < LPER; q++) {
         const int i = t + q * kLinkThreads;
         if (i >= L) continue;
-        const int32_t m = minidx[root[q]];
         if (i >= hl) {
-            w.gparent[ids[q]] = m;
-        } else if (ids[q] != m) {
-            const int e = atomicAdd(&w.status->n_edges, 1);
-            if (e < w.edge_cap) w.edges[e] = make_int2(ids[q], m);
+            w.gparent[ids[q]] = m[q];
+        } else if (ids[q] != m[q]) {
+            const int64_t e = (int64_t)e_base + pos++;
+            if (e < w.edge_cap) w.edges[e] = make_int2(ids[q], m[q]);
             else atomicOr(&w.status->err_internal, 1);
         }
     }
