@@ -106,7 +106,8 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.fb_key[1] = (uint64_t*)take(8 * N);
     x.fb_val[0] = (uint32_t*)take(4 * N);
     x.fb_val[1] = (uint32_t*)take(4 * N);
-    x.fb_hist = (uint32_t*)take(4 * 256 * (size_t)x.n_fb_blocks);
+    // digit counters, then one total per scan segment
+    x.fb_hist = (uint32_t*)take(4 * (256 * (size_t)x.n_fb_blocks + fb_scan_segments(x.n_fb_blocks)));
     if (w) *w = x;
     return off;
 }

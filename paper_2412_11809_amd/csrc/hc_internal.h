@@ -29,6 +29,8 @@ constexpr int kScanThreads = 256;
 constexpr int kFbBlock = 2048;        // elements per fallback radix block
 constexpr int kFbThreads = 512;
 constexpr int kFbMaxPasses = 8;       // 8-bit digits of a 64-bit key
+constexpr int kFbScanSeg = 16384;     // digit counters per parallel scan task
+constexpr int kFbGroup = 32;          // blocks per histogram / scatter task (fewer cross-XCD fences)
 constexpr int kMaxNeighbourTiles = 16; // sort merge looks at most this far
 
 // Partial or final integer features of one cluster (64 bytes).
@@ -62,7 +64,8 @@ struct RadixState {
     int32_t scatter_done[kFbMaxPasses];
     int32_t query_done;
     int32_t shift;          // batch sort: chunk id sits above this many ToA bits
-    int32_t pad2_[14];
+    int32_t seg_done[kFbMaxPasses];  // segments of the counter scan finished
+    int32_t pad2_[6];
 };
 
 struct Status {
@@ -184,6 +187,11 @@ inline int32_t link_mode_of(const hc_opts* o)
 {
     if (!o) return 0;
     return o->flags == HC_FLAG_LINK_PIXEL_INDEX ? 1 : o->flags == HC_FLAG_LINK_WINDOW ? 2 : 0;
+}
+// Segments of the fallback's digit-counter scan (256 counters per block).
+__host__ __device__ inline int32_t fb_scan_segments(int32_t nb)
+{
+    return (int32_t)(((int64_t)256 * nb + kFbScanSeg - 1) / kFbScanSeg);
 }
 // Cached per-device workspace for callers that pass none (grown on demand).
 int cached_workspace(size_t need, void** out);

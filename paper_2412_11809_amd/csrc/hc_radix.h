@@ -7,9 +7,11 @@
 // co-residency guarantee and every wait ends.  Task 0 decides whether the
 // sort is needed at all; if not, every other work-group exits at once.
 //
-// Tasks: 0 = plan; then per pass p: kFbBlock-sized histogram tasks, one scan
-// task, scatter tasks; then `extra` caller tasks (queries on the result).
-// Sorting is stable, so equal keys keep their source order.
+// Tasks: 0 = plan; then per pass p: kFbBlock-sized histogram tasks, the
+// digit-counter scan in segments of kFbScanSeg counters (one task each), one
+// task scanning the segment totals, scatter tasks; then `extra` caller tasks
+// (queries on the result).  Sorting is stable, so equal keys keep their
+// source order.
 #pragma once
 
 #include "hc_device.h"
@@ -84,7 +86,8 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
             const int extra = job.plan(*st, L);
             __syncthreads();
             if (t == 0) {
-                if (st->active) st->total_tasks = 1 + st->passes * (2 * nb + 1) + extra;
+                const int nh = (nb + kFbGroup - 1) / kFbGroup;
+                if (st->active) st->total_tasks = 1 + st->passes * (2 * nh + fb_scan_segments(nb) + 1) + extra;
                 __threadfence();
                 __hip_atomic_store(&st->plan_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -94,10 +97,14 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
         if (task >= __hip_atomic_load(&st->total_tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
         const int passes = st->passes;
         const uint64_t kmin = st->key_min;
-        const int per_pass = 2 * nb + 1;
+        const int nseg = fb_scan_segments(nb);
+        const int nh = (nb + kFbGroup - 1) / kFbGroup;  // tasks of kFbGroup blocks
+        const int per_pass = 2 * nh + nseg + 1;
+        const int64_t n_counters = (int64_t)256 * nb;
+        uint32_t* seg_tot = hist + n_counters;
         const int tt = task - 1;
         if (tt >= passes * per_pass) {
-            wait_at_least(&st->scatter_done[passes - 1], nb, nullptr);
+            wait_at_least(&st->scatter_done[passes - 1], nh, nullptr);
             const int last = (passes - 1) & 1;
             job.extra(tt - passes * per_pass, key_buf[last], val_buf[last], L);
             continue;
@@ -106,35 +113,55 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
         const int shift = 8 * p;
         const uint64_t* kin = key_buf[(p + 1) & 1];
         const uint32_t* vin = val_buf[(p + 1) & 1];
-        if (r < nb) {  // ---- histogram of block r
-            const int b = r;
-            if (p > 0) wait_at_least(&st->scatter_done[p - 1], nb, nullptr);
-            for (int i = t; i < 256; i += kFbThreads) L.hist[i] = 0;
-            __syncthreads();
-            for (int i = t; i < kFbBlock; i += kFbThreads) {
-                const int64_t g = (int64_t)b * kFbBlock + i;
-                if (g < n) {
-                    uint64_t k;
-                    uint32_t v;
-                    if (p == 0) {
-                        job.load(g, k, v);
-                        k -= kmin;
-                    } else {
-                        k = kin[g];
+        if (r < nh) {  // ---- histograms of blocks [r * kFbGroup, ...)
+            if (p > 0) wait_at_least(&st->scatter_done[p - 1], nh, nullptr);
+            const int b1 = (r + 1) * kFbGroup < nb ? (r + 1) * kFbGroup : nb;
+            for (int b = r * kFbGroup; b < b1; b++) {
+                for (int i = t; i < 256; i += kFbThreads) L.hist[i] = 0;
+                __syncthreads();
+                for (int i = t; i < kFbBlock; i += kFbThreads) {
+                    const int64_t g = (int64_t)b * kFbBlock + i;
+                    if (g < n) {
+                        uint64_t k;
+                        uint32_t v;
+                        if (p == 0) {
+                            job.load(g, k, v);
+                            k -= kmin;
+                        } else {
+                            k = kin[g];
+                        }
+                        atomicAdd(&L.hist[(k >> shift) & 255u], 1u);
                     }
-                    atomicAdd(&L.hist[(k >> shift) & 255u], 1u);
                 }
+                __syncthreads();
+                for (int i = t; i < 256; i += kFbThreads) hist[(int64_t)i * nb + b] = L.hist[i];
             }
-            __syncthreads();
-            for (int i = t; i < 256; i += kFbThreads) hist[(int64_t)i * nb + b] = L.hist[i];
             signal_done(&st->hist_done[p]);
-        } else if (r == nb) {  // ---- exclusive scan of all block histograms
-            wait_at_least(&st->hist_done[p], nb, nullptr);
-            radix_scan_counts(hist, (int64_t)256 * nb, L);
+        } else if (r < nh + nseg) {  // ---- exclusive scan of one segment of the counters
+            const int sg = r - nh;
+            wait_at_least(&st->hist_done[p], nh, nullptr);
+            const int64_t c0 = (int64_t)sg * kFbScanSeg;
+            const int64_t len = n_counters - c0 < kFbScanSeg ? n_counters - c0 : kFbScanSeg;
+            if (t == 0) L.misc = 0;
+            __syncthreads();
+            // segment total before the in-place exclusive scan overwrites it
+            uint32_t part = 0;
+            for (int64_t i = t; i < len; i += kFbThreads) part += hist[c0 + i];
+            atomicAdd((uint32_t*)&L.misc, part);
+            __syncthreads();
+            radix_scan_counts(hist + c0, len, L);
+            if (t == 0) seg_tot[sg] = (uint32_t)L.misc;
+            signal_done(&st->seg_done[p]);
+        } else if (r == nh + nseg) {  // ---- exclusive scan of the segment totals
+            wait_at_least(&st->seg_done[p], nseg, nullptr);
+            radix_scan_counts(seg_tot, nseg, L);
             signal_done(&st->scan_done[p]);
-        } else {  // ---- stable scatter of block b
-            const int b = r - nb - 1;
+        } else {  // ---- stable scatter of blocks [h * kFbGroup, ...)
+            const int h = r - nh - nseg - 1;
             wait_at_least(&st->scan_done[p], 1, nullptr);
+            const int b1 = (h + 1) * kFbGroup < nb ? (h + 1) * kFbGroup : nb;
+            for (int b = h * kFbGroup; b < b1; b++) {
+            __syncthreads();  // the previous block's LDS is no longer read
             const int64_t g0 = (int64_t)b * kFbBlock;
             const int cntb = (int)((n - g0) < kFbBlock ? (n - g0) : kFbBlock);
             for (int i = t; i < kFbBlock; i += kFbThreads) {
@@ -176,7 +203,8 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
             for (int rr = t; rr < cntb; rr += kFbThreads) {
                 const uint32_t d = sk[rr];
                 const int e = sv[rr];
-                const int64_t pos = (int64_t)hist[(int64_t)d * nb + b] + (rr - (int)L.start[d]);
+                const int64_t ci = (int64_t)d * nb + b;
+                const int64_t pos = (int64_t)hist[ci] + seg_tot[ci / kFbScanSeg] + (rr - (int)L.start[d]);
                 if (pos < 0 || pos >= n) {
                     atomicOr(err, 1);
                     continue;
@@ -187,6 +215,7 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
                     vout[pos] = L.val[e];
                 }
             }
+            }  // blocks of the task
             signal_done(&st->scatter_done[p]);
         }
     }
