@@ -304,6 +304,22 @@ __device__ inline int32_t gfind(int32_t* parent, int32_t x, int32_t* err)
     }
 }
 
+// Root of x once no union runs any more (after the last kernel that links):
+// plain, cacheable loads, and no path writes.  Every value read is an
+// ancestor, so the walk ends at the root.
+__device__ inline int32_t gfind_final(const int32_t* __restrict__ parent, int32_t x, int32_t* err)
+{
+    while (true) {
+        const int32_t p = parent[x];
+        if (p == x) return x;
+        if (p < 0 || p > x) {
+            atomicOr(err, 1);
+            return x;
+        }
+        x = p;
+    }
+}
+
 __device__ inline void gunion(int32_t* parent, int32_t a, int32_t b, int32_t* err)
 {
     while (true) {

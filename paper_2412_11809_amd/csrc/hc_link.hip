@@ -700,7 +700,7 @@ __global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __res
         const int64_t i = base + q * kScanThreads + t;
         bool root = false;
         if (i < end) {
-            const int32_t r = gfind(w.gparent, (int32_t)i, &w.status->err_internal);
+            const int32_t r = gfind_final(w.gparent, (int32_t)i, &w.status->err_internal);
             labels[i] = r;
             root = (r == (int32_t)i);
         }
