@@ -63,7 +63,7 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.n_scan_blocks = (int32_t)nt[3];
     x.n_fb_blocks = (int32_t)((n + kFbBlock - 1) / kFbBlock);
     x.edge_cap = (int64_t)x.n_link_tiles * kLinkHaloCap;
-    x.carry_cap = n;
+    x.carry_cap = (int64_t)x.n_feat_tiles * kFeatHash;
 
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -96,9 +96,11 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.link_h0 = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.gparent = (int32_t*)take(4 * N);
     x.edges = (int2*)take(sizeof(int2) * (size_t)x.edge_cap);
+    x.tile_nedge = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.overflow_tiles = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.slots = (SlotRec*)take(sizeof(SlotRec) * N);
     x.carries = (SlotRec*)take(sizeof(SlotRec) * (size_t)x.carry_cap);
+    x.tile_ncarry = (int32_t*)take(4 * (size_t)x.n_feat_tiles);
     x.blk_count = (uint32_t*)take(4 * (size_t)x.n_scan_blocks);
     x.blk_off = (uint32_t*)take(4 * (size_t)x.n_scan_blocks + 4);
     x.root_mask = (unsigned long long*)take(8 * (size_t)x.n_scan_blocks * (kScanBlock / 64));

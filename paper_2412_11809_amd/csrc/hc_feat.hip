@@ -133,9 +133,8 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     }
     __syncthreads();
     // Records: the owner tile writes the cluster's slot; every other tile
-    // queues a carry.  Carry positions come from one counter per work-group
-    // (a block scan of the per-thread counts, then a single global atomic),
-    // not one global atomic per carry.
+    // queues a carry in its own region of kFeatHash entries (positions from a
+    // block scan of the per-thread counts), with no global counter.
     constexpr int SPT = kFeatHash / kFeatThreads;  // hash entries per thread
     uint32_t nc = 0;
 #pragma unroll
@@ -144,12 +143,10 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         nc += (h_key[s] != 0u && !a_own[s]) ? 1u : 0u;
     }
     __shared__ uint32_t wsum[kFeatThreads / kWave];
-    __shared__ int32_t s_base;
     uint32_t total;
     uint32_t pos = block_exclusive_scan<kFeatThreads>(nc, wsum, &total);
-    if (t == 0) s_base = total ? atomicAdd(&w.status->n_carries, (int32_t)total) : 0;
-    __syncthreads();
-    const int64_t base = s_base;
+    if (t == 0) w.tile_ncarry[tile] = (int32_t)total;
+    const int64_t base = (int64_t)tile * kFeatHash;
 #pragma unroll
     for (int k = 0; k < SPT; k++) {
         const int s = t + k * kFeatThreads;
@@ -169,9 +166,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         if (a_own[s]) {
             w.slots[key - 1u] = r;
         } else {
-            const int64_t c = base + pos++;
-            if (c < w.carry_cap) w.carries[c] = r;
-            else atomicOr(&w.status->err_internal, 1);
+            w.carries[base + pos++] = r;  // pos < kFeatHash: one entry per hash slot at most
         }
     }
 }
@@ -183,32 +178,37 @@ hipError_t launch_features(const Work& w, const int32_t* labels, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_carries(Work w)
+// Folds every tile's carries into the owners' records (64-bit atomics):
+// one work-group per feature tile (grid-stride), most tiles have none.
+__global__ __launch_bounds__(64) void k_carries(Work w)
 {
     if (w.status->err_range) return;
-    const int64_t nc = w.status->n_carries < w.carry_cap ? w.status->n_carries : w.carry_cap;
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
-        const SlotRec r = w.carries[c];
-        if (r.root < 0 || r.root >= w.n) {
-            atomicOr(&w.status->err_internal, 1);
-            continue;
+    for (int64_t k = blockIdx.x; k < w.n_feat_tiles; k += gridDim.x) {
+        const int nc = w.tile_ncarry[k];
+        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+            const SlotRec r = w.carries[k * kFeatHash + c];
+            if (r.root < 0 || r.root >= w.n) {
+                atomicOr(&w.status->err_internal, 1);
+                continue;
+            }
+            SlotRec* d = w.slots + r.root;
+            atomicAdd(&d->size, r.size);
+            atomicAdd((unsigned long long*)&d->sum_tot, (unsigned long long)r.sum_tot);
+            atomicAdd((unsigned long long*)&d->sum_xt, (unsigned long long)r.sum_xt);
+            atomicAdd((unsigned long long*)&d->sum_yt, (unsigned long long)r.sum_yt);
+            atomicAdd((unsigned long long*)&d->sum_x, (unsigned long long)r.sum_x);
+            atomicAdd((unsigned long long*)&d->sum_y, (unsigned long long)r.sum_y);
+            atomicMin((unsigned long long*)&d->toa_min, (unsigned long long)r.toa_min);
+            atomicMax((unsigned long long*)&d->toa_max, (unsigned long long)r.toa_max);
         }
-        SlotRec* d = w.slots + r.root;
-        atomicAdd(&d->size, r.size);
-        atomicAdd((unsigned long long*)&d->sum_tot, (unsigned long long)r.sum_tot);
-        atomicAdd((unsigned long long*)&d->sum_xt, (unsigned long long)r.sum_xt);
-        atomicAdd((unsigned long long*)&d->sum_yt, (unsigned long long)r.sum_yt);
-        atomicAdd((unsigned long long*)&d->sum_x, (unsigned long long)r.sum_x);
-        atomicAdd((unsigned long long*)&d->sum_y, (unsigned long long)r.sum_y);
-        atomicMin((unsigned long long*)&d->toa_min, (unsigned long long)r.toa_min);
-        atomicMax((unsigned long long*)&d->toa_max, (unsigned long long)r.toa_max);
     }
 }
 
 hipError_t launch_carries(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("carries", s);
-    hipLaunchKernelGGL(k_carries, dim3(256), dim3(256), 0, s, w);
+    const int grid = w.n_feat_tiles < 8192 ? (w.n_feat_tiles > 0 ? w.n_feat_tiles : 1) : 8192;
+    hipLaunchKernelGGL(k_carries, dim3(grid), dim3(64), 0, s, w);
     return hipGetLastError();
 }
 

@@ -72,9 +72,7 @@ struct Status {
     int32_t err_range;      // a hit lies outside the sensor
     int32_t sort_fallback;  // tile sort/merge could not order the input
     int32_t n_overflow;     // link tiles whose halo did not fit
-    int32_t n_edges;        // cross-tile unions queued by the link kernel
-    int32_t n_carries;      // partial features queued for atomic merging
-    int32_t scan_ticket;    // compaction block ticket
+    int32_t unused_[3];
     int32_t err_internal;   // an index derived from device data was out of range
     int32_t err_span;       // batch sort fallback: a chunk's ToA span too large
     int32_t pad_[8];
@@ -123,8 +121,8 @@ struct Work {
     int32_t n_feat_tiles;
     int32_t n_scan_blocks;
     int32_t n_fb_blocks;
-    int64_t edge_cap;
-    int64_t carry_cap;
+    int64_t edge_cap;        // kLinkHaloCap cross-tile edges per link tile
+    int64_t carry_cap;       // kFeatHash carries per feature tile
 
     Status* status;
     TileInfo* tiles;
@@ -138,9 +136,11 @@ struct Work {
     int32_t* link_h0;     // per link tile: first halo position, or -1 if it overflows
     int32_t* gparent;
     int2* edges;
+    int32_t* tile_nedge;     // cross-tile edges of every link tile
     int32_t* overflow_tiles;
     SlotRec* slots;
     SlotRec* carries;
+    int32_t* tile_ncarry;    // carries of every feature tile
     uint32_t* blk_count;              // roots per block of kScanBlock indices
     uint32_t* blk_off;                // exclusive scan of blk_count
     unsigned long long* root_mask;    // one bit per input index: labels[i] == i

@@ -87,7 +87,7 @@ hipError_t launch_link_halo(const Work& w, hipStream_t s)
 // the tree's tile hits, and as cross-tile edges for its halo hits.
 // minidx: LDS scratch of L words (the caller's ToA array, no longer read).
 template <int PER, int LPER>
-__device__ inline void link_union_publish(const Work& w, int32_t* l_par, int (&cand)[PER][9],
+__device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_par, int (&cand)[PER][9],
                                           const int32_t (&ids)[LPER], int hl, int L, int32_t* minidx)
 {
     const int t = threadIdx.x;
@@ -132,8 +132,8 @@ __device__ inline void link_union_publish(const Work& w, int32_t* l_par, int (&c
         if (root[q] >= 0) atomicMin(&minidx[root[q]], ids[q]);
     }
     __syncthreads();
-    // halo hits joined by this tile become cross-tile edges; their positions
-    // come from one reservation per work-group (block scan + one atomic)
+    // halo hits joined by this tile become cross-tile edges, in the tile's
+    // own region of kLinkHaloCap entries (positions from a block scan)
     int32_t m[LPER];
     uint32_t ne = 0;
 #pragma unroll
@@ -143,11 +143,10 @@ __device__ inline void link_union_publish(const Work& w, int32_t* l_par, int (&c
         ne += (i < hl && ids[q] != m[q]) ? 1u : 0u;
     }
     __shared__ uint32_t e_wsum[kLinkThreads / kWave];
-    __shared__ int32_t e_base;
     uint32_t n_tile_edges;
     uint32_t pos = block_exclusive_scan<kLinkThreads>(ne, e_wsum, &n_tile_edges);
-    if (t == 0) e_base = n_tile_edges ? atomicAdd(&w.status->n_edges, (int32_t)n_tile_edges) : 0;
-    __syncthreads();
+    if (t == 0) w.tile_nedge[tile] = (int32_t)n_tile_edges;
+    const int64_t e_base = (int64_t)tile * kLinkHaloCap;
 #pragma unroll
     for (int q = 0; q < LPER; q++) {
         const int i = t + q * kLinkThreads;
@@ -155,9 +154,7 @@ __device__ inline void link_union_publish(const Work& w, int32_t* l_par, int (&c
         if (i >= hl) {
             w.gparent[ids[q]] = m[q];
         } else if (ids[q] != m[q]) {
-            const int64_t e = (int64_t)e_base + pos++;
-            if (e < w.edge_cap) w.edges[e] = make_int2(ids[q], m[q]);
-            else atomicOr(&w.status->err_internal, 1);
+            w.edges[e_base + pos++] = make_int2(ids[q], m[q]);  // pos < hl <= kLinkHaloCap
         }
     }
 }
@@ -257,6 +254,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         if (t == 0) {
             const int k = atomicAdd(&w.status->n_overflow, 1);
             w.overflow_tiles[k] = tile;
+            w.tile_nedge[tile] = 0;
         }
         return;
     }
@@ -457,7 +455,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
     }
 
     }  // pixel index
-    link_union_publish(w, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
+    link_union_publish(w, tile, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
 // Same contract as k_link, without a pixel index: the latest earlier hit at
@@ -498,6 +496,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link_window(Work w)
         if (t == 0) {
             const int k = atomicAdd(&w.status->n_overflow, 1);
             w.overflow_tiles[k] = tile;
+            w.tile_nedge[tile] = 0;
         }
         return;
     }
@@ -545,7 +544,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link_window(Work w)
     }
     int cand[PER][9];
     link_window_search<PER>(l_toa, l_xy, hl, L, lo, cand);
-    link_union_publish(w, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
+    link_union_publish(w, tile, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
 // The window-scan kernel, or the per-tile hybrid / pixel-index kernel.
@@ -663,20 +662,24 @@ hipError_t launch_link_fallback(const Work& w, hipStream_t s)
 }
 
 // ------------------------------------------------- cross-tile unions
-__global__ void k_union_edges(Work w)
+// Cross-tile unions: one work-group per link tile's edge region (grid-stride).
+__global__ __launch_bounds__(64) void k_union_edges(Work w)
 {
     if (w.status->err_range) return;
-    const int64_t ne = w.status->n_edges < w.edge_cap ? w.status->n_edges : w.edge_cap;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
-        const int2 ed = w.edges[e];
-        gunion(w.gparent, ed.x, ed.y, &w.status->err_internal);
+    for (int64_t k = blockIdx.x; k < w.n_link_tiles; k += gridDim.x) {
+        const int ne = w.tile_nedge[k];
+        for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+            const int2 ed = w.edges[k * kLinkHaloCap + e];
+            gunion(w.gparent, ed.x, ed.y, &w.status->err_internal);
+        }
     }
 }
 
 hipError_t launch_union_edges(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("union_edges", s);
-    hipLaunchKernelGGL(k_union_edges, dim3(256), dim3(256), 0, s, w);
+    const int grid = w.n_link_tiles < 8192 ? (w.n_link_tiles > 0 ? w.n_link_tiles : 1) : 8192;
+    hipLaunchKernelGGL(k_union_edges, dim3(grid), dim3(64), 0, s, w);
     return hipGetLastError();
 }
 

@@ -34,8 +34,6 @@ __global__ void k_init(Work w)
     int32_t* s = reinterpret_cast<int32_t*>(w.status);
     for (int i = t; i < (int)(sizeof(Status) / 4); i += stride) s[i] = 0;
     if (t == 0 && w.force_fallback) w.status->sort_fallback = 1;
-    if (w.n_seg > 1)
-        for (int i = t; i < w.n_seg; i += stride) w.segs[i].toa_min = ~0ull;
 }
 
 hipError_t launch_init(const Work& w, hipStream_t s)
@@ -83,7 +81,6 @@ __global__ __launch_bounds__(NT) void k_tile_sort(const hc_hit* __restrict__ hit
     if (bad) atomicOr(&w.status->err_range, 1);
     tmin = block_min_u64<NT>(tmin, red);
     tmax = block_max_u64<NT>(tmax, red);
-    if (w.n_seg > 1 && t == 0) atomicMin((unsigned long long*)&w.segs[tr.seg].toa_min, (unsigned long long)tmin);
     const uint64_t range = tmax - tmin;
     if (range > 0xFFFFFFFFull) {
         if (t == 0) {
@@ -341,6 +338,18 @@ struct ToaSortJob {
     __device__ int plan(RadixState& st, RadixLds& L)
     {
         __shared__ uint64_t red[kFbThreads / kWave];
+        if (w.n_seg > 1) {  // every chunk's smallest ToA: the minimum of its tiles' minima
+            for (int sg = threadIdx.x; sg < w.n_seg; sg += kFbThreads) {
+                const SegInfo& si = w.segs[sg];
+                const int t0 = si.tile0[kSortKind];
+                const int t1 = t0 + (si.count + w.sort_tile - 1) / w.sort_tile;
+                uint64_t m = ~0ull;
+                for (int i = t0; i < t1; i++) m = w.tiles[i].base < m ? w.tiles[i].base : m;
+                w.segs[sg].toa_min = m;
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
         uint64_t mn = ~0ull, mx = 0;
         for (int i = threadIdx.x; i < w.n_sort_tiles; i += kFbThreads) {
             const TileInfo ti = w.tiles[i];
