@@ -40,9 +40,7 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.xcd_map = 1;
     x.link_mode = 0;
     const int64_t D = disorder ? disorder : 4096;
-    int T = 8192;
-    if (2 * D <= 2048) T = 2048;
-    else if (2 * D <= 4096) T = 4096;
+    const int T = sort_tile_for(D);
     x.sort_tile = T;
     x.sort_ipt = T / kSortThreads;
     int64_t m = (2 * D + T - 1) / T;

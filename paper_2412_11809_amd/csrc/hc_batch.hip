@@ -187,7 +187,7 @@ int hc_cluster_batch(const hc_hit* hits, const int64_t* offsets, int32_t n_chunk
 int hc_batch_plan_describe(const hc_batch_plan* plan, char* buf, size_t cap)
 {
     if (!plan || !buf || cap == 0) return set_error(HC_ERR_ARG, "NULL plan or buffer");
-    const int T = 2 * (int64_t)plan->disorder_hint <= 2048 ? 2048 : 2 * (int64_t)plan->disorder_hint <= 4096 ? 4096 : 8192;
+    const int T = sort_tile_for(plan->disorder_hint ? plan->disorder_hint : 4096);
     snprintf(buf, cap, "disorder_hint=%u sort_tile=%d xcd_map=%d link=%s time_ms=%.4f", plan->disorder_hint, T,
              plan->xcd_map, plan->link_mode == 1 ? "index" : plan->link_mode == 2 ? "window" : "hybrid",
              plan->time_ms);

@@ -178,6 +178,17 @@ int enqueue_cluster(const hc_hit* hits, const Work& w, int32_t* labels, hc_featu
                     int32_t* n_clusters, hipStream_t s);
 // Record an error for hc_last_error and return its code.
 int set_error(int code, const std::string& msg);
+// Sort tile for a displacement hint D: tiles of T hits ranked against
+// m = ceil(2D / T) neighbour tiles per side.  4096-hit tiles with up to two
+// neighbours measured faster than 8192-hit tiles with one (smaller LDS
+// footprint, more work-groups per CU).
+inline int sort_tile_for(int64_t D)
+{
+    if (2 * D <= 2048) return 2048;
+    if (2 * D <= 8192) return 4096;
+    return 8192;
+}
+
 // hc_opts.flags: at most one HC_FLAG_LINK_* value; the Work.link_mode it selects.
 inline bool link_flags_valid(uint32_t f)
 {
