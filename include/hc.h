@@ -83,13 +83,11 @@ typedef struct {
     void* stream;            /* hipStream_t to run on; NULL = null stream */
 } hc_opts;
 
-/* Neighbour search variant (results are identical).  By default, on sensors
- * of up to 256 x 256 pixels each tile picks by its hits' dt windows: short
- * windows are scanned backwards, long ones (dense showers) go through a pixel
- * index (occupancy bitmap + per-pixel lists); larger sensors scan windows.
- * The flags force one of the two for every tile.  The window scan needs
- * sensors up to 16384 x 16384, the pixel index one of at most 448 x 512
- * pixels' worth of bitmap (larger sensors take a slower path). */
+/* Neighbour search variant (results are identical).  By default every tile
+ * goes through a pixel index (occupancy bitmap + per-pixel lists in LDS) when
+ * the sensor has at most 448 x 512 pixels, and scans each hit's dt window
+ * backwards on larger sensors (up to 16384 x 16384; beyond both, tiles take
+ * a slower path).  The flags force one of the two for every tile. */
 #define HC_FLAG_LINK_PIXEL_INDEX 1u
 #define HC_FLAG_LINK_WINDOW 2u
 

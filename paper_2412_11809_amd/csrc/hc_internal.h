@@ -16,8 +16,6 @@ constexpr int kSortThreads = 512;     // threads of the tile-sort / merge kernel
 constexpr int kLinkTile = 1024;       // sorted hits per link work-group
 constexpr int kLinkHaloCap = 1024;    // earlier hits a link work-group can hold
 constexpr uint32_t kLinkWindowMaxDim = 16384;  // window scan: coordinates fit 14 bits
-constexpr int kLinkWindowMeanCost = 16;        // a tile scans its windows below this many slots per hit
-constexpr uint64_t kLinkHybridMaxPixels = 65536; // larger sensors: window scan (bitmap LDS would cut occupancy)
 constexpr int kLinkThreads = 512;
 
 
@@ -228,12 +226,8 @@ struct TimedLaunch {
 }  // namespace hc
 
 namespace hc {
-// Occupancy bitmap of the link kernel: one bit per sensor pixel, plus one
-// prefix count per word (dynamic LDS of 8 bytes per word).  Sensors with more
-// than kLinkMaxPixels pixels send every tile to the fallback.
+// Occupancy bitmap of the link kernel's pixel index: one bit per sensor pixel
+// plus a 16-bit prefix count per 64-bit word, in dynamic LDS (2.25 bits per
+// pixel).  Sensors with more than kLinkMaxPixels pixels cannot use the index.
 constexpr uint64_t kLinkMaxPixels = 448ull * 512ull;
-inline int link_bitmap_words(uint32_t width, uint32_t height)
-{
-    return (int)(((uint64_t)width * height + 31) / 32);
-}
 }  // namespace hc

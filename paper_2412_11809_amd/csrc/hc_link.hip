@@ -10,40 +10,38 @@
 // and works entirely in LDS:
 //   * an occupancy bitmap of the sensor and the popcount prefix of its words
 //     give every occupied pixel of the tile a dense rank, and a CSR lists the
-//     tile's hits per pixel rank in time order -- the tile-sized replacement
-//     of the paper's dense matrix;
-//   * each tile hit joins, at each of its 9 pixels, the latest earlier hit if
-//     it lies within dt (the hit the paper's matrix holds).  Hits of one pixel
-//     whose consecutive ToAs differ by <= dt are chained by their own-pixel
-//     probes, so this reaches every earlier hit within dt;
+//     tile's hits per pixel rank -- the tile-sized replacement of the paper's
+//     dense matrix;
+//   * each tile hit joins, at each of its 9 pixels, an earlier hit within dt
+//     (the paper's matrix holds the latest one; any gives the same clusters,
+//     see k_link);
 //   * the joins are applied in bulk rounds in an LDS forest whose roots are
 //     the earliest slots (the paper's time-ordered roots); the smallest input
 //     index of every tree is the label candidate written to the global parent
 //     array, and halo hits joined by the tile are queued as cross-tile edges.
-// A tile whose halo does not fit (or whose ToA span exceeds 32 bits) is
-// handled by k_link_fallback: a pixel-sorted copy of all hits plus binary
-// searches.  k_union_edges applies the queued cross-tile edges with atomic
-// compare-and-swap, and k_flatten writes labels[i] = root(i).
+// Sensors too large for the bitmap (or a caller's flag) use k_link_window,
+// which scans each hit's dt window instead.  A tile whose halo does not fit
+// (or whose ToA span exceeds 32 bits) is handled by k_link_fallback: a
+// pixel-sorted copy of all hits plus binary searches.  k_union_edges applies
+// the queued cross-tile edges with atomic compare-and-swap, and k_flatten
+// writes labels[i] = root(i).
 #include "hc_device.h"
 #include "hc_radix.h"
 
 namespace hc {
 
-// Which neighbour search runs: 0 = window scan only (k_link_window),
-// 1 = per tile, window scan or pixel index (k_link), 2 = pixel index only
-// (k_link).  The window scan needs coordinates below 2^14, the pixel index
-// room for the sensor's occupancy bitmap in LDS.
-enum { kLinkWindowOnly = 0, kLinkHybrid = 1, kLinkIndexOnly = 2 };
+// Which neighbour search runs: the pixel index (k_link) whenever the
+// sensor's occupancy bitmap fits in LDS, else the window scan (k_link_window,
+// coordinates below 2^14); a caller's flag can force either.  The index is
+// faster on every stream measured, sparse or dense, so it is the default.
+enum { kLinkWindow = 0, kLinkIndex = 1 };
 __host__ __device__ inline int link_kernel(const Work& w)
 {
     const bool win_ok = w.width <= kLinkWindowMaxDim && w.height <= kLinkWindowMaxDim;
     const bool idx_ok = (uint64_t)w.width * w.height <= kLinkMaxPixels;
-    if (w.link_mode == 1 || !win_ok) return kLinkIndexOnly;
-    if (w.link_mode == 2 || !idx_ok) return kLinkWindowOnly;
-    // beyond 256 x 256 pixels the bitmap leaves room for one work-group per
-    // CU, which costs every tile more than scanning its windows
-    if (w.link_mode == 0 && (uint64_t)w.width * w.height > kLinkHybridMaxPixels) return kLinkWindowOnly;
-    return kLinkHybrid;
+    if (w.link_mode == 1 || !win_ok) return kLinkIndex;
+    if (w.link_mode == 2 || !idx_ok) return kLinkWindow;
+    return kLinkIndex;
 }
 
 // First halo position of every link tile: the earliest sorted position p
@@ -68,7 +66,7 @@ __global__ void k_link_halo(Work w)
     }
     bool overflow = (a == lim && lim > tr.seg_start && w.s_toa[lim - 1] >= lo);
     overflow |= (w.s_toa[p1 - 1] - w.s_toa[a]) > 0xFFFFFFFFull;
-    overflow |= link_kernel(w) != kLinkWindowOnly && (uint64_t)w.width * w.height > kLinkMaxPixels;  // no bitmap room
+    overflow |= link_kernel(w) == kLinkIndex && (uint64_t)w.width * w.height > kLinkMaxPixels;  // no bitmap room
     w.link_h0[k] = overflow ? -1 : (int32_t)a;
 }
 
@@ -109,14 +107,17 @@ __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_pa
             }
         }
         __syncthreads();
+        // every slot walks to its root, shortening its own pointer at each
+        // step: the walks of later slots on the same path reuse those jumps
+        // (a pointer only ever moves to an ancestor, so any value read is valid)
         for (int x = t; x < L; x += kLinkThreads) {
             int p = l_par[x];
             while (true) {
                 const int g = l_par[p];
                 if (g == p) break;
+                l_par[x] = g;
                 p = g;
             }
-            l_par[x] = p;
         }
         if (!__syncthreads_or(changed)) break;
     }
@@ -195,46 +196,64 @@ __device__ inline void link_window_search(const uint32_t* l_toa, const uint32_t*
     }
 }
 
+// x, y of a pixel id p = y * W + x.  16-bit ids (sensors of at most 2^16
+// pixels) divide by multiplying with magic = ceil(2^32 / W), exact for every
+// p < 2^16 because the rounding error of magic times p stays below 2^32.
+template <typename PixT>
+__device__ inline void pix_xy(uint32_t p, uint32_t W, uint32_t magic, int& x, int& y)
+{
+    const uint32_t q = sizeof(PixT) == 2 ? (W > 1 ? __umulhi(p, magic) : p) : p / W;
+    y = (int)q;
+    x = (int)(p - q * W);
+}
+
+// Dense rank (in pixel order) of an occupied pixel: set bits before it in the
+// occupancy bitmap, from the 16-bit prefix count of its 64-bit word.
+__device__ inline uint32_t pix_rank(uint32_t p, const uint64_t* bm, const uint16_t* wpre)
+{
+    const uint32_t wd = p >> 6;
+    return wpre[wd] + (uint32_t)__popcll(bm[wd] & ((1ull << (p & 63u)) - 1ull));
+}
+
 // One work-group per tile of kLinkTile sorted hits (+ halo), all in LDS.
 //
 // Local slots 0..L-1 are the sorted positions h0..p1-1, so a smaller slot is
-// an earlier hit.  The paper's per-pixel "last hit" matrix is replaced by a
-// tile-sized index of the occupied pixels:
-//   * an occupancy bitmap of the sensor plus the popcount prefix of its words
-//     gives every occupied pixel a dense rank (pixel order) without hashing;
-//   * a CSR lists, per occupied pixel, the slots of its hits in ascending
-//     order, so the three pixels of a neighbour row are three consecutive
-//     segments and the latest earlier hit at a pixel is found by stepping back
-//     from its segment's end (usually one step).
-// Each tile hit joins, for each of its (up to) 9 neighbour pixels, the latest
-// earlier hit there if it lies within dt -- the hit the paper's matrix would
-// hold.  Joins are applied in bulk rounds (hook the larger root under the
-// smaller with an atomic minimum, then jump pointers until every tree is a
-// star) in an LDS forest whose roots are the earliest slots, as in the paper's
-// time-ordered forest.  The smallest input index of every local tree is then
-// published as the label candidate of its tile hits; halo hits joined by the
-// tile become cross-tile edges.
-// Dynamic LDS: bitmap (bm_words words) followed by the 16-bit word prefix
-// counts.  LDS is kept near 53 KiB (256 x 256 sensor) so three work-groups
-// share a CU.
-__global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
+// an earlier hit.  A tile-sized index of the occupied pixels replaces the
+// paper's per-pixel "last hit" matrix:
+//   * an occupancy bitmap of the sensor plus the popcount prefix of its 64-bit
+//     words gives every occupied pixel a dense rank (pixel order);
+//   * a CSR lists, per occupied pixel, the slots of its hits (in no particular
+//     order), so the three pixels of a neighbour row are three consecutive
+//     segments.
+// The matrix would join a hit to the LATEST earlier hit at each neighbour
+// pixel (within dt).  Joining it to ANY earlier hit there within dt gives the
+// same clusters: the hits of one pixel whose ToAs lie within one dt of each
+// other are always connected among themselves (each joins an earlier one
+// within dt, by induction over time), and the latest earlier hit and the one
+// chosen both lie in the dt before the joining hit.  So the index needs no
+// order inside a pixel's list: the first entry of the segment that is earlier
+// and within dt is taken (usually the only entry).
+// link_union_publish then applies the joins and publishes the labels.
+// Hits are kept as pixel ids (16-bit up to 2^16 pixels): with the 64-bit
+// word prefixes the tile's LDS stays below 40 KiB on a 256 x 256 sensor, so
+// four work-groups share a CU (the kernel is latency bound: occupancy is what
+// speeds it up).  Dynamic LDS: the bitmap (bm64 words), then the prefixes.
+template <typename PixT>
+__global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint32_t magic)
 {
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
     constexpr int PER = kLinkTile / kLinkThreads;
     constexpr int LPER = LCAP / kLinkThreads;
-    constexpr uint16_t kUnsorted = 0x8000u;
-    __shared__ uint32_t l_toa[LCAP];
-    __shared__ uint32_t l_xy[LCAP];
+    __shared__ uint32_t l_toa[LCAP];      // ToA - tile base; then minima
+    __shared__ PixT l_pix[LCAP];          // pixel id y * W + x
     __shared__ int32_t l_par[LCAP];
-    __shared__ uint16_t l_rank[LCAP];     // hit's rank among its pixel's hits, then root
-    __shared__ uint16_t l_pixr[LCAP];     // hit's pixel rank
     __shared__ uint16_t csr[LCAP];        // slots grouped by pixel rank
-    __shared__ uint16_t pstart[LCAP + 2]; // count (packed in pairs), then first CSR position per pixel rank [| kUnsorted]
+    __shared__ uint16_t pstart[LCAP + 2]; // counts (packed in pairs), then end of each rank's CSR segment
     __shared__ uint32_t wsum[kLinkThreads / kWave];
-    __shared__ uint32_t s_cost;
-    extern __shared__ uint32_t dyn[];
-    uint32_t* bm = dyn;
-    uint16_t* wpre = reinterpret_cast<uint16_t*>(dyn + bm_words);
+    extern __shared__ uint64_t dyn64[];
+    uint64_t* bm = dyn64;
+    uint32_t* bm32 = reinterpret_cast<uint32_t*>(dyn64);
+    uint16_t* wpre = reinterpret_cast<uint16_t*>(dyn64 + bm64);
     uint32_t* pcount = reinterpret_cast<uint32_t*>(pstart);  // two 16-bit counters per word
 
     if (w.status->err_range) return;
@@ -270,7 +289,8 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
         if (i < L) {
             const int64_t p = h0 + i;
             l_toa[i] = (uint32_t)(w.s_toa[p] - tbase);
-            l_xy[i] = w.s_xy[p];
+            const uint32_t xy = w.s_xy[p];
+            l_pix[i] = (PixT)((xy >> 16) * W + (xy & 0xFFFFu));
             l_par[i] = i;
             int32_t id = w.s_idx[p];
             if (id < 0 || id >= w.n) {
@@ -280,181 +300,133 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Work w, int bm_words)
             ids[q] = id;
         }
     }
-    if (t == 0) s_cost = 0u;
     __syncthreads();
 
-    // ---- the dt window of every tile hit (slots [lo, i)) and what scanning
-    // the windows would cost: per wave, the longest window of each step
     const uint64_t dt = seg_dt(w, tr.seg);
-    const int lane = t & (kWave - 1);
-    int lo[PER];
-    uint32_t cost = 0;
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-        const int i = hl + t + q * kLinkThreads;
-        lo[q] = i;
-        if (i < L) {
-            const uint32_t ti = l_toa[i];
-            int a = 0;
-            if (dt < (uint64_t)ti) {
-                const uint32_t th = ti - (uint32_t)dt;
-                int b = i;
-                while (a < b) {
-                    const int m = (a + b) >> 1;
-                    if (l_toa[m] < th) a = m + 1; else b = m;
-                }
-            }
-            lo[q] = a;
-        }
-        uint32_t win = (uint32_t)(i < L ? i - lo[q] : 0);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint32_t v = __shfl_xor(win, o, kWave);
-            win = v > win ? v : win;
-        }
-        cost += win;
-    }
-    if (lane == 0) atomicAdd(&s_cost, cost * kWave);
-    __syncthreads();
-    // short windows (sparse hits): scan them; long ones (showers): pixel index
-    const bool window = link_kernel(w) == kLinkHybrid && s_cost <= (uint32_t)(kLinkWindowMeanCost * (L - hl));
     int cand[PER][9];
-    if (window) {
-        link_window_search<PER>(l_toa, l_xy, hl, L, lo, cand);
-    } else {
-    for (int i = t; i < bm_words; i += kLinkThreads) bm[i] = 0u;
-    for (int i = t; i < (LCAP + 2) / 2; i += kLinkThreads) pcount[i] = 0u;
-    __syncthreads();
-
-    // ---- occupancy bitmap
-    for (int i = t; i < L; i += kLinkThreads) {
-        const uint32_t xy = l_xy[i];
-        const uint32_t pix = (xy >> 16) * W + (xy & 0xFFFFu);
-        atomicOr(&bm[pix >> 5], 1u << (pix & 31u));
-    }
-    __syncthreads();
-    // ---- popcount prefix of the bitmap words (rank of the first pixel of a word)
     {
-        const int per = (bm_words + kLinkThreads - 1) / kLinkThreads;
-        const int w0 = t * per;
-        uint32_t c = 0;
-        for (int k = 0; k < per; k++)
-            if (w0 + k < bm_words) c += __popc(bm[w0 + k]);
-        uint32_t run = block_exclusive_scan<kLinkThreads>(c, wsum, nullptr);
-        for (int k = 0; k < per; k++)
-            if (w0 + k < bm_words) {
-                wpre[w0 + k] = (uint16_t)run;
-                run += __popc(bm[w0 + k]);
+        for (int i = t; i < bm64; i += kLinkThreads) bm[i] = 0ull;
+        for (int i = t; i < (LCAP + 2) / 2; i += kLinkThreads) pcount[i] = 0u;
+        __syncthreads();
+        // ---- occupancy bitmap
+        for (int i = t; i < L; i += kLinkThreads) {
+            const uint32_t p = l_pix[i];
+            atomicOr(&bm32[p >> 5], 1u << (p & 31u));
+        }
+        __syncthreads();
+        // ---- popcount prefix of the 64-bit bitmap words
+        {
+            const int per = (bm64 + kLinkThreads - 1) / kLinkThreads;
+            const int w0 = t * per;
+            uint32_t c = 0;
+            for (int k = 0; k < per; k++)
+                if (w0 + k < bm64) c += (uint32_t)__popcll(bm[w0 + k]);
+            uint32_t run = block_exclusive_scan<kLinkThreads>(c, wsum, nullptr);
+            for (int k = 0; k < per; k++)
+                if (w0 + k < bm64) {
+                    wpre[w0 + k] = (uint16_t)run;
+                    run += (uint32_t)__popcll(bm[w0 + k]);
+                }
+        }
+        __syncthreads();
+        // ---- hits per occupied pixel (counts stay below 2^16: no carry between halves)
+        for (int i = t; i < L; i += kLinkThreads) {
+            const uint32_t r = pix_rank(l_pix[i], bm, wpre);
+            atomicAdd(&pcount[r >> 1], 1u << (16u * (r & 1u)));
+        }
+        __syncthreads();
+        // ---- exclusive scan of the counts -> first CSR position per pixel rank
+        {
+            uint32_t c[LPER];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int k = 0; k < LPER; k++) {
+                c[k] = pstart[t * LPER + k];
+                sum += c[k];
             }
-    }
-    __syncthreads();
-    // ---- per-pixel counts (the atomic returns each hit's rank in its pixel)
-    for (int i = t; i < L; i += kLinkThreads) {
-        const uint32_t xy = l_xy[i];
-        const uint32_t pix = (xy >> 16) * W + (xy & 0xFFFFu);
-        const uint32_t wd = pix >> 5;
-        const uint32_t r = wpre[wd] + __popc(bm[wd] & ((1u << (pix & 31u)) - 1u));
-        l_pixr[i] = (uint16_t)r;
-        const uint32_t half = 16u * (r & 1u);  // counts stay below 2^16: no carry into the neighbour
-        l_rank[i] = (uint16_t)(atomicAdd(&pcount[r >> 1], 1u << half) >> half);
-    }
-    __syncthreads();
-    // ---- exclusive scan of the counts -> first CSR position per pixel rank
-    {
-        uint32_t c[LPER];
-        uint32_t sum = 0;
+            uint32_t run = block_exclusive_scan<kLinkThreads>(sum, wsum, nullptr);
 #pragma unroll
-        for (int k = 0; k < LPER; k++) {
-            c[k] = pstart[t * LPER + k];
-            sum += c[k];
-        }
-        uint32_t run = block_exclusive_scan<kLinkThreads>(sum, wsum, nullptr);
-#pragma unroll
-        for (int k = 0; k < LPER; k++) {
-            pstart[t * LPER + k] = (uint16_t)run;
-            run += c[k];
-        }
-        if (t == kLinkThreads - 1) pstart[LCAP] = (uint16_t)run;
-    }
-    __syncthreads();
-    for (int i = t; i < L; i += kLinkThreads) csr[pstart[l_pixr[i]] + l_rank[i]] = (uint16_t)i;
-    __syncthreads();
-    // ---- sort every pixel's segment by slot (segments are short; a pile-up
-    // of more than 64 hits on one pixel is left unsorted and scanned instead)
-    for (int r = t; r < LCAP; r += kLinkThreads) {
-        // a neighbouring thread may already have flagged pstart[r + 1]
-        const int s0 = (int)(pstart[r] & ~kUnsorted), s1 = (int)(pstart[r + 1] & ~kUnsorted);
-        const int cnt = s1 - s0;
-        if (cnt < 2) continue;
-        if (cnt > 64) {
-            pstart[r] = (uint16_t)(s0 | kUnsorted);
-            continue;
-        }
-        for (int a = s0 + 1; a < s1; a++) {
-            const uint16_t v = csr[a];
-            int b = a - 1;
-            while (b >= s0 && csr[b] > v) {
-                csr[b + 1] = csr[b];
-                b--;
+            for (int k = 0; k < LPER; k++) {
+                pstart[t * LPER + k] = (uint16_t)run;
+                run += c[k];
             }
-            csr[b + 1] = v;
         }
-    }
-    __syncthreads();
-
-    // ---- neighbour search: latest earlier hit per neighbour pixel
-    const int H = (int)w.height;
+        __syncthreads();
+        // ---- fill: each hit takes the next position of its pixel's segment;
+        // afterwards pstart[r] is the end of segment r (its start is pstart[r - 1])
+        for (int i = t; i < L; i += kLinkThreads) {
+            const uint32_t r = pix_rank(l_pix[i], bm, wpre);
+            const uint32_t half = 16u * (r & 1u);
+            const uint32_t pos = (atomicAdd(&pcount[r >> 1], 1u << half) >> half) & 0xFFFFu;
+            csr[pos] = (uint16_t)i;
+        }
+        __syncthreads();
+        // ---- neighbour search: an earlier hit within dt per neighbour pixel.
+        // Branch-free stages, so the LDS reads of all 9 pixels overlap: the
+        // three rows' bitmap bits and first ranks, the 9 segment bounds, the
+        // segments' first entries, their ToAs.  Empty pixels read slot 0 and
+        // discard it.  Only a segment whose first entry does not qualify
+        // (a pixel hit more than once in the tile) is walked further.
+        const int H = (int)w.height;
+        const uint32_t dt32 = dt < 0xFFFFFFFFull ? (uint32_t)dt : 0xFFFFFFFFu;
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
+        for (int q = 0; q < PER; q++) {
 #pragma unroll
-        for (int k = 0; k < 9; k++) cand[q][k] = -1;
-        const int i = hl + t + q * kLinkThreads;
-        if (i >= L) continue;
-        const uint32_t xy = l_xy[i];
-        const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
-        const uint32_t ti = l_toa[i];
-        const int xlo = x > 0 ? x - 1 : 0;
-        const int xhi = x + 1 < (int)W ? x + 1 : (int)W - 1;
-        const uint32_t rowmask = (1u << (xhi - xlo + 1)) - 1u;
+            for (int k = 0; k < 9; k++) cand[q][k] = -1;
+            const int i = hl + t + q * kLinkThreads;
+            if (i >= L) continue;
+            int x, y;
+            pix_xy<PixT>(l_pix[i], W, magic, x, y);
+            const uint32_t ti = l_toa[i];
+            const int xlo = x > 0 ? x - 1 : 0;
+            const int xhi = x + 1 < (int)W ? x + 1 : (int)W - 1;
+            const uint32_t rowmask = (1u << (xhi - xlo + 1)) - 1u;
+            uint32_t occ[3];
+            int rk0[3];
 #pragma unroll
-        for (int r = 0; r < 3; r++) {
-            const int qy = y - 1 + r;
-            if (qy < 0 || qy >= H) continue;
-            const uint32_t pa = (uint32_t)qy * W + (uint32_t)xlo;
-            const uint32_t wa = pa >> 5, sh = pa & 31u;
-            uint64_t bits = bm[wa];
-            if (sh > 29u && wa + 1 < (uint32_t)bm_words) bits |= (uint64_t)bm[wa + 1] << 32;
-            const uint32_t occ = (uint32_t)(bits >> sh) & rowmask;
-            if (!occ) continue;
-            // rank of the first occupied pixel of this row segment
-            int rk = (int)(wpre[wa] + __popc(bm[wa] & ((1u << sh) - 1u)));
+            for (int rr = 0; rr < 3; rr++) {
+                const int qy = y - 1 + rr;
+                const bool rowok = qy >= 0 && qy < H;
+                const uint32_t pa = rowok ? (uint32_t)qy * W + (uint32_t)xlo : 0u;
+                const uint32_t wa = pa >> 6, sh = pa & 63u;
+                const uint64_t b0 = bm[wa];
+                const uint64_t b1 = bm[(int)wa + 1 < bm64 ? wa + 1 : wa];
+                uint64_t bits = b0 >> sh;
+                if (sh > 61u) bits |= b1 << (64u - sh);
+                occ[rr] = rowok ? (uint32_t)bits & rowmask : 0u;
+                rk0[rr] = (int)(wpre[wa] + (uint32_t)__popcll(b0 & ((1ull << sh) - 1ull)));
+            }
+            int s0[9], s1[9];
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                if (!(occ & (1u << k))) continue;
-                const uint32_t st = pstart[rk];  // (16-bit entry)
-                const int s0 = (int)(st & ~kUnsorted), s1 = (int)(pstart[rk + 1] & ~kUnsorted);
-                rk++;
-                int a = -1;
-                if (!(st & kUnsorted)) {
-                    int j = s1 - 1;
-                    while (j >= s0 && (int)csr[j] >= i) j--;
-                    if (j >= s0) a = csr[j];
-                } else {
-                    for (int j = s0; j < s1; j++) {
-                        const int v = csr[j];
-                        if (v < i && v > a) a = v;
+            for (int d = 0; d < 9; d++) {
+                const uint32_t o = occ[d / 3];
+                const bool has = (o >> (d % 3)) & 1u;
+                const int r = has ? rk0[d / 3] + __popc(o & ((1u << (d % 3)) - 1u)) : 0;
+                const int e = pstart[r];
+                const int b = r ? (int)pstart[r - 1] : 0;
+                s0[d] = has ? b : 0;
+                s1[d] = has ? e : 0;
+            }
+            int v[9];
+#pragma unroll
+            for (int d = 0; d < 9; d++) v[d] = csr[s0[d] < s1[d] ? s0[d] : 0];
+#pragma unroll
+            for (int d = 0; d < 9; d++) {
+                const uint32_t tv = l_toa[v[d]];
+                if (s0[d] < s1[d] && v[d] < i && ti - tv <= dt32) {
+                    cand[q][d] = v[d];
+                } else if (s1[d] - s0[d] > 1) {
+                    for (int j = s0[d] + 1; j < s1[d]; j++) {
+                        const int u = csr[j];
+                        if (u < i && ti - l_toa[u] <= dt32) {
+                            cand[q][d] = u;
+                            break;
+                        }
                     }
                 }
-                if (a >= 0 && (uint64_t)(ti - l_toa[a]) <= dt) {
-#pragma unroll
-                    for (int kk = 0; kk < 9; kk++)
-                        if (kk == 3 * r + k) cand[q][kk] = a;
-                }
             }
         }
     }
-
-    }  // pixel index
     link_union_publish(w, tile, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
@@ -547,17 +519,22 @@ __global__ __launch_bounds__(kLinkThreads) void k_link_window(Work w)
     link_union_publish(w, tile, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
-// The window-scan kernel, or the per-tile hybrid / pixel-index kernel.
+// The pixel-index kernel, or the window-scan kernel.
 hipError_t launch_link(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("link", s);
     const dim3 grid(xcd_grid(w.n_link_tiles));
-    if (link_kernel(w) == kLinkWindowOnly) {
+    if (link_kernel(w) == kLinkWindow) {
         hipLaunchKernelGGL(k_link_window, grid, dim3(kLinkThreads), 0, s, w);
     } else {
-        const int bm_words = link_bitmap_words(w.width, w.height);
-        const size_t dyn = (size_t)bm_words * 4 + (((size_t)bm_words * 2 + 3) & ~(size_t)3);
-        hipLaunchKernelGGL(k_link, grid, dim3(kLinkThreads), dyn, s, w, bm_words);
+        const uint64_t pixels = (uint64_t)w.width * w.height;
+        const int bm64 = (int)((pixels + 63) / 64);
+        const size_t dyn = (size_t)bm64 * 8 + (((size_t)bm64 * 2 + 7) & ~(size_t)7);
+        const uint32_t magic = w.width > 1 ? (uint32_t)(((1ull << 32) + w.width - 1) / w.width) : 0u;
+        if (pixels <= 65536u)
+            hipLaunchKernelGGL(k_link<uint16_t>, grid, dim3(kLinkThreads), dyn, s, w, bm64, magic);
+        else
+            hipLaunchKernelGGL(k_link<uint32_t>, grid, dim3(kLinkThreads), dyn, s, w, bm64, magic);
     }
     return hipGetLastError();
 }

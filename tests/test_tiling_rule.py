@@ -1,4 +1,4 @@
-"""The neighbour rule the link kernel relies on, checked on the CPU.
+"""The neighbour rules the link kernels rely on, checked on the CPU.
 
 The kernel processes the ToA-sorted hits in tiles; every tile hit joins, at
 each pixel of its 3x3 neighbourhood, only the LATEST earlier hit there (if it
@@ -7,6 +7,10 @@ dt before the tile's first hit).  This is a restatement of the paper's sweep
 with a per-pixel "last hit" matrix (Section 4.1) cut into independent tiles.
 This test emulates exactly that rule in plain Python and compares the result
 with the oracle, at tile sizes small enough that many clusters cross tiles.
+The pixel-index kernel relaxes it further -- ANY earlier hit within dt at
+each neighbour pixel -- which gives the same clusters (tested below with
+several choices, and a counterexample showing that later hits may not be
+offered).
 """
 import numpy as np
 import pytest
@@ -66,6 +70,90 @@ def test_tiled_latest_hit_rule_matches_oracle(case):
     want, _ = oracle.cluster(hits, w, h, dt)
     got = tiled_rule_labels(hits, w, h, dt, tile=64)
     assert (got == want).all()
+
+
+def tiled_any_rule_labels(hits, width, height, dt, tile, choose, earlier_only=True):
+    """The pixel index's form of the rule: every tile hit joins, at each pixel
+    of its 3x3 neighbourhood, ONE earlier hit of the tile or its halo that is
+    within dt, picked by ``choose(candidates, time_distances)`` from all of
+    them (not necessarily the latest).  earlier_only=False also offers the
+    later hits within dt (a rule that is NOT exact)."""
+    n = hits.size
+    order = np.lexsort((np.arange(n), hits["toa"]))
+    toa = hits["toa"][order].astype(np.int64)
+    x = hits["x"][order].astype(np.int64)
+    y = hits["y"][order].astype(np.int64)
+    parent = list(range(n))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for p0 in range(0, n, tile):
+        p1 = min(n, p0 + tile)
+        h0 = int(np.searchsorted(toa[:p0], max(int(toa[p0]) - dt, 0), side="left"))
+        at = {}
+        for j in range(h0, p1):
+            at.setdefault((x[j], y[j]), []).append(j)
+        for i in range(p0, p1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    ok = [j for j in at.get((x[i] + dx, y[i] + dy), ())
+                          if (j < i or (not earlier_only and j != i)) and abs(toa[i] - toa[j]) <= dt]
+                    if ok:
+                        ra, rb = find(choose(ok, [abs(toa[i] - toa[j]) for j in ok])), find(i)
+                        if ra != rb:
+                            parent[max(ra, rb)] = min(ra, rb)
+    lab = np.empty(n, dtype=np.int64)
+    lab[order] = [find(i) for i in range(n)]
+    return canonical(lab)
+
+
+def _earliest(ok, dist):
+    return min(ok)
+
+
+def _farthest(ok, dist):
+    return ok[int(np.argmax(dist))]
+
+
+@pytest.mark.parametrize("case", ["mixed", "dense"])
+@pytest.mark.parametrize("pick", ["earliest", "farthest", "random"])
+def test_tiled_any_earlier_hit_rule_matches_oracle(case, pick):
+    if case == "mixed":
+        hits, p = hitgen.mixed_10m(n=20_000, seed=34)
+        w, h, dt = 256, 256, p["dt"]
+    else:
+        hits = hitgen.uniform_hits(4_000, 35, 10, 10, 12_000, disorder=40)
+        w, h, dt = 10, 10, 25
+    rng = np.random.default_rng(36)
+    choose = {"earliest": _earliest, "farthest": _farthest,
+              "random": lambda ok, dist: ok[int(rng.integers(len(ok)))]}[pick]
+    want, _ = oracle.cluster(hits, w, h, dt)
+    got = tiled_any_rule_labels(hits, w, h, dt, 64, choose)
+    assert (got == want).all()
+
+
+def test_any_hit_rule_must_look_back_only():
+    # a (P, t=0) and b (Q, t=50) are neighbours within dt = 60, so the oracle
+    # keeps j (Q, -60), a, b and a2 (P, 110) in one cluster.  Offered later
+    # hits too, a may pick j and b may pick a2 and the cluster splits; with
+    # earlier hits only, b must pick a.
+    hits = _rows([(0, 0, 0), (1, 0, -60), (1, 0, 50), (0, 0, 110)], base=1000)
+    want, _ = oracle.cluster(hits, 4, 4, 60)
+    assert len(set(want.tolist())) == 1
+    assert (tiled_any_rule_labels(hits, 4, 4, 60, 64, _farthest) == want).all()
+    split = tiled_any_rule_labels(hits, 4, 4, 60, 64, _farthest, earlier_only=False)
+    assert len(set(split.tolist())) == 2
+
+
+def _rows(rows, base):
+    h = np.zeros(len(rows), dtype=oracle.HIT_DTYPE)
+    for k, (xx, yy, t) in enumerate(rows):
+        h[k]["x"], h[k]["y"], h[k]["toa"], h[k]["tot"] = xx, yy, base + t, 1
+    return h
 
 
 # ---- the time-window form of the same rule (the default link kernel)
