@@ -44,7 +44,7 @@ KERNEL_SOURCES = {
 # Device function of each timed launch, as rocprofv3 names it.
 KERNEL_FUNCS = {
     "tile_sort": "hc::k_tile_sort<", "tile_rank": "hc::k_tile_rank<", "tile_gather": "hc::k_tile_gather<",
-    "link": "hc::k_link(", "flatten": "hc::k_flatten(", "features": "hc::k_features(",
+    "link": "hc::k_link<", "flatten": "hc::k_flatten(", "features": "hc::k_features(",
     "compact": "hc::k_compact(",
 }
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_mixed10m.json")

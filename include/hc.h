@@ -197,14 +197,15 @@ size_t hc_batch_workspace_size(const int64_t* offsets, int32_t n_chunks, const h
                                const hc_opts* opts);
 
 /* Autotuner: runs every candidate plan (sort tile size / neighbour reach, XCD
- * tile mapping) on this batch, rejects any candidate whose labels, features
+ * tile mapping, neighbour search variant) on this batch, rejects any candidate whose labels, features
  * or counts differ from the default plan's in a single bit, and returns the
  * fastest.  Uses labels/features/n_clusters as scratch (they end up holding
  * the result).  The choice is cached per (device, size class) for the process. */
 int hc_batch_autotune(const hc_hit* hits, const int64_t* offsets, int32_t n_chunks, const uint64_t* dts,
                       int32_t* labels, hc_features* features, int32_t* n_clusters, const hc_opts* opts,
                       hc_batch_plan** out);
-/* Human-readable plan (e.g. "sort_tile=8192 reach=1 xcd_map=1 time_ms=0.42"). */
+/* Human-readable plan (e.g. "disorder_hint=1024 sort_tile=2048 xcd_map=1
+ * link=default time_ms=0.42"). */
 int hc_batch_plan_describe(const hc_batch_plan* plan, char* buf, size_t cap);
 void hc_batch_plan_destroy(hc_batch_plan* plan);
 

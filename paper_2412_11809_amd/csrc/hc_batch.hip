@@ -46,7 +46,7 @@ using namespace hc;
 struct hc_batch_plan {
     uint32_t disorder_hint;
     int32_t xcd_map;
-    int32_t link_mode;  // 0: per tile by window length, 1: pixel index, 2: window scan
+    int32_t link_mode;  // 0: default (pixel index when the bitmap fits), 1: pixel index, 2: window scan
     double time_ms;
 };
 
@@ -189,7 +189,7 @@ int hc_batch_plan_describe(const hc_batch_plan* plan, char* buf, size_t cap)
     if (!plan || !buf || cap == 0) return set_error(HC_ERR_ARG, "NULL plan or buffer");
     const int T = sort_tile_for(plan->disorder_hint ? plan->disorder_hint : 4096);
     snprintf(buf, cap, "disorder_hint=%u sort_tile=%d xcd_map=%d link=%s time_ms=%.4f", plan->disorder_hint, T,
-             plan->xcd_map, plan->link_mode == 1 ? "index" : plan->link_mode == 2 ? "window" : "hybrid",
+             plan->xcd_map, plan->link_mode == 1 ? "index" : plan->link_mode == 2 ? "window" : "default",
              plan->time_ms);
     return HC_OK;
 }
@@ -259,8 +259,8 @@ int hc_batch_autotune(const hc_hit* hits, const int64_t* offsets, int32_t n_chun
     const uint32_t hints[] = {512, 1024, 2048, 4096, 8192, 16384};
     hc_batch_plan best{0, 0, 0, 1e30};
     for (uint32_t h : hints) {
-        for (int cfg = 0; cfg < 6; cfg++) {
-            hc_batch_plan cand{h, 1 - (cfg & 1), cfg >> 1, 0.0};
+        for (int cfg = 0; cfg < 4; cfg++) {  // link mode: default, window scan
+            hc_batch_plan cand{h, 1 - (cfg & 1), (cfg >> 1) ? 2 : 0, 0.0};
             if ((rc = run(&cand)) != HC_OK) break;  // warm-up (and the parity check below)
             unsigned long long nd = 0;
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)diff, (int64_t)2, 0u);

@@ -104,8 +104,8 @@ struct Work {
     uint32_t width, height;
     uint64_t dt;
     int32_t xcd_map;         // 1: contiguous tile ranges per XCD, 0: round-robin
-    int32_t link_mode;       // 0: per tile, window scan or pixel index by window length;
-                             // 1: pixel index (bitmap + CSR) only; 2: window scan only
+    int32_t link_mode;       // 0: pixel index if the sensor's bitmap fits in LDS, else
+                             // window scan; 1: pixel index (bitmap + CSR); 2: window scan
     int32_t n_seg;           // 1: one chunk, tile ranges computed arithmetically
     SegInfo* segs;           // n_seg > 1: chunk table
     int32_t* tile_seg[4];    // n_seg > 1: chunk of every tile, per kind
