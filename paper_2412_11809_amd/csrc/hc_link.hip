@@ -79,8 +79,9 @@ hipError_t launch_link_halo(const Work& w, hipStream_t s)
 
 // Joins of one tile (cand: per tile hit, the slot joined at each of its 9
 // pixels, or -1) applied in bulk rounds in the LDS forest l_par: hook every
-// edge's larger root under the smaller (atomic minimum), then jump pointers
-// until every tree is a star; repeat until no edge joins two roots.  Then the
+// edge's larger root under the smaller (atomic minimum) and retire the edges
+// already inside one tree, then walk every slot to its root; repeat until no
+// edge joins two roots.  Then the
 // smallest input index of every local tree is published: as the parent of
 // the tree's tile hits, and as cross-tile edges for its halo hits.
 // minidx: LDS scratch of L words (the caller's ToA array, no longer read).
@@ -103,6 +104,13 @@ __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_pa
                 if (pc != pi) {
                     atomicMin(&l_par[pc > pi ? pc : pi], pc > pi ? pi : pc);
                     changed = true;
+                } else {
+                    // joined: retire the edge.  The pointers just read may be
+                    // hooks of this round that a smaller atomic minimum later
+                    // replaces, but the edge that made each such hook saw
+                    // different roots, so it stays and is checked again next
+                    // round; a round without hooks reads only settled trees.
+                    cand[q][k] = -1;
                 }
             }
         }
@@ -442,7 +450,7 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint
 // of 2 (low bits 3) is rejected inside the rarely taken branch.
 // Sparse input gives short windows (a few slots); inside a dense shower the
 // window holds every hit of the last dt.
-__global__ __launch_bounds__(kLinkThreads) void k_link_window(Work w)
+__global__ __launch_bounds__(kLinkThreads, 8) void k_link_window(Work w)
 {
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
     constexpr int PER = kLinkTile / kLinkThreads;
