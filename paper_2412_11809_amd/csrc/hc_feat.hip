@@ -5,7 +5,11 @@
 // task (Section 6).  Here the features are reduced without moving any hit:
 //   k_features  per tile of kFeatTile sorted hits: an LDS hash keyed by the
 //               cluster label gathers each cluster's partial sums (size, ToT,
-//               x*ToT, y*ToT, x, y) and ToA min/max with LDS atomics.  The one
+//               x*ToT, y*ToT, x, y) and its ToA min/max (32-bit offsets
+//               from the tile's first ToA; in the rare tile whose ToA span
+//               exceeds 32 bits, the tile positions of the cluster's first
+//               and last hit, the tile being in ToA order) with LDS
+//               atomics.  The one
 //               tile that holds the cluster's label hit (idx == label) stores
 //               its partial as the cluster's record; every other tile queues
 //               its partial as a "carry";
@@ -24,12 +28,15 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
 {
     static_assert(kFeatHash == 512 && kFeatHash >= kFeatTile, "root_hash yields 9 bits; a tile never fills the table");
     static_assert((uint64_t)kFeatTile * 65535u < (1ull << 32), "paired 32-bit sums must not carry");
+    // label + 1 (below 2^31), bit 31 set once the cluster's label hit is seen
     __shared__ uint32_t h_key[kFeatHash];
     // two 32-bit sums per 64-bit word (size | sum ToT << 32, sum x | sum y << 32):
     // a tile's sums stay below 2^32, so one atomic adds both without carry
     __shared__ unsigned long long a_cs[kFeatHash], a_xy[kFeatHash];
-    __shared__ uint32_t a_own[kFeatHash];
-    __shared__ unsigned long long a_sxt[kFeatHash], a_syt[kFeatHash], a_tmin[kFeatHash], a_tmax[kFeatHash];
+    __shared__ unsigned long long a_sxt[kFeatHash], a_syt[kFeatHash];
+    // ToA min / max: offsets from the tile's first ToA, or tile positions in a wide tile
+    __shared__ uint32_t a_pmin[kFeatHash], a_pmax[kFeatHash];
+    constexpr uint32_t kOwn = 0x80000000u;
     constexpr int PER = kFeatTile / kFeatThreads;
 
     if (w.status->err_range) return;
@@ -40,6 +47,8 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     const int64_t p0 = tr.start;
     const int64_t p_end = tr.start + tr.count;
     for (int i = t; i < kFeatHash; i += kFeatThreads) h_key[i] = 0u;
+    const uint64_t tfirst = p_end > p0 ? w.s_toa[p0] : 0ull;
+    const bool wide = p_end > p0 && w.s_toa[p_end - 1] - tfirst > 0xFFFFFFFFull;
     __syncthreads();
 
     int slot[PER];
@@ -50,6 +59,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     for (int q = 0; q < PER; q++) {
         const int64_t p = p0 + t + q * kFeatThreads;
         slot[q] = -1;
+        toa[q] = tfirst;
         if (p < p_end) {
             idx[q] = w.s_idx[p];
             toa[q] = w.s_toa[p];
@@ -69,11 +79,10 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
                 if (old == 0u) {  // first hit of this cluster here: initialise
                     a_cs[s] = 0ull;
                     a_xy[s] = 0ull;
-                    a_own[s] = 0u;
                     a_sxt[s] = 0ull;
                     a_syt[s] = 0ull;
-                    a_tmin[s] = ~0ull;
-                    a_tmax[s] = 0ull;
+                    a_pmin[s] = ~0u;
+                    a_pmax[s] = 0u;
                     break;
                 }
                 if (old == key) break;
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         const bool valid = s >= 0;
         const uint32_t x = valid ? (xy[q] & 0xFFFFu) : 0u, y = valid ? (xy[q] >> 16) : 0u;
         const uint32_t st = valid ? tot[q] : 0u;
-        const bool own_lane = valid && (uint32_t)idx[q] + 1u == h_key[s];
+        const bool own_lane = valid && (uint32_t)idx[q] + 1u == (h_key[s] & ~kOwn);
         const unsigned long long owners = __ballot(own_lane);
         const uint32_t P_st = wave_incl_scan_u32(st);
         const uint32_t P_sx = wave_incl_scan_u32(x);
@@ -117,7 +126,8 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         const uint32_t B_st = __shfl(P_st, src, kWave), B_sx = __shfl(P_sx, src, kWave);
         const uint32_t B_sy = __shfl(P_sy, src, kWave);
         const uint64_t B_sxt = __shfl(P_sxt, src, kWave), B_syt = __shfl(P_syt, src, kWave);
-        const uint64_t tmn = __shfl(valid ? toa[q] : 0ull, start, kWave);
+        const uint32_t pos = wide ? (uint32_t)(t + q * kFeatThreads) : (uint32_t)(toa[q] - tfirst);
+        const uint32_t pmn = (uint32_t)__shfl((int)pos, start, kWave);
         if (tail && valid) {
             const unsigned long long run = le_mask & ~((1ull << start) - 1ull);
             const uint64_t n_st = P_st - (first ? 0u : B_st);
@@ -126,9 +136,9 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
             atomicAdd(&a_xy[s], (unsigned long long)(n_sx | (n_sy << 32)));
             atomicAdd(&a_sxt[s], (unsigned long long)(P_sxt - (first ? 0ull : B_sxt)));
             atomicAdd(&a_syt[s], (unsigned long long)(P_syt - (first ? 0ull : B_syt)));
-            atomicMin(&a_tmin[s], (unsigned long long)tmn);
-            atomicMax(&a_tmax[s], (unsigned long long)toa[q]);
-            if (owners & run) a_own[s] = 1u;
+            atomicMin(&a_pmin[s], pmn);
+            atomicMax(&a_pmax[s], pos);
+            if (owners & run) atomicOr(&h_key[s], kOwn);
         }
     }
     __syncthreads();
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
 #pragma unroll
     for (int k = 0; k < SPT; k++) {
         const int s = t + k * kFeatThreads;
-        nc += (h_key[s] != 0u && !a_own[s]) ? 1u : 0u;
+        nc += (h_key[s] != 0u && !(h_key[s] & kOwn)) ? 1u : 0u;
     }
     __shared__ uint32_t wsum[kFeatThreads / kWave];
     uint32_t total;
@@ -150,20 +160,21 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
 #pragma unroll
     for (int k = 0; k < SPT; k++) {
         const int s = t + k * kFeatThreads;
-        const uint32_t key = h_key[s];
-        if (key == 0u) continue;
+        const uint32_t hk = h_key[s];
+        if (hk == 0u) continue;
+        const uint32_t key = hk & ~kOwn;
         SlotRec r;
         const uint64_t cs = a_cs[s], sxy = a_xy[s];
         r.size = (uint32_t)cs;
         r.root = (int32_t)(key - 1u);
         r.sum_tot = cs >> 32;
-        r.toa_min = a_tmin[s];
-        r.toa_max = a_tmax[s];
+        r.toa_min = wide ? w.s_toa[p0 + a_pmin[s]] : tfirst + a_pmin[s];
+        r.toa_max = wide ? w.s_toa[p0 + a_pmax[s]] : tfirst + a_pmax[s];
         r.sum_xt = a_sxt[s];
         r.sum_yt = a_syt[s];
         r.sum_x = (uint32_t)sxy;
         r.sum_y = sxy >> 32;
-        if (a_own[s]) {
+        if (hk & kOwn) {
             w.slots[key - 1u] = r;
         } else {
             w.carries[base + pos++] = r;  // pos < kFeatHash: one entry per hash slot at most

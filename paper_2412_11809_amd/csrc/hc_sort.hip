@@ -215,15 +215,25 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
     for (int i = first_tile; i <= last_tile; i++) {
         if (i == j) continue;
         const TileInfo ti = w.tiles[i];
+        // tiles that do not overlap this one in ToA: every count is all or none
+        if (i < j ? tj.base >= ti.max_toa : tj.max_toa < ti.base) {
+            if (i < j) {
+#pragma unroll
+                for (int q = 0; q < IPT; q++) rank[q] += (uint32_t)ti.count;
+            }
+            continue;
+        }
         const int64_t ibase = jr.seg_start + (int64_t)(i - t0) * T;
         __syncthreads();
         for (int e = t; e < ti.count; e += kSortThreads) nk[e] = w.ts_rel[ibase + e];
         __syncthreads();
+        // a thread whose smallest key lies beyond the whole tile counts all of it
+        const bool all = i < j ? toa[0] >= ti.max_toa : toa[0] > ti.max_toa;
         int lo = 0;
 #pragma unroll
         for (int q = 0; q < IPT; q++) {
             if (r0 + q < tj.count) {
-                lo = count_below(nk, ti.count, ti.base, toa[q], i < j, lo);
+                lo = all ? ti.count : count_below(nk, ti.count, ti.base, toa[q], i < j, lo);
                 rank[q] += (uint32_t)lo;
             }
         }
