@@ -322,6 +322,10 @@ const char* hc_version(void);
  * reset; it synchronises with the recorded events.  Not thread-safe: enable
  * it only in single-threaded measurement code. */
 int hc_timing_enable(int on);
+/* Restrict the timing to launches of one kernel (a name hc_timing_read
+ * reports, e.g. "link"), so that the other launches carry no events; NULL or
+ * "" times every kernel again.  Returns HC_OK. */
+int hc_timing_select(const char* name);
 int hc_timing_reset(void);
 /* Writes up to cap entries; names are static strings owned by the library.
  * Returns the number of distinct kernels (may exceed cap), or < 0 on error. */

@@ -68,6 +68,7 @@ def load_library(path=LIB_PATH):
     lib.hc_last_error.restype = ctypes.c_char_p
     lib.hc_version.restype = ctypes.c_char_p
     lib.hc_timing_enable.argtypes = [ctypes.c_int]
+    lib.hc_timing_select.argtypes = [ctypes.c_char_p]
     lib.hc_timing_read.restype = ctypes.c_int
     lib.hc_timing_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
@@ -159,6 +160,11 @@ def features_to_numpy(feats, k):
 # ---- kernel timing (diagnostics)
 def hc_timing_enable(on=True):
     load_library().hc_timing_enable(1 if on else 0)
+
+
+def hc_timing_select(name=None):
+    """Time only launches of kernel ``name`` (None: every kernel)."""
+    load_library().hc_timing_select(name.encode() if name else None)
 
 
 def hc_timing_reset():

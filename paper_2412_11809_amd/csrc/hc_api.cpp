@@ -211,6 +211,7 @@ struct TimingRec {
     hipEvent_t start, stop;
 };
 static bool g_timing = false;
+static std::string g_tsel;  // time only launches of this kernel name (empty: all)
 static std::mutex g_tmu;  // launches from several host threads (server workers)
 static std::vector<TimingRec> g_trecs;
 static size_t g_tused = 0;
@@ -226,6 +227,7 @@ TimedLaunch::TimedLaunch(const char* name, hipStream_t s) : name_(name), s_(s), 
 {
     if (!g_timing) return;
     std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_tsel.empty() && g_tsel != name) return;
     if (g_tused == g_trecs.size()) {
         TimingRec r{name, nullptr, nullptr};
         if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
@@ -328,6 +330,13 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_f
 int hc_timing_enable(int on)
 {
     g_timing = on != 0;
+    return HC_OK;
+}
+
+int hc_timing_select(const char* name)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_tsel = name ? name : "";
     return HC_OK;
 }
 
