@@ -24,8 +24,7 @@ HBM_PEAK_GBS = 8000.0
 # hit (read the 16-byte hit, write the 4-byte label) + 64 B per cluster.
 ALG_BYTES = {
     "tile_sort": (16 + 12, 0),   # hit record in; relative ToA + payload (index, ToT, pixel) out
-    "tile_rank": (4 + 4, 0),     # relative ToA in; global rank out
-    "tile_gather": (16 + 18, 0), # rank, relative ToA, payload in; sorted ToA, pixel, ToT, index out
+    "tile_rank": (12 + 18, 0),   # relative ToA + payload in; sorted ToA, pixel, ToT, index out
     "link": (16 + 4, 0),         # sorted ToA, pixel, index in; parent out
     "flatten": (4 + 4, 0),       # parent in; label out
     "features": (22, 64),        # index, label, ToA, pixel, ToT in; cluster record out
@@ -37,13 +36,13 @@ ALG_BYTES = {
 _COMMON = ["hc_device.h", "hc_internal.h", "hc_radix.h"]
 KERNEL_SOURCES = {
     "tile_sort": ["hc_sort.hip"] + _COMMON, "tile_rank": ["hc_sort.hip"] + _COMMON,
-    "tile_gather": ["hc_sort.hip"] + _COMMON, "link": ["hc_link.hip"] + _COMMON,
+    "link": ["hc_link.hip"] + _COMMON,
     "flatten": ["hc_link.hip"] + _COMMON, "features": ["hc_feat.hip"] + _COMMON,
     "compact": ["hc_feat.hip"] + _COMMON,
 }
 # Device function of each timed launch, as rocprofv3 names it.
 KERNEL_FUNCS = {
-    "tile_sort": "hc::k_tile_sort<", "tile_rank": "hc::k_tile_rank<", "tile_gather": "hc::k_tile_gather<",
+    "tile_sort": "hc::k_tile_sort<", "tile_rank": "hc::k_tile_rank<",
     "link": "hc::k_link<", "flatten": "hc::k_flatten(", "features": "hc::k_features(",
     "compact": "hc::k_compact(",
 }

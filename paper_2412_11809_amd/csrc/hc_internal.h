@@ -126,7 +126,6 @@ struct Work {
     TileInfo* tiles;
     uint32_t* ts_rel;     // tile-sorted ToA relative to the tile minimum
     uint2* ts_pay;        // tile-sorted payload: (local index | ToT << 16, x | y << 16)
-    uint32_t* ts_rank;    // tile-sorted global rank
     uint64_t* s_toa;
     uint32_t* s_xy;
     uint16_t* s_tot;

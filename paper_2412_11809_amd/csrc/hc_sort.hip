@@ -7,10 +7,11 @@
 //   k_tile_sort   sorts tiles of T consecutive input hits in LDS (stable radix
 //                 sort on ToA relative to the tile minimum), writes the tile in
 //                 sorted order plus its min/max keys;
-//   k_tile_merge  gives every element its global rank: all of its tile's
+//   k_tile_rank   gives every element its global rank: all of its tile's
 //                 predecessors plus, for each of the m neighbour tiles on both
 //                 sides, the number of smaller keys there (binary search in
-//                 LDS).  This is exact whenever tiles more than m apart do not
+//                 LDS), and writes the element's sorted record at that rank.
+//                 This is exact whenever tiles more than m apart do not
 //                 interleave, which the kernel verifies from the tile min/max
 //                 keys: tile minima ascend and the max of tile i lies below
 //                 the min of tile i+m+1 (then every element of a tile more
@@ -169,9 +170,10 @@ __device__ inline int count_below(const uint32_t* rel, int cnt, uint64_t base, u
 }
 
 // Global rank of every element of tile j: all elements of tiles before
-// j - m, its position in its own tile, and its count in each neighbour tile.
-// Written in tile-sorted order (coalesced).  Also checks the conditions
-// under which this is exact.
+// j - m, its position in its own tile, and its count in each neighbour tile;
+// the element's sorted record is written at that rank.  Also checks the
+// conditions under which this is exact (if they fail anywhere, the fallback
+// sort rewrites every record).
 template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
 {
@@ -238,55 +240,19 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
             }
         }
     }
+    // scatter: element e of the sorted tile goes to position rank(e) of its
+    // chunk.  Ranks pass through LDS so that consecutive lanes take
+    // consecutive elements, whose ranks are mostly consecutive too.
+    __syncthreads();  // the neighbour keys are no longer read
 #pragma unroll
     for (int q = 0; q < IPT; q++)
-        if (r0 + q < tj.count) w.ts_rank[base + r0 + q] = rank[q];
-}
-
-// Output tile k (sorted positions [kT, kT + T)) collects the elements of
-// tiles k-m .. k+m whose rank falls in it, then writes the sorted arrays
-// with coalesced stores.
-template <int IPT>
-__global__ __launch_bounds__(kSortThreads) void k_tile_gather(Work w)
-{
-    constexpr int T = kSortThreads * IPT;
-    __shared__ uint32_t slot[T];
-    if (w.status->sort_fallback) return;
-    const int k = xcd_tile(w.n_sort_tiles, w.xcd_map);
-    if (k < 0) return;
-    const int t = threadIdx.x;
-    const int m = w.sort_m;
-    const TileRange kr = tile_range(w, kSortKind, k, T);
-    const int t0 = kr.tile0, nt = kr.tile1;
-    const int64_t out0 = kr.start;                  // global position of the output tile
-    const int64_t rel0 = (int64_t)(k - t0) * T;     // its chunk-relative position
-    const int cnt_out = kr.count;
-    for (int r = t; r < T; r += kSortThreads) slot[r] = 0xFFFFFFFFu;
+        if (r0 + q < tj.count) nk[r0 + q] = rank[q];
     __syncthreads();
-    const int first_tile = k - m < t0 ? t0 : k - m;
-    const int last_tile = k + m >= nt ? nt - 1 : k + m;
-    for (int i = first_tile; i <= last_tile; i++) {
-        const int ci = w.tiles[i].count;
-        const int64_t ibase = kr.seg_start + (int64_t)(i - t0) * T;
-        for (int e = t; e < ci; e += kSortThreads) {
-            const int64_t r = (int64_t)w.ts_rank[ibase + e] - rel0;
-            if (r >= 0 && r < cnt_out) slot[r] = ((uint32_t)(i - first_tile) << 16) | (uint32_t)e;
-        }
-    }
-    __syncthreads();
-    for (int r = t; r < cnt_out; r += kSortThreads) {
-        const uint32_t v = slot[r];
-        if (v == 0xFFFFFFFFu) {
-            atomicOr(&w.status->err_internal, 1);
-            continue;
-        }
-        const int i = first_tile + (int)(v >> 16);
-        const int64_t ibase = kr.seg_start + (int64_t)(i - t0) * T;
-        const int64_t src = ibase + (v & 0xFFFFu);
-        const uint2 pay = w.ts_pay[src];
-        const int64_t dst = out0 + r;
-        w.s_toa[dst] = w.tiles[i].base + w.ts_rel[src];
-        w.s_idx[dst] = (int32_t)(ibase + (pay.x & 0xFFFFu));
+    for (int e = t; e < tj.count; e += kSortThreads) {
+        const int64_t dst = jr.seg_start + nk[e];
+        const uint2 pay = w.ts_pay[base + e];
+        w.s_toa[dst] = tj.base + w.ts_rel[base + e];
+        w.s_idx[dst] = (int32_t)(base + (pay.x & 0xFFFFu));
         w.s_tot[dst] = (uint16_t)(pay.x >> 16);
         w.s_xy[dst] = pay.y;
     }
@@ -295,22 +261,11 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_gather(Work w)
 hipError_t launch_tile_merge(const Work& w, hipStream_t s)
 {
     dim3 grid(xcd_grid(w.n_sort_tiles)), block(kSortThreads);
-    {
-        TimedLaunch tl("tile_rank", s);
-        switch (w.sort_ipt) {
-        case 4: hipLaunchKernelGGL(k_tile_rank<4>, grid, block, 0, s, w); break;
-        case 8: hipLaunchKernelGGL(k_tile_rank<8>, grid, block, 0, s, w); break;
-        case 16: hipLaunchKernelGGL(k_tile_rank<16>, grid, block, 0, s, w); break;
-        default: return hipErrorInvalidValue;
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    TimedLaunch tl("tile_gather", s);
+    TimedLaunch tl("tile_rank", s);
     switch (w.sort_ipt) {
-    case 4: hipLaunchKernelGGL(k_tile_gather<4>, grid, block, 0, s, w); break;
-    case 8: hipLaunchKernelGGL(k_tile_gather<8>, grid, block, 0, s, w); break;
-    case 16: hipLaunchKernelGGL(k_tile_gather<16>, grid, block, 0, s, w); break;
+    case 4: hipLaunchKernelGGL(k_tile_rank<4>, grid, block, 0, s, w); break;
+    case 8: hipLaunchKernelGGL(k_tile_rank<8>, grid, block, 0, s, w); break;
+    case 16: hipLaunchKernelGGL(k_tile_rank<16>, grid, block, 0, s, w); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
