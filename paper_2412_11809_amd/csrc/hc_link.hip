@@ -77,6 +77,75 @@ hipError_t launch_link_halo(const Work& w, hipStream_t s)
     return hipGetLastError();
 }
 
+// Global loads of a link tile, ordered so that the halo start is the only
+// thing that waits on a round trip: the error flag, the halo start and the
+// tile's own hits (whose positions are known) are requested together; the
+// halo hits and the ToA base follow.  Thread t holds the tile hits at slots
+// hl + t + q * kLinkThreads (q < PER) and the halo hits at slots
+// t + q * kLinkThreads below hl (q < 2).  Returns false when the work-group
+// has to stop: the error flag is set, or the halo does not fit, in which case
+// the tile's hits become their own roots and the tile goes to the fallback.
+template <int PER>
+__device__ inline bool link_tile_load(const Work& w, int tile, const TileRange& tr, int64_t& h0, uint64_t& tbase,
+                                      uint64_t (&ttoa)[PER], uint32_t (&txy)[PER], int32_t (&tid)[PER],
+                                      uint64_t (&htoa)[2], uint32_t (&hxy)[2], int32_t (&hid)[2])
+{
+    const int t = threadIdx.x;
+    const int64_t p0 = tr.start;
+    const int64_t p1 = tr.start + tr.count;
+    const int err = w.status->err_range;
+    h0 = w.link_h0[tile];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int64_t p = p0 + t + q * kLinkThreads;
+        tid[q] = -1;
+        if (p < p1) {
+            ttoa[q] = w.s_toa[p];
+            txy[q] = w.s_xy[p];
+            tid[q] = w.s_idx[p];
+        }
+    }
+    if (err) return false;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int64_t p = p0 + t + q * kLinkThreads;
+        if (p < p1 && (tid[q] < 0 || tid[q] >= w.n)) {
+            atomicOr(&w.status->err_internal, 1);
+            tid[q] = 0;
+        }
+    }
+    if (h0 < 0) {  // halo too large: every hit is its own root here, the fallback joins them
+#pragma unroll
+        for (int q = 0; q < PER; q++)
+            if (p0 + t + q * kLinkThreads < p1) w.gparent[tid[q]] = tid[q];
+        if (t == 0) {
+            const int k = atomicAdd(&w.status->n_overflow, 1);
+            w.overflow_tiles[k] = tile;
+            w.tile_nedge[tile] = 0;
+        }
+        return false;
+    }
+    const int hl = (int)(p0 - h0);
+    tbase = w.s_toa[h0];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int a = t + q * kLinkThreads;
+        hid[q] = -1;
+        if (a < hl) {
+            const int64_t p = h0 + a;
+            htoa[q] = w.s_toa[p];
+            hxy[q] = w.s_xy[p];
+            int32_t id = w.s_idx[p];
+            if (id < 0 || id >= w.n) {
+                atomicOr(&w.status->err_internal, 1);
+                id = 0;
+            }
+            hid[q] = id;
+        }
+    }
+    return true;
+}
+
 // Joins of one tile (cand: per tile hit, the slot joined at each of its 9
 // pixels, or -1) applied in bulk rounds in the LDS forest l_par: hook every
 // edge's larger root under the smaller (atomic minimum) and retire the edges
@@ -85,9 +154,10 @@ hipError_t launch_link_halo(const Work& w, hipStream_t s)
 // smallest input index of every local tree is published: as the parent of
 // the tree's tile hits, and as cross-tile edges for its halo hits.
 // minidx: LDS scratch of L words (the caller's ToA array, no longer read).
-template <int PER, int LPER>
+template <int PER>
 __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_par, int (&cand)[PER][9],
-                                          const int32_t (&ids)[LPER], int hl, int L, int32_t* minidx)
+                                          const int32_t (&tid)[PER], const int32_t (&hid)[2], int hl, int L,
+                                          int32_t* minidx)
 {
     const int t = threadIdx.x;
     while (true) {
@@ -133,23 +203,28 @@ __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_pa
     // ---- smallest input index per local tree, then publish
     for (int i = t; i < L; i += kLinkThreads) minidx[i] = 0x7FFFFFFF;
     __syncthreads();
-    int32_t root[LPER];
+    int32_t rt[PER], rh[2];
 #pragma unroll
-    for (int q = 0; q < LPER; q++) {
-        const int i = t + q * kLinkThreads;
-        root[q] = i < L ? l_par[i] : -1;
-        if (root[q] >= 0) atomicMin(&minidx[root[q]], ids[q]);
+    for (int q = 0; q < PER; q++) {
+        const int i = hl + t + q * kLinkThreads;
+        rt[q] = i < L ? l_par[i] : -1;
+        if (rt[q] >= 0) atomicMin(&minidx[rt[q]], tid[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int a = t + q * kLinkThreads;
+        rh[q] = a < hl ? l_par[a] : -1;
+        if (rh[q] >= 0) atomicMin(&minidx[rh[q]], hid[q]);
     }
     __syncthreads();
     // halo hits joined by this tile become cross-tile edges, in the tile's
     // own region of kLinkHaloCap entries (positions from a block scan)
-    int32_t m[LPER];
+    int32_t mh[2];
     uint32_t ne = 0;
 #pragma unroll
-    for (int q = 0; q < LPER; q++) {
-        const int i = t + q * kLinkThreads;
-        m[q] = i < L ? minidx[root[q]] : -1;
-        ne += (i < hl && ids[q] != m[q]) ? 1u : 0u;
+    for (int q = 0; q < 2; q++) {
+        mh[q] = rh[q] >= 0 ? minidx[rh[q]] : -1;
+        ne += (rh[q] >= 0 && hid[q] != mh[q]) ? 1u : 0u;
     }
     __shared__ uint32_t e_wsum[kLinkThreads / kWave];
     uint32_t n_tile_edges;
@@ -157,15 +232,12 @@ __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_pa
     if (t == 0) w.tile_nedge[tile] = (int32_t)n_tile_edges;
     const int64_t e_base = (int64_t)tile * kLinkHaloCap;
 #pragma unroll
-    for (int q = 0; q < LPER; q++) {
-        const int i = t + q * kLinkThreads;
-        if (i >= L) continue;
-        if (i >= hl) {
-            w.gparent[ids[q]] = m[q];
-        } else if (ids[q] != m[q]) {
-            w.edges[e_base + pos++] = make_int2(ids[q], m[q]);  // pos < hl <= kLinkHaloCap
-        }
-    }
+    for (int q = 0; q < PER; q++)
+        if (rt[q] >= 0) w.gparent[tid[q]] = minidx[rt[q]];
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+        if (rh[q] >= 0 && hid[q] != mh[q])
+            w.edges[e_base + pos++] = make_int2(hid[q], mh[q]);  // pos < hl <= kLinkHaloCap
 }
 
 // Window scan of the tile hits (see k_link_window): for tile hit i, the
@@ -264,48 +336,35 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint
     uint16_t* wpre = reinterpret_cast<uint16_t*>(dyn64 + bm64);
     uint32_t* pcount = reinterpret_cast<uint32_t*>(pstart);  // two 16-bit counters per word
 
-    if (w.status->err_range) return;
     const int tile = xcd_tile(w.n_link_tiles, w.xcd_map);
     if (tile < 0) return;
     const int t = threadIdx.x;
     const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
-    const int64_t p0 = tr.start;
+    int64_t h0;
+    uint64_t tbase, ttoa[PER], htoa[2];
+    uint32_t txy[PER], hxy[2];
+    int32_t tid[PER], hid[2];
+    if (!link_tile_load<PER>(w, tile, tr, h0, tbase, ttoa, txy, tid, htoa, hxy, hid)) return;
     const int64_t p1 = tr.start + tr.count;
-    const int64_t h0 = w.link_h0[tile];
-    if (h0 < 0) {  // halo too large: every hit is its own root here, the fallback joins them
-        for (int64_t p = p0 + t; p < p1; p += kLinkThreads) {
-            const int32_t id = w.s_idx[p];
-            if (id >= 0 && id < w.n) w.gparent[id] = id;
-            else atomicOr(&w.status->err_internal, 1);
-        }
-        if (t == 0) {
-            const int k = atomicAdd(&w.status->n_overflow, 1);
-            w.overflow_tiles[k] = tile;
-            w.tile_nedge[tile] = 0;
-        }
-        return;
-    }
     const int L = (int)(p1 - h0);
-    const int hl = (int)(p0 - h0);
-    const uint64_t tbase = w.s_toa[h0];
+    const int hl = (int)(tr.start - h0);
     const uint32_t W = w.width;
-    int32_t ids[LPER];
 #pragma unroll
-    for (int q = 0; q < LPER; q++) {
-        const int i = t + q * kLinkThreads;
-        ids[q] = -1;
+    for (int q = 0; q < 2; q++) {
+        const int a = t + q * kLinkThreads;
+        if (a < hl) {
+            l_toa[a] = (uint32_t)(htoa[q] - tbase);
+            l_pix[a] = (PixT)((hxy[q] >> 16) * W + (hxy[q] & 0xFFFFu));
+            l_par[a] = a;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = hl + t + q * kLinkThreads;
         if (i < L) {
-            const int64_t p = h0 + i;
-            l_toa[i] = (uint32_t)(w.s_toa[p] - tbase);
-            const uint32_t xy = w.s_xy[p];
-            l_pix[i] = (PixT)((xy >> 16) * W + (xy & 0xFFFFu));
+            l_toa[i] = (uint32_t)(ttoa[q] - tbase);
+            l_pix[i] = (PixT)((txy[q] >> 16) * W + (txy[q] & 0xFFFFu));
             l_par[i] = i;
-            int32_t id = w.s_idx[p];
-            if (id < 0 || id >= w.n) {
-                atomicOr(&w.status->err_internal, 1);
-                id = 0;
-            }
-            ids[q] = id;
         }
     }
     __syncthreads();
@@ -435,7 +494,7 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint
             }
         }
     }
-    link_union_publish(w, tile, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
+    link_union_publish(w, tile, l_par, cand, tid, hid, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
 // Same contract as k_link, without a pixel index: the latest earlier hit at
@@ -454,51 +513,38 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link_window(Work w)
 {
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
     constexpr int PER = kLinkTile / kLinkThreads;
-    constexpr int LPER = LCAP / kLinkThreads;
     __shared__ uint32_t l_toa[LCAP];
     __shared__ uint32_t l_xy[LCAP];
     __shared__ int32_t l_par[LCAP];
 
-    if (w.status->err_range) return;
     const int tile = xcd_tile(w.n_link_tiles, w.xcd_map);
     if (tile < 0) return;
     const int t = threadIdx.x;
     const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
-    const int64_t p0 = tr.start;
+    int64_t h0;
+    uint64_t tbase, ttoa[PER], htoa[2];
+    uint32_t txy[PER], hxy[2];
+    int32_t tid[PER], hid[2];
+    if (!link_tile_load<PER>(w, tile, tr, h0, tbase, ttoa, txy, tid, htoa, hxy, hid)) return;
     const int64_t p1 = tr.start + tr.count;
-    const int64_t h0 = w.link_h0[tile];
-    if (h0 < 0) {  // halo too large: every hit is its own root here, the fallback joins them
-        for (int64_t p = p0 + t; p < p1; p += kLinkThreads) {
-            const int32_t id = w.s_idx[p];
-            if (id >= 0 && id < w.n) w.gparent[id] = id;
-            else atomicOr(&w.status->err_internal, 1);
-        }
-        if (t == 0) {
-            const int k = atomicAdd(&w.status->n_overflow, 1);
-            w.overflow_tiles[k] = tile;
-            w.tile_nedge[tile] = 0;
-        }
-        return;
-    }
     const int L = (int)(p1 - h0);
-    const int hl = (int)(p0 - h0);
-    const uint64_t tbase = w.s_toa[h0];
-    int32_t ids[LPER];
+    const int hl = (int)(tr.start - h0);
 #pragma unroll
-    for (int q = 0; q < LPER; q++) {
-        const int i = t + q * kLinkThreads;
-        ids[q] = -1;
+    for (int q = 0; q < 2; q++) {
+        const int a = t + q * kLinkThreads;
+        if (a < hl) {
+            l_toa[a] = (uint32_t)(htoa[q] - tbase);
+            l_xy[a] = hxy[q];
+            l_par[a] = a;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = hl + t + q * kLinkThreads;
         if (i < L) {
-            const int64_t p = h0 + i;
-            l_toa[i] = (uint32_t)(w.s_toa[p] - tbase);
-            l_xy[i] = w.s_xy[p];
+            l_toa[i] = (uint32_t)(ttoa[q] - tbase);
+            l_xy[i] = txy[q];
             l_par[i] = i;
-            int32_t id = w.s_idx[p];
-            if (id < 0 || id >= w.n) {
-                atomicOr(&w.status->err_internal, 1);
-                id = 0;
-            }
-            ids[q] = id;
         }
     }
     __syncthreads();
@@ -524,7 +570,7 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link_window(Work w)
     }
     int cand[PER][9];
     link_window_search<PER>(l_toa, l_xy, hl, L, lo, cand);
-    link_union_publish(w, tile, l_par, cand, ids, hl, L, reinterpret_cast<int32_t*>(l_toa));
+    link_union_publish(w, tile, l_par, cand, tid, hid, hl, L, reinterpret_cast<int32_t*>(l_toa));
 }
 
 // The pixel-index kernel, or the window-scan kernel.
