@@ -693,24 +693,27 @@ hipError_t launch_link_fallback(const Work& w, hipStream_t s)
 }
 
 // ------------------------------------------------- cross-tile unions
-// Cross-tile unions: one work-group per link tile's edge region (grid-stride).
-__global__ __launch_bounds__(64) void k_union_edges(Work w)
+// Cross-tile unions: one wave per link tile's edge region, all tiles in one
+// pass (the regions hold a handful of edges, so the time is the latency of
+// reading the count, the edges and the parent chains once).
+__global__ __launch_bounds__(256) void k_union_edges(Work w)
 {
     if (w.status->err_range) return;
-    for (int64_t k = blockIdx.x; k < w.n_link_tiles; k += gridDim.x) {
-        const int ne = w.tile_nedge[k];
-        for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-            const int2 ed = w.edges[k * kLinkHaloCap + e];
-            gunion(w.gparent, ed.x, ed.y, &w.status->err_internal);
-        }
+    const int64_t k = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (k >= w.n_link_tiles) return;
+    const int ne = w.tile_nedge[k];
+    for (int e = threadIdx.x & (kWave - 1); e < ne; e += kWave) {
+        const int2 ed = w.edges[k * kLinkHaloCap + e];
+        gunion(w.gparent, ed.x, ed.y, &w.status->err_internal);
     }
 }
 
 hipError_t launch_union_edges(const Work& w, hipStream_t s)
 {
     TimedLaunch tl("union_edges", s);
-    const int grid = w.n_link_tiles < 8192 ? (w.n_link_tiles > 0 ? w.n_link_tiles : 1) : 8192;
-    hipLaunchKernelGGL(k_union_edges, dim3(grid), dim3(64), 0, s, w);
+    const int per = 256 / kWave;
+    const int grid = w.n_link_tiles > 0 ? (w.n_link_tiles + per - 1) / per : 1;
+    hipLaunchKernelGGL(k_union_edges, dim3(grid), dim3(256), 0, s, w);
     return hipGetLastError();
 }
 
