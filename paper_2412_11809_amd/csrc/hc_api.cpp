@@ -268,7 +268,7 @@ int enqueue_cluster(const hc_hit* hits, const Work& w, int32_t* labels, hc_featu
         HC_LAUNCH(launch_features(w, labels, s), "features");
         HC_LAUNCH(launch_carries(w, s), "carries");
     }
-    HC_LAUNCH(launch_compact(w, labels, features, n_clusters, s), "compact");
+    HC_LAUNCH(launch_compact(w, features, n_clusters, s), "compact");
 #undef HC_LAUNCH
     return HC_OK;
 }

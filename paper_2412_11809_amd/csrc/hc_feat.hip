@@ -46,6 +46,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     const TileRange tr = tile_range(w, kFeatKind, tile, kFeatTile);
     const int64_t p0 = tr.start;
     const int64_t p_end = tr.start + tr.count;
+    const int32_t lab0 = w.n_seg > 1 ? (int32_t)tr.seg_start : 0;  // labels are chunk-local in a batch
     for (int i = t; i < kFeatHash; i += kFeatThreads) h_key[i] = 0u;
     const uint64_t tfirst = p_end > p0 ? w.s_toa[p0] : 0ull;
     const bool wide = p_end > p0 && w.s_toa[p_end - 1] - tfirst > 0xFFFFFFFFull;
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
             xy[q] = w.s_xy[p];
             tot[q] = w.s_tot[p];
             int32_t lab = 0;
-            if (idx[q] >= 0 && idx[q] < w.n) lab = labels[idx[q]];
+            if (idx[q] >= 0 && idx[q] < w.n) lab = labels[idx[q]] + lab0;
             else atomicOr(&w.status->err_internal, 1);
             if (lab < 0 || lab >= w.n) {
                 atomicOr(&w.status->err_internal, 1);
@@ -258,9 +259,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Work w, int32_t* n_cluster
 }
 
 // features[rank] for every root of one block of kScanBlock input indices.
-// For a batch of chunks it also turns the labels of its block chunk-local.
-__global__ __launch_bounds__(kScanThreads) void k_compact(Work w, int32_t* __restrict__ labels,
-                                                          hc_features* __restrict__ out)
+__global__ __launch_bounds__(kScanThreads) void k_compact(Work w, hc_features* __restrict__ out)
 {
     constexpr int PER = kScanBlock / kScanThreads;  // 8 consecutive indices per thread
     __shared__ uint32_t wsum[kScanThreads / kWave];
@@ -269,11 +268,6 @@ __global__ __launch_bounds__(kScanThreads) void k_compact(Work w, int32_t* __res
     const int b = blockIdx.x, t = threadIdx.x;
     const TileRange tr = tile_range(w, kScanKind, b, kScanBlock);
     const int64_t base = tr.start;
-    if (w.n_seg > 1) {
-        const int64_t end = tr.start + tr.count;
-        for (int64_t i = base + t; i < end; i += kScanThreads) labels[i] -= (int32_t)tr.seg_start;
-    }
-    if (!out) return;
     // bits of indices [base + PER*t, base + PER*t + PER) within mask word (PER*t)/64
     const unsigned long long word = w.root_mask[(int64_t)b * (kScanBlock / 64) + (PER * t) / 64];
     const uint32_t bits = (uint32_t)((word >> ((PER * t) % 64)) & ((1u << PER) - 1u));
@@ -304,7 +298,7 @@ __global__ __launch_bounds__(kScanThreads) void k_compact(Work w, int32_t* __res
     }
 }
 
-hipError_t launch_compact(const Work& w, int32_t* labels, hc_features* features, int32_t* n_clusters,
+hipError_t launch_compact(const Work& w, hc_features* features, int32_t* n_clusters,
                           hipStream_t s)
 {
     {
@@ -313,9 +307,9 @@ hipError_t launch_compact(const Work& w, int32_t* labels, hc_features* features,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (!features && w.n_seg <= 1) return hipSuccess;
+    if (!features) return hipSuccess;
     TimedLaunch tl("compact", s);
-    hipLaunchKernelGGL(k_compact, dim3(w.n_scan_blocks), dim3(kScanThreads), 0, s, w, labels, features);
+    hipLaunchKernelGGL(k_compact, dim3(w.n_scan_blocks), dim3(kScanThreads), 0, s, w, features);
     return hipGetLastError();
 }
 

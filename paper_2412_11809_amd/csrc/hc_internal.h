@@ -166,8 +166,7 @@ hipError_t launch_union_edges(const Work& w, hipStream_t s);
 hipError_t launch_flatten(const Work& w, int32_t* labels, hipStream_t s);
 hipError_t launch_features(const Work& w, const int32_t* labels, hipStream_t s);
 hipError_t launch_carries(const Work& w, hipStream_t s);
-hipError_t launch_compact(const Work& w, int32_t* labels, hc_features* features,
-                          int32_t* n_clusters, hipStream_t s);
+hipError_t launch_compact(const Work& w, hc_features* features, int32_t* n_clusters, hipStream_t s);
 hipError_t launch_write_count(int32_t* n_clusters, int32_t value, hipStream_t s);
 
 // The whole plain clustering sequence on one workspace (hc_api.cpp).

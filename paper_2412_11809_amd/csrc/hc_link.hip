@@ -718,8 +718,9 @@ hipError_t launch_union_edges(const Work& w, hipStream_t s)
 }
 
 // ------------------------------------------------------------ flatten
-// labels[i] = root(i).  One work-group per block of kScanBlock indices; a
-// root (labels[i] == i) is a cluster: its bit is set in the block's mask and
+// labels[i] = root(i) (minus the chunk's first index for a batch, whose
+// labels are chunk-local).  One work-group per block of kScanBlock indices; a
+// root (root(i) == i) is a cluster: its bit is set in the block's mask and
 // the block's root count is stored for the compaction scan.
 __global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __restrict__ labels)
 {
@@ -731,6 +732,7 @@ __global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __res
     const TileRange tr = tile_range(w, kScanKind, b, kScanBlock);
     const int64_t base = tr.start;
     const int64_t end = tr.start + tr.count;
+    const int64_t lab0 = w.n_seg > 1 ? tr.seg_start : 0;  // a batch's labels are chunk-local
     uint32_t c = 0;
 #pragma unroll
     for (int q = 0; q < kScanBlock / kScanThreads; q++) {
@@ -738,7 +740,7 @@ __global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __res
         bool root = false;
         if (i < end) {
             const int32_t r = gfind_final(w.gparent, (int32_t)i, &w.status->err_internal);
-            labels[i] = r;
+            labels[i] = r - (int32_t)lab0;
             root = (r == (int32_t)i);
         }
         const unsigned long long m = __ballot(root);
