@@ -127,6 +127,45 @@ def cpu_baseline(hits, p, budget_s):
             "sample": "the full %d-hit workload, one sequential run (%.1f s)" % (n, dt_s)}
 
 
+def bench_small(hc, torch, dev, calls=200):
+    """The 100k-hit blob stream (a few clusters' worth of work per tile): one
+    call costs about as much as its launches, so report call latency."""
+    import hitgen
+    hits, p = hitgen.blobs_100k()
+    n = hits.size
+    d = hc.hits_to_device(hits, dev)
+    ws = torch.empty(hc.hc_workspace_size(n, p["width"], p["height"], p["disorder"]), dtype=torch.uint8, device=dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    feats = torch.empty((n, 64), dtype=torch.uint8, device=dev)
+    k = torch.empty(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def call():
+        hc.hc_cluster(d, n, p["dt"], labels, feats, k, p["width"], p["height"], p["disorder"], ws, stream)
+
+    for _ in range(10):
+        call()
+    torch.cuda.synchronize(dev)
+    lat = []
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize(dev)
+        lat.append((time.perf_counter() - t0) * 1e3)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        call()
+    torch.cuda.synchronize(dev)
+    back_to_back_ms = (time.perf_counter() - t0) * 1e3 / calls
+    lat.sort()
+    return {"workload": "plain hc_cluster: 256x256 sensor, %d hits of random-walk blobs over 10 ms, "
+                        "dt = 200 ns" % n,
+            "n_hits": n, "n_clusters": int(k.item()), "calls": calls,
+            "latency_ms": {"p50": round(lat[len(lat) // 2], 4), "p99": round(lat[int(len(lat) * 0.99)], 4)},
+            "back_to_back_ms_per_call": round(back_to_back_ms, 4),
+            "note": "latency = one call from the host until its results are on the device, synchronised"}
+
+
 def bench_batch(hc, torch, dev, reps):
     """64 chunks of log-uniform size (~27M hits, 4 detectors, dt per chunk in
     {100, 200, 500} ns): the plain path chunk after chunk vs one batched launch
@@ -509,6 +548,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize(dev)
         out["copy_calibration_bytes"] = 1 << 30
+    if args.only is None:
+        out["small"] = bench_small(hc, torch, dev)
+        print("small done", file=sys.stderr, flush=True)
     if not args.no_batch:
         del d_hits, ws, labels, feats
         torch.cuda.empty_cache()
