@@ -242,6 +242,64 @@ __device__ inline int block_radix_sort(uint32_t* k0, uint16_t* v0, uint32_t* k1,
     return cur;
 }
 
+// Stable LSD sort of the NT*IPT element indices in e0 by key[e] (the keys
+// stay in place in LDS and are read through the index), the low `bits` bits,
+// four bits per pass.  Half the LDS of sorting (key, index) pairs, which lets
+// more work-groups share a CU.  Thread t owns positions [t*IPT, (t+1)*IPT);
+// e1 is the second buffer, cnt holds 16*NT u16 counters and wsum NT/64
+// words.  Returns which buffer (0 or 1) holds the sorted indices.
+template <int NT, int IPT>
+__device__ inline int block_radix_sort_index(const uint32_t* key, uint16_t* e0, uint16_t* e1, uint16_t* cnt,
+                                             uint32_t* wsum, int bits)
+{
+    static_assert(IPT <= 255, "per-thread counters are bytes");
+    const int t = threadIdx.x;
+    int cur = 0;
+    for (int shift = 0; shift < bits; shift += 4) {
+        uint16_t* ei = cur ? e1 : e0;
+        uint16_t* eo = cur ? e0 : e1;
+        uint16_t e[IPT];
+        uint32_t dl[IPT];  // digit | rank among the thread's equal digits << 4
+        uint32_t c[4] = {0u, 0u, 0u, 0u};  // 16 byte-sized digit counters
+#pragma unroll
+        for (int j = 0; j < IPT; j++) e[j] = ei[t * IPT + j];
+#pragma unroll
+        for (int j = 0; j < IPT; j++) {
+            const uint32_t d = (key[e[j]] >> shift) & 15u;
+            const uint32_t sh = (d & 3u) * 8u;
+            const uint32_t r = d >> 2;
+            const uint32_t cur_c = r == 0 ? c[0] : r == 1 ? c[1] : r == 2 ? c[2] : c[3];
+            dl[j] = d | (((cur_c >> sh) & 0xFFu) << 4);
+            const uint32_t inc = 1u << sh;
+            c[0] += r == 0 ? inc : 0u;
+            c[1] += r == 1 ? inc : 0u;
+            c[2] += r == 2 ? inc : 0u;
+            c[3] += r == 3 ? inc : 0u;
+        }
+#pragma unroll
+        for (int dd = 0; dd < 16; dd++) cnt[dd * NT + t] = (uint16_t)((c[dd >> 2] >> ((dd & 3) * 8)) & 0xFFu);
+        __syncthreads();
+        // exclusive scan over cnt in (digit, thread) order; thread t owns 16
+        // consecutive counters (read twice rather than held in registers)
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < 16; i++) sum += cnt[t * 16 + i];
+        uint32_t run = block_exclusive_scan<NT>(sum, wsum, nullptr);
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            const uint32_t v = cnt[t * 16 + i];
+            cnt[t * 16 + i] = (uint16_t)run;
+            run += v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; j++) eo[(uint32_t)cnt[(dl[j] & 15u) * NT + t] + (dl[j] >> 4)] = e[j];
+        __syncthreads();
+        cur ^= 1;
+    }
+    return cur;
+}
+
 // ------------------------------------------------------- spin waiting
 __device__ inline int32_t ld_acquire(const int32_t* p)
 {

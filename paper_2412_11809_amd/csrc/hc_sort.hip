@@ -48,11 +48,11 @@ hipError_t launch_init(const Work& w, hipStream_t s)
 // NT threads sort a tile of T = NT * IPT hits (8192-hit tiles use 1024
 // threads: their LDS allows one work-group per CU, so it gets more waves).
 template <int NT, int IPT>
-__global__ __launch_bounds__(NT) void k_tile_sort(const hc_hit* __restrict__ hits, Work w)
+__global__ __launch_bounds__(NT, NT == 512 ? 6 : 4) void k_tile_sort(const hc_hit* __restrict__ hits, Work w)
 {
     constexpr int T = NT * IPT;
-    __shared__ uint32_t k0[T], k1[T];
-    __shared__ uint16_t v0[T], v1[T];
+    __shared__ uint32_t kr[T];  // ToA - tile minimum, by input position
+    __shared__ uint16_t e0[T], e1[T];
     __shared__ uint16_t cnt[16 * NT];
     __shared__ uint32_t wsum[NT / kWave];
     __shared__ uint64_t red[NT / kWave];
@@ -64,26 +64,27 @@ __global__ __launch_bounds__(NT) void k_tile_sort(const hc_hit* __restrict__ hit
     const int64_t base = tr.start;
     const int cnt_e = tr.count;
 
+    // ToAs first; the pixel (checked against the sensor) comes with the
+    // payload once the tile is sorted
     uint64_t toa[IPT];
     uint64_t tmin = ~0ull, tmax = 0;
-    bool bad = false;
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
         const int e = t + j * NT;
         toa[j] = 0;
         if (e < cnt_e) {
-            const hc_hit h = hits[base + e];
-            toa[j] = h.toa;
-            tmin = h.toa < tmin ? h.toa : tmin;
-            tmax = h.toa > tmax ? h.toa : tmax;
-            bad |= (h.x >= w.width) | (h.y >= w.height);
+            toa[j] = hits[base + e].toa;
+            tmin = toa[j] < tmin ? toa[j] : tmin;
+            tmax = toa[j] > tmax ? toa[j] : tmax;
         }
     }
-    if (bad) atomicOr(&w.status->err_range, 1);
     tmin = block_min_u64<NT>(tmin, red);
     tmax = block_max_u64<NT>(tmax, red);
     const uint64_t range = tmax - tmin;
     if (range > 0xFFFFFFFFull) {
+        bool bad = false;
+        for (int e = t; e < cnt_e; e += NT) bad |= (hits[base + e].x >= w.width) | (hits[base + e].y >= w.height);
+        if (bad) atomicOr(&w.status->err_range, 1);
         if (t == 0) {
             TileInfo ti;
             ti.base = tmin;
@@ -100,15 +101,15 @@ __global__ __launch_bounds__(NT) void k_tile_sort(const hc_hit* __restrict__ hit
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
         const int e = t + j * NT;
-        k0[e] = e < cnt_e ? (uint32_t)(toa[j] - tmin) : 0xFFFFFFFFu;
-        v0[e] = (uint16_t)e;
+        kr[e] = e < cnt_e ? (uint32_t)(toa[j] - tmin) : 0xFFFFFFFFu;
+        e0[e] = (uint16_t)e;
     }
     __syncthreads();
     const int bits = range == 0 ? 0 : 32 - __builtin_clz((uint32_t)range);
-    const int which = block_radix_sort<NT, IPT>(k0, v0, k1, v1, cnt, wsum, bits);
-    const uint32_t* sk = which ? k1 : k0;
-    const uint16_t* sv = which ? v1 : v0;
-#pragma unroll
+    const int which = block_radix_sort_index<NT, IPT>(kr, e0, e1, cnt, wsum, bits);
+    const uint16_t* sv = which ? e1 : e0;
+    bool bad = false;
+#pragma unroll 2
     for (int j = 0; j < IPT; j++) {
         const int e = t + j * NT;
         if (e < cnt_e) {
@@ -118,11 +119,13 @@ __global__ __launch_bounds__(NT) void k_tile_sort(const hc_hit* __restrict__ hit
                 l = 0;
             }
             const hc_hit h = hits[base + l];
-            w.ts_rel[base + e] = sk[e];
+            bad |= (h.x >= w.width) | (h.y >= w.height);
+            w.ts_rel[base + e] = kr[l];
             w.ts_pay[base + e] = make_uint2((uint32_t)l | ((uint32_t)h.tot << 16),
                                             (uint32_t)h.x | ((uint32_t)h.y << 16));
         }
     }
+    if (bad) atomicOr(&w.status->err_range, 1);
     if (t == 0) {
         TileInfo ti;
         ti.base = tmin;
