@@ -158,12 +158,38 @@ def bench_small(hc, torch, dev, calls=200):
     torch.cuda.synchronize(dev)
     back_to_back_ms = (time.perf_counter() - t0) * 1e3 / calls
     lat.sort()
+    n_clusters = int(k.item())
+    # the same call as a one-chunk batch captured in a HIP graph: one launch per call
+    import numpy as np
+    k1 = torch.empty(1, dtype=torch.int32, device=dev)
+    graph = hc.hc_batch_graph_create(d, np.array([0, n], np.int64), np.array([p["dt"]], np.uint64), labels, feats,
+                                     k1, None, p["width"], p["height"], p["disorder"])
+    for _ in range(10):
+        graph.launch(stream)
+    torch.cuda.synchronize(dev)
+    glat = []
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        graph.launch(stream)
+        torch.cuda.synchronize(dev)
+        glat.append((time.perf_counter() - t0) * 1e3)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        graph.launch(stream)
+    torch.cuda.synchronize(dev)
+    graph_b2b_ms = (time.perf_counter() - t0) * 1e3 / calls
+    assert int(k1.item()) == n_clusters, "graph replay cluster count differs"
+    graph.close()
+    glat.sort()
     return {"workload": "plain hc_cluster: 256x256 sensor, %d hits of random-walk blobs over 10 ms, "
                         "dt = 200 ns" % n,
-            "n_hits": n, "n_clusters": int(k.item()), "calls": calls,
+            "n_hits": n, "n_clusters": n_clusters, "calls": calls,
             "latency_ms": {"p50": round(lat[len(lat) // 2], 4), "p99": round(lat[int(len(lat) * 0.99)], 4)},
             "back_to_back_ms_per_call": round(back_to_back_ms, 4),
-            "note": "latency = one call from the host until its results are on the device, synchronised"}
+            "graph_latency_ms": {"p50": round(glat[len(glat) // 2], 4), "p99": round(glat[int(len(glat) * 0.99)], 4)},
+            "graph_back_to_back_ms_per_call": round(graph_b2b_ms, 4),
+            "note": "latency = one call from the host until its results are on the device, synchronised; "
+                    "graph = the same call captured once as a one-chunk batch and replayed"}
 
 
 def bench_batch(hc, torch, dev, reps):
