@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint
     __shared__ PixT l_pix[LCAP];          // pixel id y * W + x
     __shared__ int32_t l_par[LCAP];
     __shared__ uint16_t csr[LCAP];        // slots grouped by pixel rank
-    __shared__ uint16_t pstart[LCAP + 2]; // counts (packed in pairs), then end of each rank's CSR segment
+    __shared__ uint16_t pstart[LCAP + 2]; // counts (packed in pairs), then start of each rank's CSR segment
     __shared__ uint32_t wsum[kLinkThreads / kWave];
     extern __shared__ uint64_t dyn64[];
     uint64_t* bm = dyn64;
@@ -396,10 +396,17 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint
                 }
         }
         __syncthreads();
-        // ---- hits per occupied pixel (counts stay below 2^16: no carry between halves)
-        for (int i = t; i < L; i += kLinkThreads) {
-            const uint32_t r = pix_rank(l_pix[i], bm, wpre);
-            atomicAdd(&pcount[r >> 1], 1u << (16u * (r & 1u)));
+        // ---- hits per occupied pixel (counts stay below 2^16: no carry between
+        // halves); the count a hit sees is its place in its pixel's segment
+        uint32_t rp[LPER];  // pixel rank | place in the segment << 16
+#pragma unroll
+        for (int q = 0; q < LPER; q++) {
+            const int i = t + q * kLinkThreads;
+            if (i < L) {
+                const uint32_t r = pix_rank(l_pix[i], bm, wpre);
+                const uint32_t half = 16u * (r & 1u);
+                rp[q] = r | (((atomicAdd(&pcount[r >> 1], 1u << half) >> half) & 0xFFFFu) << 16);
+            }
         }
         __syncthreads();
         // ---- exclusive scan of the counts -> first CSR position per pixel rank
@@ -417,15 +424,14 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint
                 pstart[t * LPER + k] = (uint16_t)run;
                 run += c[k];
             }
+            if (t == kLinkThreads - 1) pstart[LCAP] = (uint16_t)run;  // end of the last segment
         }
         __syncthreads();
-        // ---- fill: each hit takes the next position of its pixel's segment;
-        // afterwards pstart[r] is the end of segment r (its start is pstart[r - 1])
-        for (int i = t; i < L; i += kLinkThreads) {
-            const uint32_t r = pix_rank(l_pix[i], bm, wpre);
-            const uint32_t half = 16u * (r & 1u);
-            const uint32_t pos = (atomicAdd(&pcount[r >> 1], 1u << half) >> half) & 0xFFFFu;
-            csr[pos] = (uint16_t)i;
+        // ---- fill: segment r is [pstart[r], pstart[r + 1])
+#pragma unroll
+        for (int q = 0; q < LPER; q++) {
+            const int i = t + q * kLinkThreads;
+            if (i < L) csr[pstart[rp[q] & 0xFFFFu] + (rp[q] >> 16)] = (uint16_t)i;
         }
         __syncthreads();
         // ---- neighbour search: an earlier hit within dt per neighbour pixel.
@@ -469,8 +475,8 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint
                 const uint32_t o = occ[d / 3];
                 const bool has = (o >> (d % 3)) & 1u;
                 const int r = has ? rk0[d / 3] + __popc(o & ((1u << (d % 3)) - 1u)) : 0;
-                const int e = pstart[r];
-                const int b = r ? (int)pstart[r - 1] : 0;
+                const int b = pstart[r];
+                const int e = pstart[r + 1];
                 s0[d] = has ? b : 0;
                 s1[d] = has ? e : 0;
             }
