@@ -10,8 +10,8 @@
  * What it computes (paper, Section 2, conditions (i), (ii) and (iii)(a)):
  *   Two hits a != b are adjacent when
  *     - their pixels are 8-neighbours or the same pixel
- *       (Chebyshev distance max(|dx|,|dy|) <= 1; Section 4.1 searches
- *       "the 8 neighbouring pixels plus the pixel itself"), and
+ *       (Chebyshev distance max(|dx|,|dy|) <= 1; Section 4.1 searches a
+ *       hit's own pixel and its eight neighbours), and
  *     - |toa(a) - toa(b)| <= dt  (the dynamic local-time-neighbourhood
  *       variant, Section 2 (iii)(a), read as "there is a path whose every
  *       step is spatially adjacent and time-close").

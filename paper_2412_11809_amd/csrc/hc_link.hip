@@ -1,8 +1,8 @@
 // Steps A2 and A3 of the clustering path: neighbour search and union-find.
 //
 // The paper (Section 4.1) sweeps the ToA-sorted hits, finds for each hit the
-// latest earlier hit at each of "the 8 neighbouring pixels plus the pixel
-// itself" through a per-pixel matrix, and joins the clusters with union-find.
+// latest earlier hit at its own pixel and at each of its eight neighbours
+// through a per-pixel matrix, and joins the clusters with union-find.
 // Its GPU version gives every thread one chunk and one full 256 x 256 matrix.
 //
 // Here each work-group takes a tile of kLinkTile consecutive sorted hits plus
