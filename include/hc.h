@@ -12,9 +12,9 @@
  *                             step is between 8-neighbouring (or identical)
  *                             pixels and whose ToAs differ by at most dt.
  *   Parallel method ......... Section 4.1 and its Algorithm "High-level GPU
- *                             clustering": sort by ToA, search the 8
- *                             neighbouring pixels plus the pixel itself for
- *                             the latest earlier hit, and join clusters with a
+ *                             clustering": sort by ToA, search a hit's own
+ *                             pixel and its eight neighbours for the latest
+ *                             earlier hit, and join clusters with a
  *                             union-find forest with path compression.
  *   Features ................ Sections 1 and 6 motivate per-cluster features;
  *                             the set below is this library's.
