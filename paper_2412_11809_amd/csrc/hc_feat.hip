@@ -115,17 +115,27 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         const bool own_lane = valid && (uint32_t)idx[q] + 1u == (h_key[s] & ~kOwn);
         const unsigned long long owners = __ballot(own_lane);
         const uint32_t P_st = wave_incl_scan_u32(st);
-        const uint32_t P_sx = wave_incl_scan_u32(x);
-        const uint32_t P_sy = wave_incl_scan_u32(y);
         const uint64_t P_sxt = wave_incl_scan_u64((uint64_t)x * st);
         const uint64_t P_syt = wave_incl_scan_u64((uint64_t)y * st);
+        // the unweighted coordinate sums only serve a cluster whose ToTs are
+        // all zero; a wave without a zero ToT cannot hold a hit of one
+        const bool zero_tot = __ballot(valid && st == 0u) != 0ull;
+        uint32_t P_sx = 0, P_sy = 0;
+        if (zero_tot) {
+            P_sx = wave_incl_scan_u32(x);
+            P_sy = wave_incl_scan_u32(y);
+        }
         // prefix sums just before the run (lane start - 1; 0 for a run at lane
         // 0).  Every lane takes part in each shuffle: a lane that sat one out
         // would not supply its value to the lanes reading from it.
         const int src = start > 0 ? start - 1 : 0;
         const bool first = start == 0;
-        const uint32_t B_st = __shfl(P_st, src, kWave), B_sx = __shfl(P_sx, src, kWave);
-        const uint32_t B_sy = __shfl(P_sy, src, kWave);
+        const uint32_t B_st = __shfl(P_st, src, kWave);
+        uint32_t B_sx = 0, B_sy = 0;
+        if (zero_tot) {
+            B_sx = __shfl(P_sx, src, kWave);
+            B_sy = __shfl(P_sy, src, kWave);
+        }
         const uint64_t B_sxt = __shfl(P_sxt, src, kWave), B_syt = __shfl(P_syt, src, kWave);
         const uint32_t pos = wide ? (uint32_t)(t + q * kFeatThreads) : (uint32_t)(toa[q] - tfirst);
         const uint32_t pmn = (uint32_t)__shfl((int)pos, start, kWave);
@@ -134,7 +144,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
             const uint64_t n_st = P_st - (first ? 0u : B_st);
             const uint64_t n_sx = P_sx - (first ? 0u : B_sx), n_sy = P_sy - (first ? 0u : B_sy);
             atomicAdd(&a_cs[s], (unsigned long long)((uint64_t)(lane - start + 1) | (n_st << 32)));
-            atomicAdd(&a_xy[s], (unsigned long long)(n_sx | (n_sy << 32)));
+            if (zero_tot) atomicAdd(&a_xy[s], (unsigned long long)(n_sx | (n_sy << 32)));
             atomicAdd(&a_sxt[s], (unsigned long long)(P_sxt - (first ? 0ull : B_sxt)));
             atomicAdd(&a_syt[s], (unsigned long long)(P_syt - (first ? 0ull : B_syt)));
             atomicMin(&a_pmin[s], pmn);

@@ -219,6 +219,14 @@ def test_link_variants(hc, case, variant):
         assert_parity(hc, hits, 100, 100, 5, 512, flags=flag)
 
 
+def test_zero_tot_regions(hc):
+    # clusters left of x = 128 have ToT 0 throughout (their centroid is the
+    # unweighted mean), clusters across x = 128 mix zero and non-zero ToT
+    hits, p = hitgen.mixed_10m(n=300_000, seed=97)
+    hits["tot"][hits["x"] < 128] = 0
+    assert_parity(hc, hits, p["width"], p["height"], p["dt"], p["disorder"])
+
+
 @pytest.mark.parametrize("w,h", [(16384, 8), (8, 16384), (16385, 3), (3, 40000)])
 def test_large_sensor_coordinates(hc, w, h):
     # clusters at the far corners: window scan up to 16384, pixel index beyond
