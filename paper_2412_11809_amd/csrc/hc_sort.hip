@@ -9,8 +9,9 @@
 //                 sorted order plus its min/max keys;
 //   k_tile_rank   gives every element its global rank: all of its tile's
 //                 predecessors plus, for each of the m neighbour tiles on both
-//                 sides, the number of smaller keys there (binary search in
-//                 LDS), and writes the element's sorted record at that rank.
+//                 sides, the number of smaller keys there (a merge path of the
+//                 two sorted tiles in LDS; binary searches for short tiles),
+//                 and writes the element's sorted record at that rank.
 //                 This is exact whenever tiles more than m apart do not
 //                 interleave, which the kernel verifies from the tile min/max
 //                 keys: tile minima ascend and the max of tile i lies below
@@ -207,39 +208,89 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
 
     const int64_t base = jr.start;
     const int r0 = t * IPT;
-    uint64_t toa[IPT];
-    uint32_t rank[IPT];
     const int first_tile = j - m < t0 ? t0 : j - m;
-#pragma unroll
-    for (int q = 0; q < IPT; q++) {
-        const int r = r0 + q;
-        toa[q] = r < tj.count ? tj.base + w.ts_rel[base + r] : ~0ull;
-        rank[q] = (uint32_t)((int64_t)(first_tile - t0) * T + r);
-    }
     const int last_tile = j + m >= nt ? nt - 1 : j + m;
-    for (int i = first_tile; i <= last_tile; i++) {
-        if (i == j) continue;
-        const TileInfo ti = w.tiles[i];
-        // tiles that do not overlap this one in ToA: every count is all or none
-        if (i < j ? tj.base >= ti.max_toa : tj.max_toa < ti.base) {
-            if (i < j) {
+    uint32_t rank[IPT];
 #pragma unroll
-                for (int q = 0; q < IPT; q++) rank[q] += (uint32_t)ti.count;
-            }
-            continue;
+    for (int q = 0; q < IPT; q++) rank[q] = (uint32_t)((int64_t)(first_tile - t0) * T + r0 + q);
+    // a neighbour tile that does not overlap this one in ToA counts all or none
+    auto disjoint = [&](int i, const TileInfo& ti) {
+        if (!(i < j ? tj.base >= ti.max_toa : tj.max_toa < ti.base)) return false;
+        if (i < j) {
+#pragma unroll
+            for (int q = 0; q < IPT; q++) rank[q] += (uint32_t)ti.count;
         }
-        const int64_t ibase = jr.seg_start + (int64_t)(i - t0) * T;
-        __syncthreads();
-        for (int e = t; e < ti.count; e += kSortThreads) nk[e] = w.ts_rel[ibase + e];
-        __syncthreads();
-        // a thread whose smallest key lies beyond the whole tile counts all of it
-        const bool all = i < j ? toa[0] >= ti.max_toa : toa[0] > ti.max_toa;
-        int lo = 0;
+        return true;
+    };
+    if constexpr (IPT >= 8) {
+        // Merge path of this tile (A) with each overlapping neighbour (B): a
+        // neighbour element goes first when its ToA is <= (earlier tile,
+        // smaller indices) or < (later tile) the element's.  Each thread
+        // takes an equal share of the merged sequence: one binary search for
+        // where its share starts, then a sequential merge that records, for
+        // every A element it places, how many B elements precede it.
+        __shared__ uint32_t ak[T];
+        __shared__ uint16_t below[T];  // per element of this tile: neighbour elements below it
+        for (int e = t; e < tj.count; e += kSortThreads) ak[e] = w.ts_rel[base + e];
+        for (int i = first_tile; i <= last_tile; i++) {
+            if (i == j) continue;
+            const TileInfo ti = w.tiles[i];
+            if (disjoint(i, ti)) continue;
+            const int64_t ibase = jr.seg_start + (int64_t)(i - t0) * T;
+            __syncthreads();  // nk and below of the previous neighbour are no longer read
+            for (int e = t; e < ti.count; e += kSortThreads) nk[e] = w.ts_rel[ibase + e];
+            __syncthreads();
+            const bool earlier = i < j;
+            const int na = tj.count, nb = ti.count;
+            auto b_first = [&](int bi, int ai) {
+                const uint64_t tb = ti.base + nk[bi], ta = tj.base + ak[ai];
+                return earlier ? tb <= ta : tb < ta;
+            };
+            const int total = na + nb;
+            const int per = (total + kSortThreads - 1) / kSortThreads;
+            const int d0 = t * per < total ? t * per : total;
+            const int d1 = d0 + per < total ? d0 + per : total;
+            int lo = d0 - nb > 0 ? d0 - nb : 0, hi = d0 < na ? d0 : na;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (!b_first(d0 - mid - 1, mid)) lo = mid + 1; else hi = mid;
+            }
+            int ai = lo, bi = d0 - lo;
+            for (int d = d0; d < d1; d++) {
+                if (bi < nb && (ai == na || b_first(bi, ai))) {
+                    bi++;
+                } else {
+                    below[ai] = (uint16_t)bi;
+                    ai++;
+                }
+            }
+            __syncthreads();
 #pragma unroll
-        for (int q = 0; q < IPT; q++) {
-            if (r0 + q < tj.count) {
-                lo = all ? ti.count : count_below(nk, ti.count, ti.base, toa[q], i < j, lo);
-                rank[q] += (uint32_t)lo;
+            for (int q = 0; q < IPT; q++)
+                if (r0 + q < tj.count) rank[q] += below[r0 + q];
+        }
+    } else {
+        // short tiles: a binary search per element and neighbour
+        uint64_t toa[IPT];
+#pragma unroll
+        for (int q = 0; q < IPT; q++) toa[q] = r0 + q < tj.count ? tj.base + w.ts_rel[base + r0 + q] : ~0ull;
+        for (int i = first_tile; i <= last_tile; i++) {
+            if (i == j) continue;
+            const TileInfo ti = w.tiles[i];
+            if (disjoint(i, ti)) continue;
+            const int64_t ibase = jr.seg_start + (int64_t)(i - t0) * T;
+            __syncthreads();
+            for (int e = t; e < ti.count; e += kSortThreads) nk[e] = w.ts_rel[ibase + e];
+            __syncthreads();
+            // a thread whose smallest key lies beyond the whole tile counts all of it
+            const bool all = i < j ? toa[0] >= ti.max_toa : toa[0] > ti.max_toa;
+            int lo = 0;
+#pragma unroll
+            for (int q = 0; q < IPT; q++) {
+                if (r0 + q < tj.count) {
+                    lo = all ? ti.count : count_below(nk, ti.count, ti.base, toa[q], i < j, lo);
+                    rank[q] += (uint32_t)lo;
+                }
             }
         }
     }

@@ -2,7 +2,8 @@
 element against the m neighbour tiles on each side): whenever the check on
 the tile minimum/maximum keys passes, the ranks are exactly the positions in
 (toa, index) order, and a displacement of at most m*T/2 always passes it --
-also when the last tile is short."""
+also when the last tile is short.  Also the merge-path form of the
+neighbour counts (equal shares of the merged sequence per thread)."""
 import numpy as np
 import pytest
 
@@ -82,3 +83,52 @@ def test_blob_stream_ranks():
         r = tile_ranks(toa, T, m)
         assert r is not None
         assert np.array_equal(r, true_ranks(toa))
+
+
+def merge_path_counts(A, B, earlier, threads):
+    """The tile rank's neighbour counts: for every key of the sorted tile A,
+    how many keys of the sorted neighbour B go before it (B <= A for an
+    earlier neighbour, whose indices are smaller; B < A for a later one),
+    each of `threads` threads merging an equal share of the merged sequence
+    after one binary search for where its share starts."""
+    na, nb = len(A), len(B)
+    below = [None] * na
+
+    def b_first(bi, ai):
+        return B[bi] <= A[ai] if earlier else B[bi] < A[ai]
+
+    total = na + nb
+    per = -(-total // threads)
+    for t in range(threads):
+        d0 = min(t * per, total)
+        d1 = min(d0 + per, total)
+        lo, hi = max(d0 - nb, 0), min(d0, na)
+        while lo < hi:
+            mid = (lo + hi) >> 1
+            if not b_first(d0 - mid - 1, mid):
+                lo = mid + 1
+            else:
+                hi = mid
+        ai, bi = lo, d0 - lo
+        for _ in range(d0, d1):
+            if bi < nb and (ai == na or b_first(bi, ai)):
+                bi += 1
+            else:
+                assert below[ai] is None, "an element placed twice"
+                below[ai] = bi
+                ai += 1
+    return below
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_merge_path_counts(seed):
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(200):
+        na, nb = int(rng.integers(1, 70)), int(rng.integers(1, 70))
+        threads = int(rng.integers(1, 24))
+        span = int(rng.integers(1, 50))  # small spans: many equal keys
+        A = sorted(rng.integers(0, span, na).tolist())
+        B = sorted(rng.integers(0, span, nb).tolist())
+        for earlier in (True, False):
+            want = [sum(1 for b in B if (b <= a if earlier else b < a)) for a in A]
+            assert merge_path_counts(A, B, earlier, threads) == want
