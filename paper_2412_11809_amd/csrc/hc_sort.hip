@@ -119,11 +119,11 @@ __global__ __launch_bounds__(NT, NT == 512 ? 6 : 4) void k_tile_sort(const hc_hi
                 atomicOr(&w.status->err_internal, 1);
                 l = 0;
             }
-            const hc_hit h = hits[base + l];
-            bad |= (h.x >= w.width) | (h.y >= w.height);
+            // the record's second half: x | y << 16, tot | reserved << 16
+            const uint2 xyt = reinterpret_cast<const uint2*>(hits + base + l)[1];
+            bad |= ((xyt.x & 0xFFFFu) >= w.width) | ((xyt.x >> 16) >= w.height);
             w.ts_rel[base + e] = kr[l];
-            w.ts_pay[base + e] = make_uint2((uint32_t)l | ((uint32_t)h.tot << 16),
-                                            (uint32_t)h.x | ((uint32_t)h.y << 16));
+            w.ts_pay[base + e] = make_uint2((uint32_t)l | (xyt.y << 16), xyt.x);
         }
     }
     if (bad) atomicOr(&w.status->err_range, 1);
@@ -213,6 +213,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
     uint32_t rank[IPT];
 #pragma unroll
     for (int q = 0; q < IPT; q++) rank[q] = (uint32_t)((int64_t)(first_tile - t0) * T + r0 + q);
+    __shared__ uint32_t ak[IPT >= 8 ? T : 1];  // this tile's keys (merge path)
     // a neighbour tile that does not overlap this one in ToA counts all or none
     auto disjoint = [&](int i, const TileInfo& ti) {
         if (!(i < j ? tj.base >= ti.max_toa : tj.max_toa < ti.base)) return false;
@@ -229,7 +230,6 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
         // takes an equal share of the merged sequence: one binary search for
         // where its share starts, then a sequential merge that records, for
         // every A element it places, how many B elements precede it.
-        __shared__ uint32_t ak[T];
         __shared__ uint16_t below[T];  // per element of this tile: neighbour elements below it
         for (int e = t; e < tj.count; e += kSortThreads) ak[e] = w.ts_rel[base + e];
         for (int i = first_tile; i <= last_tile; i++) {
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
     for (int e = t; e < tj.count; e += kSortThreads) {
         const int64_t dst = jr.seg_start + nk[e];
         const uint2 pay = w.ts_pay[base + e];
-        w.s_toa[dst] = tj.base + w.ts_rel[base + e];
+        w.s_toa[dst] = tj.base + (IPT >= 8 ? ak[e] : w.ts_rel[base + e]);
         w.s_idx[dst] = (int32_t)(base + (pay.x & 0xFFFFu));
         w.s_tot[dst] = (uint16_t)(pay.x >> 16);
         w.s_xy[dst] = pay.y;
