@@ -147,10 +147,12 @@ __device__ inline bool link_tile_load(const Work& w, int tile, const TileRange& 
 }
 
 // Joins of one tile (cand: per tile hit, the slot joined at each of its 9
-// pixels, or -1) applied in bulk rounds in the LDS forest l_par: hook every
-// edge's larger root under the smaller (atomic minimum) and retire the edges
-// already inside one tree, then walk every slot to its root; repeat until no
-// edge joins two roots.  Then the
+// pixels, or -1) applied in the LDS forest l_par: first every tile hit hangs
+// under its smallest candidate (a plain store by its own thread) and every
+// slot walks to its root; then bulk rounds hook every edge's larger root
+// under the smaller (atomic minimum) and retire the edges already inside one
+// tree, then walk every slot to its root; repeat until no edge joins two
+// roots.  Then the
 // smallest input index of every local tree is published: as the parent of
 // the tree's tile hits, and as cross-tile edges for its halo hits.
 // minidx: LDS scratch of L words (the caller's ToA array, no longer read).
@@ -160,6 +162,30 @@ __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_pa
                                           int32_t* minidx)
 {
     const int t = threadIdx.x;
+    // first round without atomics: every tile hit hangs under its smallest
+    // candidate (only its own thread writes its pointer), then the walks
+    __syncthreads();  // the caller's search has read the slots' data
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = hl + t + q * kLinkThreads;
+        if (i >= L) continue;
+        int mn = i;
+#pragma unroll
+        for (int k = 0; k < 9; k++)
+            if (cand[q][k] >= 0 && cand[q][k] < mn) mn = cand[q][k];
+        l_par[i] = mn;
+    }
+    __syncthreads();
+    for (int x = t; x < L; x += kLinkThreads) {
+        int p = l_par[x];
+        while (true) {
+            const int g = l_par[p];
+            if (g == p) break;
+            l_par[x] = g;
+            p = g;
+        }
+    }
+    __syncthreads();
     while (true) {
         bool changed = false;
 #pragma unroll
