@@ -472,7 +472,7 @@ def main():
         args.steps, args.warmup = 1, 0
         args.no_batch, args.no_served = args.only != "batch", args.only != "served"
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py: the library runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
