@@ -5,19 +5,22 @@
 // task (Section 6).  Here the features are reduced without moving any hit:
 //   k_features  per tile of kFeatTile sorted hits: an LDS hash keyed by the
 //               cluster label gathers each cluster's partial sums (size, ToT,
-//               x*ToT, y*ToT, x, y) and its ToA min/max (32-bit offsets
-//               from the tile's first ToA; in the rare tile whose ToA span
-//               exceeds 32 bits, the tile positions of the cluster's first
-//               and last hit, the tile being in ToA order) with LDS
-//               atomics.  The one
-//               tile that holds the cluster's label hit (idx == label) stores
-//               its partial as the cluster's record; every other tile queues
-//               its partial as a "carry";
+//               x*ToT, y*ToT, and x, y where a ToT is zero) and its ToA
+//               min/max (32-bit offsets from the tile's first ToA; in the
+//               rare tile whose ToA span exceeds 32 bits, the tile positions
+//               of the cluster's first and last hit, the tile being in ToA
+//               order) with LDS atomics.  The one tile that holds the
+//               cluster's label hit (idx == label) stores its partial as the
+//               cluster's record; every other tile queues its partial as a
+//               "carry";
 //   k_carries   folds the carries into the records with 64-bit atomics;
-//   k_compact   decoupled look-back scan over input indices: every index with
-//               labels[i] == i is a cluster, and its record becomes
-//               features[rank] (ascending label order) with the centroid
-//               cx = (double)sum_x_tot / (double)sum_tot (IEEE division).
+//   k_scan_blocks, k_compact
+//               the flatten pass flagged every root (labels[i] == i) in a
+//               bit mask with a count per block of input indices; one
+//               work-group scans the counts, then each block writes its
+//               roots' records as features[rank] (ascending label order)
+//               with the centroid cx = (double)sum_x_tot / (double)sum_tot
+//               (IEEE division).
 #include "hc_device.h"
 
 namespace hc {
