@@ -239,3 +239,34 @@ def test_large_sensor_coordinates(hc, w, h):
     hits["toa"] = np.sort(rng.integers(0, 4_000_000, n))
     hits["tot"] = rng.integers(1, 100, n)
     assert_parity(hc, hits, w, h, 100, 512)
+
+
+def test_random_sweep(hc):
+    """300 seeded random configurations: stream kind, size (log-uniform
+    50..200k), sensor, dt, disorder hint and neighbour-search variant."""
+    rng = np.random.default_rng(2412)
+    for case in range(300):
+        kind = ["blobs", "mixed", "uniform", "tpx4"][int(rng.integers(4))]
+        n = int(np.exp(rng.uniform(np.log(50), np.log(200_000))))
+        seed = int(rng.integers(1 << 30))
+        if kind == "blobs":
+            hits = hitgen.blob_stream(n, seed, 256, 256, span_ticks=max(64, n * int(rng.choice([8, 64, 640]))),
+                                      disorder=int(rng.choice([0, 64, 512, 4096])))
+            w = h = 256
+            dt = int(rng.choice([1, 32, 128, 1000]))
+        elif kind == "mixed":
+            hits, _ = hitgen.mixed_10m(n=n, seed=seed)
+            w = h = 256
+            dt = int(rng.choice([64, 128, 400]))
+        elif kind == "uniform":
+            w, h = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+            hits = hitgen.uniform_hits(n, seed, w, h, n * int(rng.choice([1, 10, 100])) + 1,
+                                       disorder=int(rng.choice([0, 30, 300])))
+            dt = int(rng.choice([0, 5, 50]))
+        else:
+            hits, p = hitgen.timepix4_200m(n=n, seed=seed)
+            w, h, dt = p["width"], p["height"], p["dt"]
+        hint = int(rng.choice([0, 256, 1024, 4096, 16384]))
+        flags = int(rng.choice([0, hc.HC_FLAG_LINK_PIXEL_INDEX, hc.HC_FLAG_LINK_WINDOW]))
+        print("sweep case", case, kind, n, seed, flush=True)
+        assert_parity(hc, hits, w, h, dt, hint, flags=flags)
