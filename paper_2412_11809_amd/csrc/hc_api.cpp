@@ -101,6 +101,7 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.blk_count = (uint32_t*)take(4 * (size_t)x.n_scan_blocks);
     x.blk_off = (uint32_t*)take(4 * (size_t)x.n_scan_blocks + 4);
     x.root_mask = (unsigned long long*)take(8 * (size_t)x.n_scan_blocks * (kScanBlock / 64));
+    x.root_wpre = (uint16_t*)take(2 * (size_t)x.n_scan_blocks * (kScanBlock / 64));
     x.fb_key[0] = (uint64_t*)take(8 * N);
     x.fb_key[1] = (uint64_t*)take(8 * N);
     x.fb_val[0] = (uint32_t*)take(4 * N);
@@ -264,11 +265,12 @@ int enqueue_cluster(const hc_hit* hits, const Work& w, int32_t* labels, hc_featu
     HC_LAUNCH(launch_link_fallback(w, s), "link_fallback");
     HC_LAUNCH(launch_union_edges(w, s), "union_edges");
     HC_LAUNCH(launch_flatten(w, labels, s), "flatten");
+    HC_LAUNCH(launch_scan_blocks(w, n_clusters, s), "scan_blocks");  // cluster ranks, before the records
     if (features) {
         HC_LAUNCH(launch_features(w, labels, s), "features");
         HC_LAUNCH(launch_carries(w, s), "carries");
+        HC_LAUNCH(launch_compact(w, features, s), "compact");
     }
-    HC_LAUNCH(launch_compact(w, features, n_clusters, s), "compact");
 #undef HC_LAUNCH
     return HC_OK;
 }

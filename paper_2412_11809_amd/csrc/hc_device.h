@@ -300,6 +300,21 @@ __device__ inline int block_radix_sort_index(const uint32_t* key, uint16_t* e0, 
     return cur;
 }
 
+// Rank of cluster root `root` (an input index of chunk `seg`, which starts at
+// input index seg_start) in ascending label order over all chunks: the roots
+// of earlier blocks (blk_off), of earlier mask words of its block
+// (root_wpre) and below it in its word.  Valid once the flatten pass and the
+// block scan have run.
+__device__ inline uint32_t root_rank(const Work& w, int seg, int64_t seg_start, int32_t root)
+{
+    const int64_t o = (int64_t)root - seg_start;
+    const int64_t b = (w.n_seg > 1 ? w.segs[seg].tile0[kScanKind] : 0) + o / kScanBlock;
+    const int bit = (int)(o % kScanBlock);
+    const int64_t wd = b * (kScanBlock / 64) + bit / 64;
+    const unsigned long long below = (1ull << (bit % 64)) - 1ull;
+    return w.blk_off[b] + w.root_wpre[wd] + (uint32_t)__popcll(w.root_mask[wd] & below);
+}
+
 // ------------------------------------------------------- spin waiting
 __device__ inline int32_t ld_acquire(const int32_t* p)
 {

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         r.sum_x = (uint32_t)sxy;
         r.sum_y = sxy >> 32;
         if (hk & kOwn) {
-            w.slots[key - 1u] = r;
+            w.slots[root_rank(w, tr.seg, tr.seg_start, r.root)] = r;
         } else {
             w.carries[base + pos++] = r;  // pos < kFeatHash: one entry per hash slot at most
         }
@@ -210,13 +210,14 @@ __global__ __launch_bounds__(64) void k_carries(Work w)
     if (w.status->err_range) return;
     for (int64_t k = blockIdx.x; k < w.n_feat_tiles; k += gridDim.x) {
         const int nc = w.tile_ncarry[k];
+        const TileRange tr = tile_range(w, kFeatKind, (int)k, kFeatTile);
         for (int c = threadIdx.x; c < nc; c += blockDim.x) {
             const SlotRec r = w.carries[k * kFeatHash + c];
-            if (r.root < 0 || r.root >= w.n) {
+            if (r.root < tr.seg_start || r.root >= tr.seg_end) {
                 atomicOr(&w.status->err_internal, 1);
                 continue;
             }
-            SlotRec* d = w.slots + r.root;
+            SlotRec* d = w.slots + root_rank(w, tr.seg, tr.seg_start, r.root);
             atomicAdd(&d->size, r.size);
             atomicAdd((unsigned long long*)&d->sum_tot, (unsigned long long)r.sum_tot);
             atomicAdd((unsigned long long*)&d->sum_xt, (unsigned long long)r.sum_xt);
@@ -271,29 +272,20 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Work w, int32_t* n_cluster
     }
 }
 
-// features[rank] for every root of one block of kScanBlock input indices.
+// features[rank] from the rank-ordered records of the roots of one block of
+// kScanBlock input indices (ranks blk_off[b] .. blk_off[b + 1] - 1).
 __global__ __launch_bounds__(kScanThreads) void k_compact(Work w, hc_features* __restrict__ out)
 {
-    constexpr int PER = kScanBlock / kScanThreads;  // 8 consecutive indices per thread
-    __shared__ uint32_t wsum[kScanThreads / kWave];
     const Status* st = w.status;
     if (st->err_range || st->err_internal || st->err_span) return;
     const int b = blockIdx.x, t = threadIdx.x;
     const TileRange tr = tile_range(w, kScanKind, b, kScanBlock);
-    const int64_t base = tr.start;
-    // bits of indices [base + PER*t, base + PER*t + PER) within mask word (PER*t)/64
-    const unsigned long long word = w.root_mask[(int64_t)b * (kScanBlock / 64) + (PER * t) / 64];
-    const uint32_t bits = (uint32_t)((word >> ((PER * t) % 64)) & ((1u << PER) - 1u));
-    const uint32_t off = block_exclusive_scan<kScanThreads>(__popc(bits), wsum, nullptr);
+    const uint32_t r0 = w.blk_off[b], r1 = w.blk_off[b + 1];
     const int64_t first = w.n_seg > 1 ? w.segs[tr.seg].out - (int64_t)w.blk_off[tr.tile0] : 0;
-    uint64_t k = (uint64_t)(first + (int64_t)w.blk_off[b] + off);
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-        if (!(bits & (1u << q))) continue;
-        const int64_t i = base + PER * t + q;
-        const SlotRec r = w.slots[i];
+    for (uint32_t k = r0 + t; k < r1; k += kScanThreads) {
+        const SlotRec r = w.slots[k];
         hc_features f;
-        f.label = (int32_t)(i - tr.seg_start);
+        f.label = (int32_t)(r.root - tr.seg_start);
         f.size = r.size;
         f.sum_tot = r.sum_tot;
         f.toa_min = r.toa_min;
@@ -307,20 +299,19 @@ __global__ __launch_bounds__(kScanThreads) void k_compact(Work w, hc_features* _
             f.cx = (double)r.sum_x / (double)r.size;
             f.cy = (double)r.sum_y / (double)r.size;
         }
-        out[k++] = f;
+        out[first + k] = f;
     }
 }
 
-hipError_t launch_compact(const Work& w, hc_features* features, int32_t* n_clusters,
-                          hipStream_t s)
+hipError_t launch_scan_blocks(const Work& w, int32_t* n_clusters, hipStream_t s)
 {
-    {
-        TimedLaunch tl("scan_blocks", s);
-        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, w, n_clusters);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (!features) return hipSuccess;
+    TimedLaunch tl("scan_blocks", s);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, w, n_clusters);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const Work& w, hc_features* features, hipStream_t s)
+{
     TimedLaunch tl("compact", s);
     hipLaunchKernelGGL(k_compact, dim3(w.n_scan_blocks), dim3(kScanThreads), 0, s, w, features);
     return hipGetLastError();

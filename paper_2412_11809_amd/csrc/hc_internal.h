@@ -141,6 +141,7 @@ struct Work {
     uint32_t* blk_count;              // roots per block of kScanBlock indices
     uint32_t* blk_off;                // exclusive scan of blk_count
     unsigned long long* root_mask;    // one bit per input index: labels[i] == i
+    uint16_t* root_wpre;              // per mask word: roots in the earlier words of its block
     uint64_t* fb_key[2];
     uint32_t* fb_val[2];
     uint32_t* fb_hist;
@@ -166,7 +167,8 @@ hipError_t launch_union_edges(const Work& w, hipStream_t s);
 hipError_t launch_flatten(const Work& w, int32_t* labels, hipStream_t s);
 hipError_t launch_features(const Work& w, const int32_t* labels, hipStream_t s);
 hipError_t launch_carries(const Work& w, hipStream_t s);
-hipError_t launch_compact(const Work& w, hc_features* features, int32_t* n_clusters, hipStream_t s);
+hipError_t launch_scan_blocks(const Work& w, int32_t* n_clusters, hipStream_t s);
+hipError_t launch_compact(const Work& w, hc_features* features, hipStream_t s);
 hipError_t launch_write_count(int32_t* n_clusters, int32_t value, hipStream_t s);
 
 // The whole plain clustering sequence on one workspace (hc_api.cpp).

@@ -757,7 +757,9 @@ hipError_t launch_union_edges(const Work& w, hipStream_t s)
 __global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __restrict__ labels)
 {
     static_assert(kScanBlock == 8 * kScanThreads && kScanThreads % kWave == 0, "mask layout");
+    static_assert(kScanBlock / 64 <= kWave, "one wave scans the block's mask words");
     __shared__ uint32_t wsum[kScanThreads / kWave];
+    __shared__ uint32_t s_wc[kScanBlock / 64];  // roots per mask word
     if (w.status->err_range) return;
     const int b = blockIdx.x;
     const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
@@ -776,12 +778,20 @@ __global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __res
             root = (r == (int32_t)i);
         }
         const unsigned long long m = __ballot(root);
-        if (lane == 0) w.root_mask[(int64_t)b * (kScanBlock / 64) + q * (kScanThreads / kWave) + wid] = m;
+        if (lane == 0) {
+            w.root_mask[(int64_t)b * (kScanBlock / 64) + q * (kScanThreads / kWave) + wid] = m;
+            s_wc[q * (kScanThreads / kWave) + wid] = (uint32_t)__popcll(m);
+        }
         c += root;
     }
     uint32_t total;
-    block_exclusive_scan<kScanThreads>(c, wsum, &total);
+    block_exclusive_scan<kScanThreads>(c, wsum, &total);  // (its barriers also publish s_wc)
     if (t == 0) w.blk_count[b] = total;
+    if (wid == 0) {  // roots in the block's earlier mask words, for rank lookups
+        const uint32_t v = lane < kScanBlock / 64 ? s_wc[lane] : 0u;
+        const uint32_t ex = wave_incl_scan_u32(v) - v;
+        if (lane < kScanBlock / 64) w.root_wpre[(int64_t)b * (kScanBlock / 64) + lane] = (uint16_t)ex;
+    }
 }
 
 hipError_t launch_flatten(const Work& w, int32_t* labels, hipStream_t s)

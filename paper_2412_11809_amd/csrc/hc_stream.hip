@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_stream_append(const hc_hit* __restrict_
 
 // A hit is final when its cluster is closed: write its stream-global label
 // into its chunk's buffer.  keep[i] = 1 for hits that stay open.
-__global__ void k_stream_close_hits(int n_all, const int32_t* __restrict__ lab, const SlotRec* __restrict__ slots,
+__global__ void k_stream_close_hits(int n_all, const int32_t* __restrict__ lab, const Work w,
                                     const int32_t* __restrict__ gidx, const int32_t* __restrict__ cslot,
                                     ChunkRec* chunks, uint64_t wmark, uint64_t dt, int flush, uint8_t* keep)
 {
@@ -80,7 +80,7 @@ __global__ void k_stream_close_hits(int n_all, const int32_t* __restrict__ lab, 
     int32_t slot = -1;
     if (i < n_all) {
         const int32_t r = lab[i];
-        closed = flush || sat_add_u64(slots[r].toa_max, dt) <= wmark;
+        closed = flush || sat_add_u64(w.slots[root_rank(w, 0, 0, r)].toa_max, dt) <= wmark;
         if (closed) {
             slot = cslot[i];
             ChunkRec* ch = chunks + slot;
@@ -384,7 +384,7 @@ static int process(hc_stream* st, int64_t n_all, uint64_t wmark, int flush)
     TimedLaunch tl("stream_close", st->s);  // the closing and compaction kernels below, together
     const int nb = (n + kCmpBlock - 1) / kCmpBlock;
     const int nxt = 1 - st->cur;
-    hipLaunchKernelGGL(k_stream_close_hits, dim3(blocks), dim3(256), 0, st->s, n, st->lab, w.slots,
+    hipLaunchKernelGGL(k_stream_close_hits, dim3(blocks), dim3(256), 0, st->s, n, st->lab, w,
                        st->gidx[st->cur], st->cslot[st->cur], st->chunks_dev, wmark, st->dt, flush, st->flags);
     hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, n, st->counts);
     hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, nb, &st->sd->n_keep);
