@@ -11,16 +11,16 @@
 //               of the cluster's first and last hit, the tile being in ToA
 //               order) with LDS atomics.  The one tile that holds the
 //               cluster's label hit (idx == label) stores its partial as the
-//               cluster's record; every other tile queues its partial as a
-//               "carry";
+//               cluster's record, at the cluster's rank in ascending label
+//               order; every other tile queues its partial as a "carry";
+//   k_scan_blocks  (runs before k_features) the flatten pass flagged every
+//               root (labels[i] == i) in a bit mask, with counts per block
+//               of input indices and per mask word; one work-group scans the
+//               block counts, which makes every root's rank three loads away;
 //   k_carries   folds the carries into the records with 64-bit atomics;
-//   k_scan_blocks, k_compact
-//               the flatten pass flagged every root (labels[i] == i) in a
-//               bit mask with a count per block of input indices; one
-//               work-group scans the counts, then each block writes its
-//               roots' records as features[rank] (ascending label order)
-//               with the centroid cx = (double)sum_x_tot / (double)sum_tot
-//               (IEEE division).
+//   k_compact   streams the rank-ordered records into features[rank] with
+//               the centroid cx = (double)sum_x_tot / (double)sum_tot (IEEE
+//               division).
 #include "hc_device.h"
 
 namespace hc {
