@@ -59,12 +59,15 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     int32_t idx[PER];
     uint64_t toa[PER];
     uint32_t xy[PER], tot[PER];
+    const int lane = t & (kWave - 1);
+    const unsigned long long le_mask = lane == kWave - 1 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         const int64_t p = p0 + t + q * kFeatThreads;
-        slot[q] = -1;
+        const bool valid = p < p_end;
         toa[q] = tfirst;
-        if (p < p_end) {
+        uint32_t key = 0u;  // label + 1; 0 for no hit
+        if (valid) {
             idx[q] = w.s_idx[p];
             toa[q] = w.s_toa[p];
             xy[q] = w.s_xy[p];
@@ -76,24 +79,34 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
                 atomicOr(&w.status->err_internal, 1);
                 lab = 0;
             }
-            const uint32_t key = (uint32_t)lab + 1u;
-            uint32_t s = root_hash(key);
+            key = (uint32_t)lab + 1u;
+        }
+        // only the first lane of each run of one cluster in the wave looks the
+        // cluster up in the hash; the run takes its slot from that lane
+        const uint32_t kp = (uint32_t)__shfl_up((int)key, 1, kWave);
+        const bool head = lane == 0 || kp != key;
+        const int start = kWave - 1 - __clzll(__ballot(head) & le_mask);
+        int s = -1;
+        if (head && valid) {
+            uint32_t h = root_hash(key);
             while (true) {
-                const uint32_t old = atomicCAS(&h_key[s], 0u, key);
+                const uint32_t old = atomicCAS(&h_key[h], 0u, key);
                 if (old == 0u) {  // first hit of this cluster here: initialise
-                    a_cs[s] = 0ull;
-                    a_xy[s] = 0ull;
-                    a_sxt[s] = 0ull;
-                    a_syt[s] = 0ull;
-                    a_pmin[s] = ~0u;
-                    a_pmax[s] = 0u;
+                    a_cs[h] = 0ull;
+                    a_xy[h] = 0ull;
+                    a_sxt[h] = 0ull;
+                    a_syt[h] = 0ull;
+                    a_pmin[h] = ~0u;
+                    a_pmax[h] = 0u;
                     break;
                 }
                 if (old == key) break;
-                s = (s + 1u) & (kFeatHash - 1);
+                h = (h + 1u) & (kFeatHash - 1);
             }
-            slot[q] = (int)s;
+            s = (int)h;
         }
+        s = __shfl(s, start, kWave);
+        slot[q] = valid ? s : -1;
     }
     __syncthreads();
     // Consecutive sorted hits of one cluster sit in consecutive lanes: reduce
@@ -102,8 +115,6 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
     // wave-wide prefix sums (DPP scans, no LDS), its size is its length, and
     // -- the lanes being in ToA order -- its ToA minimum is at its first lane
     // and its maximum at its last.
-    const int lane = t & (kWave - 1);
-    const unsigned long long le_mask = lane == kWave - 1 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         const int s = slot[q];
