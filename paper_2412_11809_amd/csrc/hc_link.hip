@@ -191,7 +191,11 @@ __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_pa
 #pragma unroll
         for (int q = 0; q < PER; q++) {
             const int i = hl + t + q * kLinkThreads;
-            if (i >= L) continue;
+            // the AND of the candidates is negative only when all are (retired)
+            int live = cand[q][0];
+#pragma unroll
+            for (int k = 1; k < 9; k++) live &= cand[q][k];
+            if (i >= L || live < 0) continue;
             const int pi = l_par[i];
 #pragma unroll
             for (int k = 0; k < 9; k++) {
@@ -210,7 +214,9 @@ __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_pa
                 }
             }
         }
-        __syncthreads();
+        // a round without hooks leaves the forest as the last walk left it:
+        // every pointer already names its root
+        if (!__syncthreads_or(changed)) break;
         // every slot walks to its root, shortening its own pointer at each
         // step: the walks of later slots on the same path reuse those jumps
         // (a pointer only ever moves to an ancestor, so any value read is valid)
@@ -223,7 +229,7 @@ __device__ inline void link_union_publish(const Work& w, int tile, int32_t* l_pa
                 p = g;
             }
         }
-        if (!__syncthreads_or(changed)) break;
+        __syncthreads();
     }
 
     // ---- smallest input index per local tree, then publish
