@@ -182,7 +182,8 @@ template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
 {
     constexpr int T = kSortThreads * IPT;
-    __shared__ uint32_t nk[T];
+    static_assert(IPT % 4 == 0, "ranks are staged four at a time");
+    __shared__ __align__(16) uint32_t nk[T];
     if (w.status->sort_fallback) return;  // a wide tile: everything is re-sorted later
     const int j = xcd_tile(w.n_sort_tiles, w.xcd_map);
     if (j < 0) return;
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
         // takes an equal share of the merged sequence: one binary search for
         // where its share starts, then a sequential merge that records, for
         // every A element it places, how many B elements precede it.
-        __shared__ uint16_t below[T];  // per element of this tile: neighbour elements below it
+        __shared__ __align__(16) uint16_t below[T];  // per element of this tile: neighbour elements below it
         for (int e = t; e < tj.count; e += kSortThreads) ak[e] = w.ts_rel[base + e];
         for (int i = first_tile; i <= last_tile; i++) {
             if (i == j) continue;
@@ -265,9 +266,18 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
                 }
             }
             __syncthreads();
+            // a thread's IPT counts are 16-byte aligned: read eight at a time
+            // (entries past the tile's count are never used)
 #pragma unroll
-            for (int q = 0; q < IPT; q++)
-                if (r0 + q < tj.count) rank[q] += below[r0 + q];
+            for (int q = 0; q < IPT; q += 8) {
+                const uint4 b = *reinterpret_cast<const uint4*>(&below[r0 + q]);
+                const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    rank[q + 2 * k] += bw[k] & 0xFFFFu;
+                    rank[q + 2 * k + 1] += bw[k] >> 16;
+                }
+            }
         }
     } else {
         // short tiles: a binary search per element and neighbour
@@ -298,9 +308,10 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
     // chunk.  Ranks pass through LDS so that consecutive lanes take
     // consecutive elements, whose ranks are mostly consecutive too.
     __syncthreads();  // the neighbour keys are no longer read
+    // four ranks per 16-byte store (entries past the tile's count are never read)
 #pragma unroll
-    for (int q = 0; q < IPT; q++)
-        if (r0 + q < tj.count) nk[r0 + q] = rank[q];
+    for (int q = 0; q < IPT; q += 4)
+        *reinterpret_cast<uint4*>(&nk[r0 + q]) = make_uint4(rank[q], rank[q + 1], rank[q + 2], rank[q + 3]);
     __syncthreads();
     for (int e = t; e < tj.count; e += kSortThreads) {
         const int64_t dst = jr.seg_start + nk[e];
