@@ -173,6 +173,11 @@ __device__ inline int count_below(const uint32_t* rel, int cnt, uint64_t base, u
     return a;
 }
 
+// LDS position of key e in the merge path's key arrays: the low three bits
+// are XORed with bits 5..7, so the sequential merges of consecutive lanes,
+// whose positions lie about eight keys apart, fall into different banks.
+__device__ inline int merge_swz(int e) { return e ^ ((e >> 5) & 7); }
+
 // Global rank of every element of tile j: all elements of tiles before
 // j - m, its position in its own tile, and its count in each neighbour tile;
 // the element's sorted record is written at that rank.  Also checks the
@@ -232,19 +237,19 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
         // where its share starts, then a sequential merge that records, for
         // every A element it places, how many B elements precede it.
         __shared__ __align__(16) uint16_t below[T];  // per element of this tile: neighbour elements below it
-        for (int e = t; e < tj.count; e += kSortThreads) ak[e] = w.ts_rel[base + e];
+        for (int e = t; e < tj.count; e += kSortThreads) ak[merge_swz(e)] = w.ts_rel[base + e];
         for (int i = first_tile; i <= last_tile; i++) {
             if (i == j) continue;
             const TileInfo ti = w.tiles[i];
             if (disjoint(i, ti)) continue;
             const int64_t ibase = jr.seg_start + (int64_t)(i - t0) * T;
             __syncthreads();  // nk and below of the previous neighbour are no longer read
-            for (int e = t; e < ti.count; e += kSortThreads) nk[e] = w.ts_rel[ibase + e];
+            for (int e = t; e < ti.count; e += kSortThreads) nk[merge_swz(e)] = w.ts_rel[ibase + e];
             __syncthreads();
             const bool earlier = i < j;
             const int na = tj.count, nb = ti.count;
             auto b_first = [&](int bi, int ai) {
-                const uint64_t tb = ti.base + nk[bi], ta = tj.base + ak[ai];
+                const uint64_t tb = ti.base + nk[merge_swz(bi)], ta = tj.base + ak[merge_swz(ai)];
                 return earlier ? tb <= ta : tb < ta;
             };
             const int total = na + nb;
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
     for (int e = t; e < tj.count; e += kSortThreads) {
         const int64_t dst = jr.seg_start + nk[e];
         const uint2 pay = w.ts_pay[base + e];
-        w.s_toa[dst] = tj.base + (IPT >= 8 ? ak[e] : w.ts_rel[base + e]);
+        w.s_toa[dst] = tj.base + (IPT >= 8 ? ak[merge_swz(e)] : w.ts_rel[base + e]);
         w.s_idx[dst] = (int32_t)(base + (pay.x & 0xFFFFu));
         w.s_tot[dst] = (uint16_t)(pay.x >> 16);
         w.s_xy[dst] = pay.y;
