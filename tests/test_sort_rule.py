@@ -127,8 +127,9 @@ def test_merge_path_counts(seed):
         na, nb = int(rng.integers(1, 70)), int(rng.integers(1, 70))
         threads = int(rng.integers(1, 24))
         span = int(rng.integers(1, 50))  # small spans: many equal keys
+        off = int(rng.integers(-span, span + 1))  # partial, full or no overlap
         A = sorted(rng.integers(0, span, na).tolist())
-        B = sorted(rng.integers(0, span, nb).tolist())
+        B = sorted((rng.integers(0, span, nb) + off).tolist())
         for earlier in (True, False):
             want = [sum(1 for b in B if (b <= a if earlier else b < a)) for a in A]
             assert merge_path_counts(A, B, earlier, threads) == want
