@@ -116,15 +116,54 @@ def traffic_from(fetch_dir, write_dir, command):
     print(json.dumps(out, indent=1))
 
 
-def cpu_baseline(hits, p, budget_s):
+def host_cpu():
+    """CPU model and the cores this process may use (the box's share)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, usable, os.cpu_count()
+
+
+def cpu_baseline(hits, p, sample_hits=4_000_000, runs=5):
+    """The oracle (sequential, one core) on the first `sample_hits` hits of the
+    workload (the paper's CPU benchmark also clusters 4M hits), median of
+    `runs` runs; clustering only, generation excluded."""
     import oracle
     oracle.load()
-    n = hits.size
-    t0 = time.perf_counter()
-    oracle.cluster(hits, p["width"], p["height"], p["dt"])
-    dt_s = time.perf_counter() - t0
-    return {"value": round(n / dt_s / 1e6, 3), "unit": "Mhit/s", "cores": 1, "kind": "oracle",
-            "sample": "the full %d-hit workload, one sequential run (%.1f s)" % (n, dt_s)}
+    sample = hits[:sample_hits]
+    n = sample.size
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.cluster(sample, p["width"], p["height"], p["dt"])
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    med = ts[len(ts) // 2]
+    model, usable, total = host_cpu()
+    return {"value": round(n / med / 1e6, 3), "unit": "Mhit/s", "cores": 1, "kind": "oracle",
+            "sample": "the first %d hits of the 10M mixed workload, median of %d sequential runs "
+                      "(%.2f s each; min %.2f, max %.2f)" % (n, runs, med, ts[0], ts[-1]),
+            "cpu_model": model, "host_cores_usable": usable, "host_cores_total": total}
+
+
+# The paper's own figure for this path, with the hardware and clock it states.
+PAPER_FIGURE = {
+    "value": 300.0, "unit": "Mhit/s",
+    "hardware": "NVIDIA RTX 4070 Ti Super 16 GB (PCIe 4.0 x16, 8848 cores) and RTX 3060 Laptop 6 GB "
+                "(PCIe 4.0 x4, 3840 cores); the paper does not say which one reached the figure",
+    "clock": "from a populated host buffer until the labels are back on the host (H2D and D2H included), "
+             "warm-up excluded, timed from the second buffer",
+    "workload": "the paper's measured datasets (not available here), so not the same workload as any line here",
+    "source": "abstract and Section 5 (benchmarking results)"}
 
 
 def bench_small(hc, torch, dev, calls=200):
@@ -257,6 +296,76 @@ def bench_batch(hc, torch, dev, reps):
                    "autotuned": round(t_plan * 1e3, 3), "graph": round(t_graph * 1e3, 3)}}
 
 
+def bench_stream(hc, torch, dev, n_total=200_000_000, chunk=1_000_000):
+    """The Timepix4-shaped stream (448x512, 300 Mhit/s, 195.3125 ps ticks,
+    blobs of min(60, Geom(mean 9)) hits, displacement <= 16384, dt = 200 ns)
+    pushed through one hc_stream as consecutive 1M-hit chunks from HBM, open
+    clusters stitched on the device.  The first push is a warm-up (the paper
+    times from its second buffer on); every later push and the flush are
+    timed one by one on the host (a push returns once its chunk is processed
+    on the device).  Closed features are drained to the host between pushes,
+    outside the timed calls."""
+    import numpy as np
+    import hitgen
+    p = hitgen.TPX4_PARAMS
+    workers = min(16, host_cpu()[1] or 1)
+    d_hits = torch.empty(16 * n_total, dtype=torch.uint8, device=dev)
+    at, run_max, tdis = 0, 0, 0
+    t_gen = time.perf_counter()
+    for piece in hitgen.timepix4_stream(n_total, workers=workers):
+        m = piece.size
+        d_hits[16 * at:16 * (at + m)].copy_(torch.from_numpy(piece.view(np.uint8).reshape(-1)))
+        t = piece["toa"].astype(np.int64)
+        before = np.maximum(np.concatenate([[run_max], np.maximum.accumulate(t)[:-1]]), run_max)
+        tdis = max(tdis, int((before - t).max()))
+        run_max = max(run_max, int(t.max()))
+        at += m
+    t_gen = time.perf_counter() - t_gen
+    assert at == n_total
+    print("stream workload generated (%.1f s)" % t_gen, file=sys.stderr, flush=True)
+    labels = torch.full((n_total,), -1, dtype=torch.int32, device=dev)
+    st = hc.HcStream(p["dt"], tdis + 1, p["width"], p["height"], p["disorder"])
+    st.reserve(chunk)
+    push_ms, open_hw, n_closed = [], 0, 0
+    done = []
+    n_chunks = (n_total + chunk - 1) // chunk
+    for c in range(n_chunks):
+        a, b = c * chunk, min(n_total, (c + 1) * chunk)
+        t0 = time.perf_counter()
+        st.hc_stream_push(d_hits[16 * a:16 * b], b - a, labels[a:b], c)
+        t1 = time.perf_counter()
+        if c > 0:
+            push_ms.append((t1 - t0) * 1e3)
+        open_hw = max(open_hw, st.open_hits())
+        tags, feats = st.poll()
+        done += tags
+        n_closed += feats.size
+    t0 = time.perf_counter()
+    st.flush()
+    torch.cuda.synchronize(dev)
+    flush_ms = (time.perf_counter() - t0) * 1e3
+    tags, feats = st.poll()
+    done += tags
+    n_closed += feats.size
+    st.close()
+    assert sorted(done) == list(range(n_chunks)), "not every chunk completed"
+    assert int((labels < 0).sum().item()) == 0, "labels left unwritten"
+    timed_hits = n_total - min(chunk, n_total)
+    total_ms = sum(push_ms) + flush_ms
+    a = np.array(push_ms)
+    return {"workload": "Timepix4-shaped 448x512 sensor, %d hits at 300 Mhit/s (195.3125 ps ticks), blobs of "
+                        "min(60, Geom(mean 9)) hits, local shuffle <= 16384, dt = 200 ns = 1024 ticks, pushed as "
+                        "%d-hit chunks through one hc_stream (exact stitching on the device)" % (n_total, chunk),
+            "n_hits": n_total, "chunks": n_chunks, "n_clusters": n_closed, "max_disorder_ticks": tdis + 1,
+            "mhits": round(timed_hits / (total_ms / 1e3) / 1e6, 1),
+            "push_ms": {"p50": round(float(np.quantile(a, 0.5)), 4), "p99": round(float(np.quantile(a, 0.99)), 4),
+                        "max": round(float(a.max()), 4)},
+            "flush_ms": round(flush_ms, 4), "open_hits_high_water": open_hw,
+            "generation_s": round(t_gen, 1),
+            "note": "device-resident: hits in HBM before the first push, labels written to HBM; rate = hits of "
+                    "pushes 2..%d over the summed push and flush times" % n_chunks}
+
+
 def _served_pools(n_streams, pool, seed):
     """One pool of random-walk blobs at 37.5 Mhit/s per stream; stream s sees it
     under the s-th symmetry of the square sensor (so the streams differ)."""
@@ -291,14 +400,20 @@ def _chunk_plan(rng, n, lo=4000, hi=1_000_000):
     return sizes
 
 
-def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhits=300.0):
+def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhits=300.0, check_pass=None,
+                 rate_only=False):
     """8 detector streams (256x256, 37.5 Mhit/s each), chunks of log-uniform
     size in [4k, 1M] hits arriving as independent Poisson processes at an
     aggregate 300 Mhit/s, HBM budget 16 GiB, dt = 200 ns.  Each stream replays
     its pool with a ToA offset per pass (two pinned copies, re-offset in place
     once a pass has completed).  Also: the saturated rate (every chunk of one
     pass submitted at once) against the same chunks pushed one by one through
-    one stream at a time."""
+    one stream at a time.
+
+    check_pass(stream, pass_index, n_hits, labels) -- optional, for tests: is
+    called with the final labels (a host int32 array) of the first n_hits hits
+    of every pass of the rate-limited run once they are all final.
+    rate_only -- skip the saturated and one-stream-at-a-time measurements."""
     import heapq
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
@@ -320,50 +435,20 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
     copies = [[pinned_hits(p) for _ in range(2)] for p in pools]
     labels = [[torch.empty(pool, dtype=torch.int32, pin_memory=True) for _ in range(2)] for _ in pools]
 
-    # -- saturated: one pass of every stream submitted at once
-    srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
-    plans = [_chunk_plan(rng, pool) for _ in range(n_streams)]
-    t0 = hc.hc_server_now_ns()
-    for s in range(n_streams):
-        at = 0
-        for c, m in enumerate(plans[s]):
-            srv.submit(s, copies[s][0][0][16 * at:16 * (at + m)], labels[s][0][at:at + m], c, t0)
-            at += m
-    for s in range(n_streams):
-        srv.flush(s)
-    srv.wait_idle(600000)
-    t1 = hc.hc_server_now_ns()
-    comp = srv.poll(1 << 16)
-    sat = srv.stats()
-    srv.close()
-    assert (comp["status"] == 0).all()
-    sat_mhits = n_streams * pool / ((t1 - t0) / 1e9) / 1e6
-
-    # -- the same chunks through one hc_stream at a time, no overlap
-    t0 = time.perf_counter()
-    for s in range(n_streams):
-        st = hc.HcStream(dt, tdis, 256, 256, 512)
-        st.reserve(1_000_000)
-        d_hits = torch.empty(16 * 1_000_000, dtype=torch.uint8, device=dev)
-        d_lab = [torch.empty(1_000_000, dtype=torch.int32, device=dev) for _ in range(len(plans[s]))]
-        at = 0
-        for c, m in enumerate(plans[s]):
-            d_hits[:16 * m].copy_(copies[s][0][0][16 * at:16 * (at + m)], non_blocking=True)
-            st.hc_stream_push(d_hits, m, d_lab[c], c)
-            st.poll()
-            at += m
-        st.flush()
-        st.poll()
-        torch.cuda.synchronize(dev)
-        st.close()
-    seq_mhits = n_streams * pool / (time.perf_counter() - t0) / 1e6
+    plans = [_chunk_plan(rng, pool) for _ in range(n_streams)]  # drawn either way: same later chunks
+    sat = None
+    if not rate_only:
+        sat_mhits, seq_mhits, sat = _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels,
+                                                      plans)
 
     # -- rate-limited: Poisson arrivals at the aggregate rate for `seconds`
+
     srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
     ex = ThreadPoolExecutor(max_workers=4)
     ready = [[None, None] for _ in range(n_streams)]   # future of the in-place re-offset
     passes = [[0, 1] for _ in range(n_streams)]        # pass held by each copy
     outstanding = [[0, 0] for _ in range(n_streams)]
+    submitted = [[0, 0] for _ in range(n_streams)]      # hits of the held pass submitted so far
     state = [{"pass": 0, "plan": _chunk_plan(rng, pool), "c": 0, "at": 0} for _ in range(n_streams)]
     # the second copy starts one period later
     for s in range(n_streams):
@@ -394,6 +479,9 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
             while outstanding[s][cp] > 0:
                 collect()
                 time.sleep(0.0002)
+            if check_pass is not None and submitted[s][cp]:
+                check_pass(s, passes[s][cp], submitted[s][cp], labels[s][cp].numpy())
+            submitted[s][cp] = 0
             if ready[s][cp] is None:
                 v = copies[s][cp][1]
                 ready[s][cp] = ex.submit(lambda v=v: v["toa"].__iadd__(np.uint64(2 * period)))
@@ -405,6 +493,7 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
         tag = n_sub
         key_of[(s, tag)] = (s, cp)
         outstanding[s][cp] += 1
+        submitted[s][cp] += m
         srv.submit(s, copies[s][cp][0][16 * at:16 * (at + m)], labels[s][cp][at:at + m], tag, t_arr)
         n_sub += 1
         stt["c"] += 1
@@ -418,6 +507,11 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
         srv.flush(s)
     srv.wait_idle(600000)
     collect()
+    if check_pass is not None:
+        for s in range(n_streams):
+            for cp in range(2):
+                if submitted[s][cp]:
+                    check_pass(s, passes[s][cp], submitted[s][cp], labels[s][cp].numpy())
     stats = srv.stats()
     srv.close()
     ex.shutdown()
@@ -428,20 +522,63 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
     proc = (ok["t_processed_ns"] - ok["t_arrive_ns"]) / 1e6
     fin = (ok["t_final_ns"] - ok["t_arrive_ns"]) / 1e6
     q = lambda a, f: round(float(np.quantile(a, f)), 3) if a.size else None
-    return {"workload": "%d streams of 256x256 at %.1f Mhit/s each, Poisson chunk arrivals (aggregate %.0f Mhit/s), "
-                        "chunks log-uniform in [4k, 1M] hits, dt = 200 ns, HBM budget 16 GiB, pools of %d hits "
-                        "replayed with a ToA offset per pass" % (n_streams, rate_mhits / n_streams, rate_mhits, pool),
-            "seconds": seconds, "chunks": int(comps.size), "rejected": int((comps["status"] != 0).sum()),
-            "offered_mhits": rate_mhits, "achieved_mhits": round(hits_done / t_span / 1e6, 1),
-            "processing_latency_ms": {"p50": q(proc, 0.5), "p99": q(proc, 0.99)},
-            "final_latency_ms": {"p50": q(fin, 0.5), "p99": q(fin, 0.99)},
-            "hbm_peak_bytes": int(stats["hbm_peak"]), "peak_slots_in_use": int(stats["peak_slots_in_use"]),
-            "saturated_mhits": round(sat_mhits, 1), "one_stream_at_a_time_mhits": round(seq_mhits, 1),
-            "saturated_speedup": round(sat_mhits / seq_mhits, 2),
-            "saturated_hbm_peak_bytes": int(sat["hbm_peak"]),
-            "saturated_worker_ms": {k: round(sat[k] / 1e6, 2) for k in ("ns_admit_wait", "ns_push", "ns_drain",
-                                                                       "ns_final")},
-            "note": "end-to-end from pinned host memory (H2D hits, D2H labels and closed features)"}
+    out = {"workload": "%d streams of 256x256 at %.1f Mhit/s each, Poisson chunk arrivals (aggregate %.0f Mhit/s), "
+                       "chunks log-uniform in [4k, 1M] hits, dt = 200 ns, HBM budget 16 GiB, pools of %d hits "
+                       "replayed with a ToA offset per pass" % (n_streams, rate_mhits / n_streams, rate_mhits, pool),
+           "seconds": seconds, "chunks": int(comps.size), "rejected": int((comps["status"] != 0).sum()),
+           "hits_served": hits_done,
+           "offered_mhits": rate_mhits, "achieved_mhits": round(hits_done / t_span / 1e6, 1),
+           "processing_latency_ms": {"p50": q(proc, 0.5), "p99": q(proc, 0.99)},
+           "final_latency_ms": {"p50": q(fin, 0.5), "p99": q(fin, 0.99)},
+           "hbm_peak_bytes": int(stats["hbm_peak"]), "peak_slots_in_use": int(stats["peak_slots_in_use"]),
+           "note": "end-to-end from pinned host memory (H2D hits, D2H labels and closed features)"}
+    if sat is not None:
+        out.update({"saturated_mhits": round(sat_mhits, 1), "one_stream_at_a_time_mhits": round(seq_mhits, 1),
+                    "saturated_speedup": round(sat_mhits / seq_mhits, 2),
+                    "saturated_hbm_peak_bytes": int(sat["hbm_peak"]),
+                    "saturated_worker_ms": {k: round(sat[k] / 1e6, 2) for k in ("ns_admit_wait", "ns_push",
+                                                                               "ns_drain", "ns_final")}})
+    return out
+
+
+def _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels, plans):
+    """One pass of every stream submitted to the server at once (saturated
+    rate), then the same chunks pushed through one hc_stream at a time."""
+    srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
+    t0 = hc.hc_server_now_ns()
+    for s in range(n_streams):
+        at = 0
+        for c, m in enumerate(plans[s]):
+            srv.submit(s, copies[s][0][0][16 * at:16 * (at + m)], labels[s][0][at:at + m], c, t0)
+            at += m
+    for s in range(n_streams):
+        srv.flush(s)
+    srv.wait_idle(600000)
+    t1 = hc.hc_server_now_ns()
+    comp = srv.poll(1 << 16)
+    sat = srv.stats()
+    srv.close()
+    assert (comp["status"] == 0).all()
+    sat_mhits = n_streams * pool / ((t1 - t0) / 1e9) / 1e6
+
+    t0 = time.perf_counter()
+    for s in range(n_streams):
+        st = hc.HcStream(dt, tdis, 256, 256, 512)
+        st.reserve(1_000_000)
+        d_hits = torch.empty(16 * 1_000_000, dtype=torch.uint8, device=dev)
+        d_lab = [torch.empty(1_000_000, dtype=torch.int32, device=dev) for _ in range(len(plans[s]))]
+        at = 0
+        for c, m in enumerate(plans[s]):
+            d_hits[:16 * m].copy_(copies[s][0][0][16 * at:16 * (at + m)], non_blocking=True)
+            st.hc_stream_push(d_hits, m, d_lab[c], c)
+            st.poll()
+            at += m
+        st.flush()
+        st.poll()
+        torch.cuda.synchronize(dev)
+        st.close()
+    seq_mhits = n_streams * pool / (time.perf_counter() - t0) / 1e6
+    return sat_mhits, seq_mhits, sat
 
 
 def main():
@@ -453,10 +590,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-form measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form measurement")
-    ap.add_argument("--served-seconds", type=float, default=1.0)
+    ap.add_argument("--served-seconds", type=float, default=10.0)
+    ap.add_argument("--no-stream", action="store_true", help="skip the Timepix4 stream measurement")
+    ap.add_argument("--stream-hits", type=int, default=200_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["plain", "batch", "served"],
+    ap.add_argument("--only", choices=["plain", "batch", "served", "stream"],
                     help="run one form only (profiling runs); the plain line is still printed")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_mixed10m.json from two rocprofv3 --pmc runs (CSV output) "
@@ -467,10 +606,11 @@ def main():
         traffic_from(args.traffic_from[0], args.traffic_from[1], args.traffic_command)
         return
     if args.only == "plain":
-        args.no_batch = args.no_served = True
-    elif args.only in ("batch", "served"):
+        args.no_batch = args.no_served = args.no_stream = True
+    elif args.only in ("batch", "served", "stream"):
         args.steps, args.warmup = 1, 0
         args.no_batch, args.no_served = args.only != "batch", args.only != "served"
+        args.no_stream = args.only != "stream"
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
@@ -537,11 +677,14 @@ def main():
 
     launches, total_ms = times[dom]
     avg_ms = total_ms / launches
-    per_hit, per_cluster = ALG_BYTES.get(dom, (0, 0))
-    alg = per_hit * n + per_cluster * n_clusters
-    achieved = alg / (avg_ms / 1e3) / 1e9
-    traffic = measured_traffic(dom)
+    # the path's algorithmic bytes (read every 16-byte hit once, write its
+    # 4-byte label, write one 64-byte feature row per cluster) over the
+    # dominant kernel's duration; the kernel's own contract bytes beside it
     path_bytes = 20 * n + 64 * n_clusters
+    achieved = path_bytes / (avg_ms / 1e3) / 1e9
+    per_hit, per_cluster = ALG_BYTES.get(dom, (0, 0))
+    contract = per_hit * n + per_cluster * n_clusters
+    traffic = measured_traffic(dom)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -561,12 +704,14 @@ def main():
                    "n_hits": n, "n_clusters": n_clusters, "form": "plain"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel_avg_ms": round(avg_ms, 4)},
+                     "kernel_avg_ms": round(avg_ms, 4), "alg_bytes_per_launch": path_bytes,
+                     "kernel_contract_frac": round(contract / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "path_roofline": {"achieved": round(path_bytes / (ms_per_step / 1e3) / 1e9, 1), "unit": "GB/s",
                           "frac": round(path_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                           "bytes_per_step": path_bytes},
         "kernels_ms_per_step": {name: round(v[1] / n_break, 4) for name, v in sorted(breakdown.items())},
         "sources": kernel_sources_digest(),
+        "paper": PAPER_FIGURE,
     }
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -586,8 +731,12 @@ def main():
         torch.cuda.empty_cache()
         out["served"] = bench_served(hc, torch, dev, args.served_seconds)
         print("served done", file=sys.stderr, flush=True)
+    if not args.no_stream:
+        torch.cuda.empty_cache()
+        out["stream"] = bench_stream(hc, torch, dev, n_total=args.stream_hits)
+        print("stream done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(hits, p, 30.0)
+        out["cpu_baseline"] = cpu_baseline(hits, p)
     print(json.dumps(out), flush=True)
 
 

@@ -281,3 +281,118 @@ def uniform_hits(n, seed, width=8, height=8, toa_hi=64, disorder=None):
         key = np.arange(n) + rng.integers(0, disorder + 1, n)
         hits = hits[np.argsort(key, kind="stable")]
     return hits
+
+
+# ---------------------------------------------------------------------------
+# the Timepix4-shaped stream, generated window by window
+
+
+TPX4_PARAMS = dict(width=448, height=512, dt=ns_to_ticks(200, TPX4_TICK_NS), disorder=16384)
+
+
+def _tpx4_window(seed, w, hits_per_window, span_ticks):
+    """Raw (unsorted) hits of window w: blobs of min(60, Geom(1/9)) hits drawn
+    until the window holds at least hits_per_window hits, seeds uniform over
+    [w * span, (w + 1) * span), per-hit ToA seed + U{0..100 ns}, ToT as
+    everywhere."""
+    rng = np.random.default_rng([seed, w])
+    nb = int(hits_per_window / 9.0 * 1.1) + 64
+    while True:
+        sizes = np.minimum(60, rng.geometric(1.0 / 9.0, nb))
+        c = np.cumsum(sizes)
+        if c[-1] >= hits_per_window:
+            sizes = sizes[: int(np.searchsorted(c, hits_per_window)) + 1]
+            break
+        nb *= 2
+    t0 = (np.uint64(w * span_ticks) +
+          rng.integers(0, span_ticks, sizes.size).astype(np.uint64))
+    x, y, toa, _ = _blobs(rng, sizes, 448, 512, t0, ns_to_ticks(100, TPX4_TICK_NS))
+    out = np.empty(x.size, dtype=HIT_DTYPE)
+    out["x"], out["y"], out["toa"] = x, y, toa
+    out["tot"] = _tot(rng, x.size)
+    out["reserved"] = 0
+    return out
+
+
+def timepix4_stream(n=200_000_000, seed=BASE_SEED + 4, window=1 << 20, workers=8):
+    """The Timepix4-shaped stream (448x512 sensor, 300 Mhit/s, 195.3125 ps
+    ticks, blobs of min(60, Geom(mean 9)) hits, displacement <= 16384) as a
+    generator of consecutive pieces, without ever holding the whole stream.
+
+    Window w draws clusters whose seed ToAs lie in [w * S, (w + 1) * S), S
+    being the time 300 Mhit/s needs for ``window`` hits; the stream stops after
+    n hits (the last window truncated in generation order).  The ToA sort is
+    done window by window: hits below the next window's start are final,
+    later ones wait for the next window, which makes the result the stable
+    ToA order of the whole stream.  The local shuffle (stable sort on
+    i + U{0..D}) likewise: once positions below P are all known, every key
+    below P is final.  Windows are generated in parallel threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    D = TPX4_PARAMS["disorder"]
+    span = int(round(window / 300e6 * 1e9 / TPX4_TICK_NS))
+    left = n
+    carry = np.empty(0, dtype=HIT_DTYPE)
+    pend_key = np.empty(0, dtype=np.int64)
+    pend_hits = np.empty(0, dtype=HIT_DTYPE)
+    pos = 0  # sorted positions handed out so far
+    ex = ThreadPoolExecutor(max_workers=max(1, workers))
+    futs = {}
+    w = 0
+    try:
+        while True:
+            for k in range(w, w + 2 * max(1, workers)):
+                if k not in futs:
+                    futs[k] = ex.submit(_tpx4_window, seed, k, window, span)
+            if left > 0:
+                raw = futs.pop(w).result()
+                if raw.size > left:
+                    raw = raw[:left]
+                left -= raw.size
+            else:
+                futs.pop(w).cancel()
+                raw = np.empty(0, dtype=HIT_DTYPE)
+            pool = np.concatenate([carry, raw])
+            pool = pool[np.argsort(pool["toa"], kind="stable")]
+            last = left <= 0
+            if last:
+                done, carry = pool, pool[:0]
+            else:
+                cut = int(np.searchsorted(pool["toa"], np.uint64((w + 1) * span), side="left"))
+                done, carry = pool[:cut], pool[cut:]
+            # local shuffle of the newly final sorted positions
+            rng = np.random.default_rng([seed, w, 7])
+            keys = np.arange(pos, pos + done.size, dtype=np.int64) + rng.integers(0, D + 1, done.size)
+            pos += done.size
+            pend_key = np.concatenate([pend_key, keys])
+            pend_hits = np.concatenate([pend_hits, done])
+            order = np.argsort(pend_key, kind="stable")  # pending items are in position order
+            if last:
+                yield pend_hits[order]
+                return
+            nfin = int(np.count_nonzero(pend_key < pos))  # keys below pos lead `order`
+            out = pend_hits[order[:nfin]]
+            keep = np.ones(pend_key.size, dtype=bool)  # the rest stays in position order
+            keep[order[:nfin]] = False
+            pend_key, pend_hits = pend_key[keep], pend_hits[keep]
+            if out.size:
+                yield out
+            w += 1
+    finally:
+        for f in futs.values():
+            f.cancel()
+        ex.shutdown(wait=False, cancel_futures=True)
+
+
+def pieces(gen, size):
+    """Re-cut a generator of hit arrays into consecutive arrays of ``size``
+    hits (the last one shorter)."""
+    buf, have = [], 0
+    for a in gen:
+        buf.append(a)
+        have += a.size
+        while have >= size:
+            cat = np.concatenate(buf)
+            yield cat[:size]
+            buf, have = [cat[size:]], have - size
+    if have:
+        yield np.concatenate(buf)

@@ -32,7 +32,10 @@
  *     in the data (a hit outside the sensor) are reported asynchronously:
  *     *n_clusters (device memory) then holds HC_ERR_RANGE.
  *   - Calls on distinct workspaces/streams are independent; two calls that
- *     share a workspace must be ordered by the caller (same stream).
+ *     share a workspace must be ordered by the caller (same stream).  With a
+ *     NULL workspace the library keeps one cached buffer per (device,
+ *     stream): calls on different streams never share it, and calls on one
+ *     stream are ordered by that stream, from any number of host threads.
  */
 #ifndef HC_H
 #define HC_H
@@ -78,7 +81,8 @@ typedef struct {
     uint32_t flags;          /* 0, or one HC_FLAG_LINK_* value */
     void* workspace;         /* device scratch of >= hc_workspace_size bytes,
                                 or NULL: the library then keeps a cached
-                                per-device buffer (grown with hipMalloc) */
+                                buffer per (device, stream), grown with
+                                hipMalloc and kept until the process ends */
     size_t workspace_bytes;
     void* stream;            /* hipStream_t to run on; NULL = null stream */
 } hc_opts;
@@ -125,7 +129,8 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels,
  * next chunk.  With M the largest ToA pushed so far, every later hit has
  * toa > M - t; a cluster is closed -- its labels final, its features emitted
  * (Algorithm "processHit", closeAndDispatchOldClusters) -- once
- * toa_max + dt <= M - t.
+ * toa_max + dt <= M - t.  While M < t there is no such bound yet: nothing
+ * is rejected for its ToA and nothing closes before the flush.
  *
  * Labels are stream-global: the smallest global index (0-based position in
  * the concatenation of all pushed chunks) of the hit's cluster.  They are
@@ -142,9 +147,10 @@ int hc_stream_create(const hc_opts* opts, uint64_t dt, uint64_t max_disorder_tic
 /* Append n hits (device array).  labels: device int32[n] that the library
  * fills as the chunk's clusters close; it must stay valid until `tag` is
  * returned by hc_stream_poll.  Returns HC_ERR_DISORDER (chunk rejected,
- * stream unchanged) if a hit has toa <= M - t, HC_ERR_RANGE (rejected) if a
- * hit is off the sensor, HC_ERR_OVERFLOW past 2^31 - 1 hits.  Blocks until
- * the chunk has been processed on the device. */
+ * stream unchanged) if a hit has toa <= M - t (when M >= t) or, after a
+ * flush, toa <= F (see hc_stream_flush); HC_ERR_RANGE (rejected) if a hit is
+ * off the sensor, HC_ERR_OVERFLOW past 2^31 - 1 hits.  Blocks until the
+ * chunk has been processed on the device. */
 int hc_stream_push(hc_stream* s, const hc_hit* hits, int32_t n, int32_t* labels, uint64_t tag);
 
 /* Drain completion events into HOST buffers: up to cap tags of chunks whose
@@ -159,8 +165,15 @@ int hc_stream_poll(hc_stream* s, uint64_t* done_tags, int32_t cap, int32_t* n_do
  * unless a chunk is larger or unusually many clusters stay open. */
 int hc_stream_reserve(hc_stream* s, int32_t max_chunk);
 
+/* Hits currently held open on the device (their clusters may still grow);
+ * -1 for a NULL stream. */
+int64_t hc_stream_open_hits(const hc_stream* s);
+
 /* Close every open cluster (end of stream); afterwards all pushed chunks are
- * complete. */
+ * complete.  The stream may continue as a new segment that no cluster spans:
+ * with M the largest ToA pushed before the flush, a later push is rejected
+ * (HC_ERR_DISORDER) unless every hit has toa > F = M + dt (saturating), so no
+ * later hit can be adjacent in time to a hit whose label is already final. */
 int hc_stream_flush(hc_stream* s);
 
 void hc_stream_destroy(hc_stream* s);

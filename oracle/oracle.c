@@ -62,15 +62,20 @@ typedef struct {
 
 enum { OC_OK = 0, OC_ERR_ARG = -1, OC_ERR_RANGE = -2, OC_ERR_NOMEM = -9 };
 
-static const oc_hit* g_sort_hits; /* qsort has no context argument */
+/* sort key of step 2: (toa, input index); the pair carries its own ToA, so
+ * the comparison needs no outside state and concurrent calls are safe */
+typedef struct {
+    uint64_t toa;
+    int64_t idx;
+} oc_key;
 
 static int cmp_time_then_index(const void* pa, const void* pb)
 {
-    int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
-    uint64_t ta = g_sort_hits[a].toa, tb = g_sort_hits[b].toa;
-    if (ta < tb) return -1;
-    if (ta > tb) return 1;
-    return (a < b) ? -1 : (a > b) ? 1 : 0;
+    const oc_key* a = (const oc_key*)pa;
+    const oc_key* b = (const oc_key*)pb;
+    if (a->toa < b->toa) return -1;
+    if (a->toa > b->toa) return 1;
+    return (a->idx < b->idx) ? -1 : (a->idx > b->idx) ? 1 : 0;
 }
 
 static uint64_t sat_sub(uint64_t a, uint64_t b) { return a > b ? a - b : 0; }
@@ -100,9 +105,18 @@ int oracle_cluster(const oc_hit* hits, int64_t n, uint32_t width, uint32_t heigh
     }
 
     /* step 2: time order, ties by input index */
-    for (int64_t i = 0; i < n; i++) order[i] = i;
-    g_sort_hits = hits;
-    qsort(order, (size_t)n, sizeof(int64_t), cmp_time_then_index);
+    oc_key* keys = malloc((size_t)n * sizeof(oc_key));
+    if (!keys) {
+        free(order); free(start); free(fill); free(list); free(queue);
+        return OC_ERR_NOMEM;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        keys[i].toa = hits[i].toa;
+        keys[i].idx = i;
+    }
+    qsort(keys, (size_t)n, sizeof(oc_key), cmp_time_then_index);
+    for (int64_t k = 0; k < n; k++) order[k] = keys[k].idx;
+    free(keys);
 
     /* step 3: per-pixel lists in time order */
     for (int64_t i = 0; i < n; i++)

@@ -200,6 +200,8 @@ def _bind_stream(lib):
     lib.hc_stream_reserve.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.hc_stream_flush.restype = ctypes.c_int
     lib.hc_stream_flush.argtypes = [ctypes.c_void_p]
+    lib.hc_stream_open_hits.restype = ctypes.c_int64
+    lib.hc_stream_open_hits.argtypes = [ctypes.c_void_p]
     lib.hc_stream_destroy.restype = None
     lib.hc_stream_destroy.argtypes = [ctypes.c_void_p]
     lib._stream_bound = True
@@ -246,6 +248,10 @@ class HcStream:
             if nd.value < cap and nc.value < closed_cap:
                 break
         return done, np.concatenate(feats)
+
+    def open_hits(self):
+        """Hits held open on the device (hc_stream_open_hits)."""
+        return int(self._lib.hc_stream_open_hits(self._h))
 
     def reserve(self, max_chunk):
         _check(self._lib.hc_stream_reserve(self._h, int(max_chunk)))

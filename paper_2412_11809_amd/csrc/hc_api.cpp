@@ -2,8 +2,11 @@
 // the launch sequence of hc_cluster, error strings and kernel timing.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hc.h"
@@ -157,35 +160,48 @@ int upload_segments(const Work& w, const SegSpec* segs, int n_seg, hipStream_t s
     return e == hipSuccess ? HC_OK : device_fail(e, "segment table upload");
 }
 
-// One cached workspace per device for callers that pass none.
+// One cached workspace per (device, stream) for callers that pass none.
+// Work on one stream runs in order, so calls on that stream may share its
+// buffer; calls on different streams never share one.  The entry's lock is
+// held by the caller until its launches are enqueued, so a call that grows
+// the buffer (after synchronising the stream: every earlier user enqueued its
+// work there before releasing the lock) never frees memory that another
+// thread is about to hand to a kernel.
 struct CachedWs {
+    std::mutex mu;
     void* ptr = nullptr;
     size_t bytes = 0;
 };
 static std::mutex g_ws_mu;
-static std::vector<CachedWs> g_ws;
+static std::map<std::pair<int, hipStream_t>, std::unique_ptr<CachedWs>> g_ws;
 
-int cached_workspace(size_t need, void** out)
+int cached_workspace(size_t need, hipStream_t s, void** out, std::unique_lock<std::mutex>* hold)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return device_fail(e, "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-    CachedWs& c = g_ws[dev];
-    if (c.bytes < need) {
-        if (c.ptr) {
-            e = hipDeviceSynchronize();
-            if (e != hipSuccess) return device_fail(e, "hipDeviceSynchronize");
-            (void)hipFree(c.ptr);
-            c.ptr = nullptr;
-            c.bytes = 0;
-        }
-        e = hipMalloc(&c.ptr, need);
-        if (e != hipSuccess) return device_fail(e, "hipMalloc(workspace)");
-        c.bytes = need;
+    CachedWs* c;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        std::unique_ptr<CachedWs>& slot = g_ws[std::make_pair(dev, s)];
+        if (!slot) slot.reset(new CachedWs());
+        c = slot.get();
     }
-    *out = c.ptr;
+    std::unique_lock<std::mutex> lk(c->mu);
+    if (c->bytes < need) {
+        if (c->ptr) {
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return device_fail(e, "hipStreamSynchronize");
+            (void)hipFree(c->ptr);
+            c->ptr = nullptr;
+            c->bytes = 0;
+        }
+        e = hipMalloc(&c->ptr, need);
+        if (e != hipSuccess) return device_fail(e, "hipMalloc(workspace)");
+        c->bytes = need;
+    }
+    *out = c->ptr;
+    *hold = std::move(lk);
     return HC_OK;
 }
 
@@ -313,12 +329,13 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_f
     const uint32_t D = opts ? opts->disorder_hint : 0;
     const size_t need = plan_workspace(n, W, H, D, &w, nullptr);
     void* ws = opts ? opts->workspace : nullptr;
+    std::unique_lock<std::mutex> hold;  // a cached workspace stays ours until the launches are enqueued
     if (ws) {
         if (opts->workspace_bytes < need)
             return fail(HC_ERR_WORKSPACE, "workspace of " + std::to_string(opts->workspace_bytes) +
                                               " bytes, need " + std::to_string(need));
     } else {
-        int rc = cached_workspace(need, &ws);
+        int rc = cached_workspace(need, s, &ws, &hold);
         if (rc != HC_OK) return rc;
     }
     plan_workspace(n, W, H, D, &w, (char*)ws);

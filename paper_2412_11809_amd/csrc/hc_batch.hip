@@ -174,9 +174,10 @@ int hc_cluster_batch(const hc_hit* hits, const int64_t* offsets, int32_t n_chunk
     size_t need = 0;
     if ((rc = plan_batch(offsets, n_chunks, dts, plan, opts, segs, &w, nullptr, &need)) != HC_OK) return rc;
     void* ws = opts ? opts->workspace : nullptr;
+    std::unique_lock<std::mutex> hold;  // a cached workspace stays ours until the launches are enqueued
     if (ws) {
         if (opts->workspace_bytes < need) return set_error(HC_ERR_WORKSPACE, "batch workspace too small");
-    } else if ((rc = cached_workspace(need, &ws)) != HC_OK) {
+    } else if ((rc = cached_workspace(need, s, &ws, &hold)) != HC_OK) {
         return rc;
     }
     if ((rc = plan_batch(offsets, n_chunks, dts, plan, opts, segs, &w, (char*)ws, &need)) != HC_OK) return rc;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 
 #include "hc.h"
@@ -202,8 +203,10 @@ __host__ __device__ inline int32_t fb_scan_segments(int32_t nb)
 {
     return (int32_t)(((int64_t)256 * nb + kFbScanSeg - 1) / kFbScanSeg);
 }
-// Cached per-device workspace for callers that pass none (grown on demand).
-int cached_workspace(size_t need, void** out);
+// Cached workspace of (current device, stream s) for callers that pass none
+// (grown on demand).  *hold keeps the buffer reserved for the caller until it
+// has enqueued its work on s.
+int cached_workspace(size_t need, hipStream_t s, void** out, std::unique_lock<std::mutex>* hold);
 // Switch per-kernel event timing on or off; returns the previous state.
 bool timing_set(bool on);
 // Device memory of a stream (hc_stream_*): held now, and after a push of n

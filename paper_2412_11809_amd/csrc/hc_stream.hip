@@ -72,7 +72,8 @@ __global__ __launch_bounds__(256) void k_stream_append(const hc_hit* __restrict_
 // into its chunk's buffer.  keep[i] = 1 for hits that stay open.
 __global__ void k_stream_close_hits(int n_all, const int32_t* __restrict__ lab, const Work w,
                                     const int32_t* __restrict__ gidx, const int32_t* __restrict__ cslot,
-                                    ChunkRec* chunks, uint64_t wmark, uint64_t dt, int flush, uint8_t* keep)
+                                    ChunkRec* chunks, uint64_t wmark, int has_wmark, uint64_t dt, int flush,
+                                    uint8_t* keep)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
@@ -80,7 +81,7 @@ __global__ void k_stream_close_hits(int n_all, const int32_t* __restrict__ lab, 
     int32_t slot = -1;
     if (i < n_all) {
         const int32_t r = lab[i];
-        closed = flush || sat_add_u64(w.slots[root_rank(w, 0, 0, r)].toa_max, dt) <= wmark;
+        closed = flush || (has_wmark && sat_add_u64(w.slots[root_rank(w, 0, 0, r)].toa_max, dt) <= wmark);
         if (closed) {
             slot = cslot[i];
             ChunkRec* ch = chunks + slot;
@@ -102,12 +103,12 @@ __global__ void k_stream_close_hits(int n_all, const int32_t* __restrict__ lab, 
 
 // flag[k] = 1 for clusters (feature rows, ascending label) that are closed
 __global__ void k_stream_close_feats(const hc_features* __restrict__ f, int cap, const StreamDev* sd, uint64_t wmark,
-                                     uint64_t dt, int flush, uint8_t* flag)
+                                     int has_wmark, uint64_t dt, int flush, uint8_t* flag)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= cap) return;
     const int K = sd->n_clusters;
-    flag[k] = (k < K && (flush || sat_add_u64(f[k].toa_max, dt) <= wmark)) ? 1 : 0;
+    flag[k] = (k < K && (flush || (has_wmark && sat_add_u64(f[k].toa_max, dt) <= wmark))) ? 1 : 0;
 }
 
 // Stable compaction by flag, in three steps: per-block counts, one
@@ -239,6 +240,10 @@ struct hc_stream {
     int64_t n_open = 0, next_g = 0;
     uint64_t M = 0;
     bool has_M = false;
+    // after a flush every later hit must lie more than dt after every flushed
+    // hit (toa > floor = M + dt), so no cluster spans the flush
+    uint64_t floor = 0;
+    bool has_floor = false;
     bool failed = false;
 };
 
@@ -369,8 +374,9 @@ static int grow_chunks(hc_stream* st)
 }
 
 // Cluster the buffer (open hits + new chunk), close what can be closed,
-// compact the rest.  wmark: every later hit has toa > wmark.
-static int process(hc_stream* st, int64_t n_all, uint64_t wmark, int flush)
+// compact the rest.  has_wmark: every later hit has toa > wmark (without a
+// watermark -- the largest ToA is still below t -- nothing closes).
+static int process(hc_stream* st, int64_t n_all, uint64_t wmark, bool has_wmark, int flush)
 {
     hipError_t e;
     const int n = (int)n_all;
@@ -385,14 +391,15 @@ static int process(hc_stream* st, int64_t n_all, uint64_t wmark, int flush)
     const int nb = (n + kCmpBlock - 1) / kCmpBlock;
     const int nxt = 1 - st->cur;
     hipLaunchKernelGGL(k_stream_close_hits, dim3(blocks), dim3(256), 0, st->s, n, st->lab, w,
-                       st->gidx[st->cur], st->cslot[st->cur], st->chunks_dev, wmark, st->dt, flush, st->flags);
+                       st->gidx[st->cur], st->cslot[st->cur], st->chunks_dev, wmark, has_wmark ? 1 : 0, st->dt, flush,
+                       st->flags);
     hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, n, st->counts);
     hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, nb, &st->sd->n_keep);
     hipLaunchKernelGGL(k_scatter_open, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, n, st->counts,
                        st->buf[st->cur], st->gidx[st->cur], st->cslot[st->cur], st->buf[nxt], st->gidx[nxt],
                        st->cslot[nxt]);
-    hipLaunchKernelGGL(k_stream_close_feats, dim3(blocks), dim3(256), 0, st->s, st->feats, n, st->sd, wmark, st->dt,
-                       flush, st->flags);
+    hipLaunchKernelGGL(k_stream_close_feats, dim3(blocks), dim3(256), 0, st->s, st->feats, n, st->sd, wmark,
+                       has_wmark ? 1 : 0, st->dt, flush, st->flags);
     hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, n, st->counts);
     hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, nb, &st->sd->n_closed);
     hipLaunchKernelGGL(k_scatter_feats, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, n, st->counts,
@@ -520,7 +527,12 @@ int hc_stream_push(hc_stream* st, const hc_hit* hits, int32_t n, int32_t* labels
     // append and validate (a rejected chunk leaves the open state untouched:
     // only buffer positions beyond n_open are written)
     hipError_t e;
-    const uint64_t wmark = st->M > st->tdis ? st->M - st->tdis : 0;
+    // a hit is rejected when toa <= M - t (the t-ordered contract; no bound
+    // while M < t) or, after a flush, toa <= floor
+    const bool has_w = st->has_M && st->M >= st->tdis;
+    uint64_t wmark = has_w ? st->M - st->tdis : 0;
+    if (st->has_floor && (!has_w || st->floor > wmark)) wmark = st->floor;
+    const bool reject_below = has_w || st->has_floor;
     ::memset(st->sd_pin, 0, sizeof(StreamDev));
     if ((e = hipMemcpyAsync(st->sd, st->sd_pin, sizeof(StreamDev), hipMemcpyHostToDevice, st->s)) != hipSuccess)
         return set_device_error(e, "stream reset");
@@ -528,7 +540,7 @@ int hc_stream_push(hc_stream* st, const hc_hit* hits, int32_t n, int32_t* labels
         TimedLaunch tl("stream_append", st->s);
         hipLaunchKernelGGL(k_stream_append, dim3((n + 255) / 256), dim3(256), 0, st->s, hits, n,
                            st->buf[st->cur], st->gidx[st->cur], st->cslot[st->cur], (int)st->n_open,
-                           (int32_t)st->next_g, slot, wmark, st->has_M ? 1 : 0, st->W, st->H, st->sd);
+                           (int32_t)st->next_g, slot, wmark, reject_below ? 1 : 0, st->W, st->H, st->sd);
     }
     if ((e = hipGetLastError()) != hipSuccess) return set_device_error(e, "stream append");
     if ((e = hipMemcpyAsync(st->sd_pin, st->sd, sizeof(StreamDev), hipMemcpyDeviceToHost, st->s)) != hipSuccess ||
@@ -545,8 +557,7 @@ int hc_stream_push(hc_stream* st, const hc_hit* hits, int32_t n, int32_t* labels
                             st->s)) != hipSuccess)
         return set_device_error(e, "stream chunk table");
     const uint64_t M = st->has_M ? (cmax > st->M ? cmax : st->M) : cmax;
-    const uint64_t wnew = M > st->tdis ? M - st->tdis : 0;
-    rc = process(st, n_all, wnew, 0);
+    rc = process(st, n_all, M >= st->tdis ? M - st->tdis : 0, M >= st->tdis, 0);
     if (rc != HC_OK) return rc;
     st->next_g += n;
     st->M = M;
@@ -579,14 +590,20 @@ int hc_stream_reserve(hc_stream* st, int32_t max_chunk)
     return HC_OK;
 }
 
+int64_t hc_stream_open_hits(const hc_stream* st) { return st ? st->n_open : -1; }
+
 int hc_stream_flush(hc_stream* st)
 {
     if (!st) return set_error(HC_ERR_ARG, "stream is NULL");
     if (st->failed) return set_error(HC_ERR_DEVICE, "stream failed earlier");
+    if (st->has_M) {
+        st->floor = ~0ull - st->M < st->dt ? ~0ull : st->M + st->dt;
+        st->has_floor = true;
+    }
     if (st->n_open == 0) return HC_OK;
     int rc = ensure_capacity(st, st->n_open);
     if (rc != HC_OK) return rc;
-    return process(st, st->n_open, ~0ull, 1);
+    return process(st, st->n_open, 0, false, 1);
 }
 
 int hc_stream_poll(hc_stream* st, uint64_t* done_tags, int32_t cap, int32_t* n_done, hc_features* closed,

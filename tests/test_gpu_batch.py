@@ -186,3 +186,15 @@ def test_batch_graph_replays(hc):
             assert np.array_equal(a, b) and fa.tobytes() == fb.tobytes()
         del junk
     g.close()
+
+
+def test_batch_64_chunks_full_size(hc):
+    """The 64-chunk workload at its stated size (27.1M hits, chunks of 1k-2M
+    hits, dt per chunk in {100, 200, 500} ns), default plan, every chunk
+    element by element against the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    chunks, dts, _ = hitgen.batch_64_chunks()
+    got, k = run(hc, chunks, dts, hint=512)
+    with ThreadPoolExecutor(8) as ex:
+        want = list(ex.map(lambda cd: oracle.cluster(cd[0], 256, 256, int(cd[1])), zip(chunks, dts)))
+    compare(got, k, want, "batch full size")

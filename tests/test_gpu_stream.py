@@ -102,3 +102,75 @@ def test_stream_rejects_disorder_and_continues(hc):
     want, _ = oracle.cluster(hits, 256, 256, p["dt"])
     assert (got == want).all()
     st.close()
+
+
+def test_stream_timepix4_1m_chunks(hc):
+    """The Timepix4-shaped workload at its own chunk shape: 16 consecutive
+    1M-hit pushes of the 300 Mhit/s stream (448x512, displacement <= 16384),
+    element by element against the whole-stream oracle."""
+    n = 16_000_000
+    hits = np.concatenate(list(hitgen.timepix4_stream(n=n, seed=hitgen.BASE_SEED + 14)))
+    p = hitgen.TPX4_PARAMS
+    check(hc, hits, [1_000_000] * 16, p["width"], p["height"], p["dt"], p["disorder"])
+
+
+def _push_expect(hc, st, hits, tag):
+    import torch
+    lab = torch.full((hits.size,), -7, dtype=torch.int32, device="cuda")
+    st.push(hc.hits_to_device(hits), lab, tag)
+    return lab
+
+
+def test_stream_no_watermark_while_max_below_t(hc):
+    """While the largest ToA is still below the disorder bound t there is no
+    watermark: a later hit at ToA 0 is valid (the t-ordered condition
+    toa_i < toa_j + t holds for it) and nothing closes early."""
+    a = hitgen.uniform_hits(300, 1, width=16, height=16, toa_hi=500)
+    b = hitgen.uniform_hits(300, 2, width=16, height=16, toa_hi=500)
+    b["toa"][:5] = 0
+    hits = np.concatenate([a, b])
+    tdis, dt = 1000, 3   # M stays below t throughout
+    assert int(hits["toa"].max()) < tdis
+    st = hc.HcStream(dt, tdis, 256, 256, 512)
+    la = _push_expect(hc, st, a, 0)
+    lb = _push_expect(hc, st, b, 1)
+    done, _ = st.poll()
+    assert done == []  # no watermark yet: nothing is final before the flush
+    st.flush()
+    done, feats = st.poll()
+    assert sorted(done) == [0, 1]
+    got = np.concatenate([la.cpu().numpy(), lb.cpu().numpy()])
+    want_l, want_f = oracle.cluster(hits, 256, 256, dt)
+    assert np.array_equal(got, want_l)
+    feats = feats[np.argsort(feats["label"], kind="stable")]
+    assert feats.tobytes() == want_f.tobytes()
+    st.close()
+
+
+def test_stream_push_after_flush(hc):
+    """After a flush the stream continues as a new segment: a hit within dt
+    of the largest flushed ToA is rejected (it could join a cluster whose
+    labels are already final), a later chunk is accepted and clustered on its
+    own."""
+    a, p = hitgen.blobs_100k(n=30_000, seed=21)
+    dt = p["dt"]
+    tdis = hitgen.realised_disorder_ticks(a) + 1
+    st = hc.HcStream(dt, tdis, 256, 256, p["disorder"])
+    la = _push_expect(hc, st, a, 0)
+    st.flush()
+    M = int(a["toa"].max())
+    late = a[:50].copy()
+    late["toa"] = np.uint64(M + dt)     # exactly dt after the last flushed hit
+    with pytest.raises(hc.HcError) as e:
+        _push_expect(hc, st, late, 9)
+    assert e.value.code == hc.HC_ERR_DISORDER
+    c = a.copy()
+    c["toa"] += np.uint64(M + dt + 1 - int(a["toa"].min()))
+    lc = _push_expect(hc, st, c, 1)
+    st.flush()
+    done, _ = st.poll()
+    assert sorted(done) == [0, 1]
+    want, _ = oracle.cluster(np.concatenate([a, c]), 256, 256, dt)
+    got = np.concatenate([la.cpu().numpy(), lc.cpu().numpy()])
+    assert np.array_equal(got, want)
+    st.close()
