@@ -109,39 +109,10 @@ def check_invariants(hits, labels, dt):
 
 
 def features_from_labels(hits, labels):
-    """Per-cluster features in ascending label order, recomputed with numpy."""
-    from oracle import FEATURE_DTYPE  # record layout only
-    labels = np.asarray(labels, dtype=np.int64)
-    roots = np.unique(labels)
-    inv = np.searchsorted(roots, labels)
-    k = roots.size
-    out = np.zeros(k, dtype=FEATURE_DTYPE)
-    out["label"] = roots
-    x = hits["x"].astype(U64)
-    y = hits["y"].astype(U64)
-    tot = hits["tot"].astype(U64)
-    toa = hits["toa"].astype(U64)
-    size = np.zeros(k, np.int64)
-    np.add.at(size, inv, 1)
-    st = np.zeros(k, U64); np.add.at(st, inv, tot)
-    sxt = np.zeros(k, U64); np.add.at(sxt, inv, x * tot)
-    syt = np.zeros(k, U64); np.add.at(syt, inv, y * tot)
-    sx = np.zeros(k, U64); np.add.at(sx, inv, x)
-    sy = np.zeros(k, U64); np.add.at(sy, inv, y)
-    tmin = np.full(k, np.iinfo(U64).max, U64); np.minimum.at(tmin, inv, toa)
-    tmax = np.zeros(k, U64); np.maximum.at(tmax, inv, toa)
-    out["size"] = size
-    out["sum_tot"] = st
-    out["toa_min"] = tmin
-    out["toa_max"] = tmax
-    out["sum_x_tot"] = sxt
-    out["sum_y_tot"] = syt
-    w = st > 0
-    out["cx"] = np.where(w, sxt.astype(np.float64) / np.maximum(st, 1).astype(np.float64),
-                         sx.astype(np.float64) / size.astype(np.float64))
-    out["cy"] = np.where(w, syt.astype(np.float64) / np.maximum(st, 1).astype(np.float64),
-                         sy.astype(np.float64) / size.astype(np.float64))
-    return out
+    """Per-cluster features in ascending label order, recomputed with numpy
+    (the oracle package's numpy feature step, independent of oracle.c)."""
+    import oracle
+    return oracle.features_from_labels(hits, labels)
 
 
 def features_equal(a, b):
