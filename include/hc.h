@@ -78,7 +78,8 @@ typedef struct {
                                 partial orderliness, Section 3.1).  A tuning
                                 hint only: wrong values cost speed, never
                                 exactness. 0 = 4096. */
-    uint32_t flags;          /* 0, or one HC_FLAG_LINK_* value */
+    uint32_t flags;          /* 0, or one HC_FLAG_LINK_* value; hc_cluster also
+                                takes HC_FLAG_GLOBAL_TIME */
     void* workspace;         /* device scratch of >= hc_workspace_size bytes,
                                 or NULL: the library then keeps a cached
                                 buffer per (device, stream), grown with
@@ -94,6 +95,18 @@ typedef struct {
  * a slower path).  The flags force one of the two for every tile. */
 #define HC_FLAG_LINK_PIXEL_INDEX 1u
 #define HC_FLAG_LINK_WINDOW 2u
+
+/* hc_cluster only: cluster by the paper's second definition, Section 2
+ * (iii)(b), the dynamic global-time neighbourhood: a cluster is a maximal
+ * (under inclusion) set of hits that is spatially connected through
+ * 8-neighbouring or identical pixels at any ToA, and whose ToAs, in order,
+ * leave no gap larger than dt (every hit but the earliest has another hit of
+ * the cluster at most dt before it).  Every cluster of the default definition
+ * (iii)(a) lies inside one of these.  Labels and features keep their
+ * conventions.  The device refines a partition in rounds until it no longer
+ * changes; the call waits for the stream after every round, so it returns
+ * once the work is done (hc_workspace_size grows accordingly). */
+#define HC_FLAG_GLOBAL_TIME 4u
 
 enum {
     HC_OK = 0,
@@ -119,6 +132,51 @@ size_t hc_workspace_size(const hc_opts* opts, int64_t n);
 int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels,
                hc_features* features, int32_t* n_clusters, const hc_opts* opts);
 
+/* ---- Per-cluster products ------------------------------------------------
+ *
+ * Computed on the device from what hc_cluster wrote (labels, feature table,
+ * cluster count), for the steps the paper places around the clustering:
+ *   - the bounding box of every cluster: the smallest sensor-aligned
+ *     rectangle holding its hits (Section 3.3, second test of the merge
+ *     cascade);
+ *   - a filter that keeps the clusters whose size, ToT sum and first ToA lie
+ *     in closed ranges (Section 3.1, cluster outputting: filtering to reduce
+ *     the data volume; Section 6: filtering on the GPU);
+ *   - the hits of the kept clusters grouped cluster by cluster, one block of
+ *     memory per cluster (step 6 of the paper's high-level GPU algorithm);
+ *     blocks follow the kept rows, hits inside a block keep their input
+ *     order. */
+typedef struct {
+    uint16_t x_min, x_max, y_min, y_max; /* inclusive pixel ranges */
+} hc_box;
+
+typedef struct {
+    uint32_t min_size, max_size;       /* min_size <= size <= max_size */
+    uint64_t min_sum_tot, max_sum_tot; /* min_sum_tot <= sum_tot <= max_sum_tot */
+    uint64_t toa_from, toa_to;         /* toa_from <= toa_min <= toa_to */
+} hc_filter;
+
+/* Bytes of device workspace hc_cluster_products needs for n hits. */
+size_t hc_products_workspace_size(int64_t n);
+
+/* hits[n], labels[n], features[0..K) and *n_clusters = K: device buffers as
+ * hc_cluster wrote them (same hits).  filter: NULL keeps every cluster.
+ * Outputs (device):
+ *   boxes[K]       box of every feature row, or NULL to skip;
+ *   keep_rows[K]   the kept feature rows, ascending; *n_keep = their number
+ *                  (or HC_ERR_DEVICE if the inputs are inconsistent);
+ *   grouped[n], grouped_idx[n]  the kept clusters' hits (and their input
+ *                  indices), block by block; either may be NULL (both NULL
+ *                  skips the grouping);
+ *   row_start[K+1] start of every kept block in grouped, then the total
+ *                  (entries 0..n_keep), or NULL.
+ * workspace: device memory of >= hc_products_workspace_size(n) bytes.
+ * Asynchronous on `stream` (a hipStream_t, NULL = the null stream). */
+int hc_cluster_products(const hc_hit* hits, int32_t n, const int32_t* labels, const hc_features* features,
+                        const int32_t* n_clusters, const hc_filter* filter, hc_box* boxes,
+                        int32_t* keep_rows, int32_t* n_keep, hc_hit* grouped, int32_t* grouped_idx,
+                        int64_t* row_start, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- Stream form: one detector's hit stream, pushed chunk by chunk --------
  *
  * The stream is "t-ordered" (paper, Section 3.1): for any two hits i < j in
@@ -133,50 +191,131 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels,
  * is rejected for its ToA and nothing closes before the flush.
  *
  * Labels are stream-global: the smallest global index (0-based position in
- * the concatenation of all pushed chunks) of the hit's cluster.  They are
+ * the concatenation of all accepted chunks) of the hit's cluster.  They are
  * written into each chunk's labels buffer as its clusters close, possibly
  * during a later push or the flush; a chunk is complete when its tag is
  * reported by hc_stream_poll.  At most 2^31 - 1 hits per stream.
- * A stream is single-producer; all its work runs on opts->stream. */
+ *
+ * Pushes are asynchronous: the stream's state (open hits, M, the next global
+ * index) lives on the device, each chunk is accepted or rejected there, and
+ * hc_stream_push returns once the push is enqueued (it waits only while
+ * several pushes are already in flight, or when buffers must grow).  Results
+ * arrive through hc_stream_poll.  A stream is single-producer; all its work
+ * runs on opts->stream, so work the caller enqueues later on that stream is
+ * ordered after every push. */
 typedef struct hc_stream hc_stream;
 
 /* opts: sensor size, disorder_hint (positional, for the sort), stream; the
  * workspace fields are ignored (the stream owns its device buffers). */
 int hc_stream_create(const hc_opts* opts, uint64_t dt, uint64_t max_disorder_ticks, hc_stream** out);
 
-/* Append n hits (device array).  labels: device int32[n] that the library
- * fills as the chunk's clusters close; it must stay valid until `tag` is
- * returned by hc_stream_poll.  Returns HC_ERR_DISORDER (chunk rejected,
- * stream unchanged) if a hit has toa <= M - t (when M >= t) or, after a
- * flush, toa <= F (see hc_stream_flush); HC_ERR_RANGE (rejected) if a hit is
- * off the sensor, HC_ERR_OVERFLOW past 2^31 - 1 hits.  Blocks until the
- * chunk has been processed on the device. */
+/* Append n hits (device array, read when the push runs on the stream: keep
+ * it unchanged until then -- later work on the same stream is ordered after
+ * it, and hc_stream_wait waits for it).  labels: device int32[n] that the
+ * library fills as the chunk's clusters close; it must stay valid until
+ * `tag` is returned by hc_stream_poll.  The chunk is rejected on the device,
+ * leaving the stream unchanged and its labels untouched, if a hit is off the
+ * sensor (status HC_ERR_RANGE) or has toa <= M - t (when M >= t) or, after a
+ * flush, toa <= F (see hc_stream_flush) (status HC_ERR_DISORDER); the status
+ * comes with the tag from hc_stream_poll.  Returns HC_OK once enqueued,
+ * HC_ERR_ARG for bad arguments, HC_ERR_OVERFLOW past 2^31 - 1 hits pushed,
+ * HC_ERR_DEVICE after a device failure. */
 int hc_stream_push(hc_stream* s, const hc_hit* hits, int32_t n, int32_t* labels, uint64_t tag);
 
-/* Drain completion events into HOST buffers: up to cap tags of chunks whose
- * labels are all final (in completion order), and up to closed_cap features
- * of closed clusters (labels stream-global; ascending label within one push).
+/* hc_stream_push with caller-chosen ids (device int32[n], non-negative):
+ * a cluster's label -- in the labels buffers and in the closed features --
+ * is then the smallest id among its hits instead of the smallest global
+ * index.  For callers that push hits in another order than they number them
+ * (the buffer filling of hc_ingest moves late hits into the next buffer).  A
+ * stream takes ids with every push or with none (HC_ERR_ARG otherwise); a
+ * chunk with a negative id is rejected (status HC_ERR_ARG). */
+int hc_stream_push_ids(hc_stream* s, const hc_hit* hits, const int32_t* ids, int32_t n, int32_t* labels,
+                       uint64_t tag);
+
+/* Drain completion events into HOST buffers, without waiting for pushes in
+ * flight: up to cap tags of finished chunks (in completion order) with their
+ * status (status may be NULL): HC_OK when every label of the chunk is final,
+ * or the reason it was rejected; and up to closed_cap features of closed
+ * clusters (labels stream-global; ascending label within one push).
  * Entries beyond the caps stay queued for the next call. */
-int hc_stream_poll(hc_stream* s, uint64_t* done_tags, int32_t cap, int32_t* n_done, hc_features* closed,
-                   int32_t closed_cap, int32_t* n_closed);
+int hc_stream_poll(hc_stream* s, uint64_t* done_tags, int32_t* status, int32_t cap, int32_t* n_done,
+                   hc_features* closed, int32_t closed_cap, int32_t* n_closed);
+
+/* Wait until every push enqueued so far has run on the device (their
+ * completions are then available to hc_stream_poll). */
+int hc_stream_wait(hc_stream* s);
 
 /* Pre-allocate the stream's device buffers for chunks of up to max_chunk
  * hits (plus a margin of open hits), so that later pushes allocate nothing
  * unless a chunk is larger or unusually many clusters stay open. */
 int hc_stream_reserve(hc_stream* s, int32_t max_chunk);
 
-/* Hits currently held open on the device (their clusters may still grow);
- * -1 for a NULL stream. */
+/* Hits held open on the device (their clusters may still grow) after the
+ * last push known to have completed; -1 for a NULL stream. */
 int64_t hc_stream_open_hits(const hc_stream* s);
 
-/* Close every open cluster (end of stream); afterwards all pushed chunks are
- * complete.  The stream may continue as a new segment that no cluster spans:
+/* Close every open cluster (end of stream) and wait for it; afterwards all
+ * pushed chunks are complete.  The stream may continue as a new segment that
+ * no cluster spans:
  * with M the largest ToA pushed before the flush, a later push is rejected
  * (HC_ERR_DISORDER) unless every hit has toa > F = M + dt (saturating), so no
  * later hit can be adjacent in time to a hit whose label is already final. */
 int hc_stream_flush(hc_stream* s);
 
 void hc_stream_destroy(hc_stream* s);
+
+/* ---- Host ingest front end ------------------------------------------------
+ *
+ * Hits as the detector delivers them (host memory, t-ordered, Section 3.1),
+ * numbered by arrival (0, 1, 2, ... over all feeds), are filled into pinned
+ * buffers by the paper's buffer filling (its Algorithm "Hit buffer filling",
+ * Section 4.1): a buffer takes every hit until it holds b - b_t, tracking the
+ * largest ToA seen (toa_max); after that only hits with
+ * toa < toa_max + t_closing, later ones going to the next buffer; when a hit
+ * arrives with toa - toa_max > t + t_closing the buffer is complete and is
+ * sent (so is a buffer whose next buffer is full).  Sent buffers are copied
+ * to the device on their own HIP stream and clustered by an hc_stream
+ * (exact stitching across buffers) while the next ones fill and copy
+ * (steps 1, 2 and 8 of the paper's high-level GPU algorithm; pinned memory
+ * and copy/compute overlap, Section 5).  labels_out[i] receives the smallest
+ * arrival index of hit i's cluster once final; hc_ingest_finish makes every
+ * fed hit final. */
+typedef struct hc_ingest hc_ingest;
+
+typedef struct {
+    uint32_t width, height;      /* sensor (0 => 256) */
+    uint32_t disorder_hint;      /* positional displacement hint (0 => 4096) */
+    uint32_t flags;              /* must be 0 */
+    uint64_t dt;                 /* time window of the clusters, ticks */
+    uint64_t max_disorder_ticks; /* t of the input (t-ordered bound) */
+    uint64_t t_closing;          /* the paper's t_closing: longest expected cluster duration */
+    int32_t buffer_hits;         /* b: capacity of one buffer */
+    int32_t reserve_hits;        /* b_t: hits expected within t + t_closing (0 <= b_t < b) */
+    int32_t n_buffers;           /* pinned/device buffer pairs (0 => 4; at least 3) */
+    int32_t reserved;            /* must be 0 */
+    void* stream;                /* hipStream_t of the clustering (NULL = null stream) */
+} hc_ingest_config;
+
+typedef struct {
+    int64_t hits_fed, hits_done;  /* numbered so far; with their labels placed */
+    int64_t buffers_sent, buffers_done;
+    int64_t forced_sends;         /* buffers sent because the next one was full */
+    int64_t diverted;             /* hits that arrived for the next buffer before this one was sent */
+    int64_t waits;                /* times the host waited for a free buffer */
+} hc_ingest_stats;
+
+/* labels_out: HOST int32[labels_cap]; feeding more hits returns HC_ERR_OVERFLOW. */
+int hc_ingest_create(const hc_ingest_config* cfg, int32_t* labels_out, int64_t labels_cap, hc_ingest** out);
+/* Number and buffer n more hits (host array, arrival order); sends buffers as
+ * they complete and places the labels of finished ones.  Never waits for the
+ * device unless every buffer is in use. */
+int hc_ingest_feed(hc_ingest* g, const hc_hit* hits, int64_t n);
+/* Send what is buffered, close every cluster and wait: afterwards every fed
+ * hit has its final label.  Later feeds start a new segment (see
+ * hc_stream_flush). */
+int hc_ingest_finish(hc_ingest* g);
+int hc_ingest_stats_read(const hc_ingest* g, hc_ingest_stats* out);
+void hc_ingest_destroy(hc_ingest* g);
 
 /* ---- Batch form: many independent chunks, one launch per stage ----------
  *

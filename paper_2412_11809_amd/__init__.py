@@ -78,6 +78,7 @@ def load_library(path=LIB_PATH):
 
 HC_FLAG_LINK_PIXEL_INDEX = 1
 HC_FLAG_LINK_WINDOW = 2
+HC_FLAG_GLOBAL_TIME = 4
 
 
 def _opts(width, height, disorder_hint, workspace, stream, flags=0):
@@ -108,8 +109,8 @@ def hc_last_error():
     return load_library().hc_last_error().decode()
 
 
-def hc_workspace_size(n, width=256, height=256, disorder_hint=0):
-    o = _opts(width, height, disorder_hint, None, None)
+def hc_workspace_size(n, width=256, height=256, disorder_hint=0, flags=0):
+    o = _opts(width, height, disorder_hint, None, None, flags)
     return int(load_library().hc_workspace_size(ctypes.byref(o), int(n)))
 
 
@@ -193,9 +194,11 @@ def _bind_stream(lib):
     lib.hc_stream_push.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_uint64]
     lib.hc_stream_poll.restype = ctypes.c_int
-    lib.hc_stream_poll.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+    lib.hc_stream_poll.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32)]
+    lib.hc_stream_wait.restype = ctypes.c_int
+    lib.hc_stream_wait.argtypes = [ctypes.c_void_p]
     lib.hc_stream_reserve.restype = ctypes.c_int
     lib.hc_stream_reserve.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     lib.hc_stream_flush.restype = ctypes.c_int
@@ -209,7 +212,9 @@ def _bind_stream(lib):
 
 
 class HcStream:
-    """One detector stream (hc_stream_*): push device chunks, poll completions."""
+    """One detector stream (hc_stream_*): push device chunks (asynchronous),
+    poll completions.  Chunks the device rejected are collected in
+    ``rejected`` ({tag: status}) by ``poll``."""
 
     def __init__(self, dt, max_disorder_ticks, width=256, height=256, disorder_hint=0, stream=None, flags=0):
         import torch
@@ -221,6 +226,7 @@ class HcStream:
         h = ctypes.c_void_p()
         _check(self._lib.hc_stream_create(ctypes.byref(o), int(dt), int(max_disorder_ticks), ctypes.byref(h)))
         self._h = h
+        self.rejected = {}
 
     def hc_stream_push(self, hits, n, labels, tag):
         rc = self._lib.hc_stream_push(self._h, _ptr(hits), int(n), _ptr(labels), int(tag))
@@ -230,10 +236,12 @@ class HcStream:
         self.hc_stream_push(hits, hits.numel() // 16, labels, tag)
 
     def poll(self, cap=1 << 12, closed_cap=1 << 16):
-        """All completed tags and closed features (drains in rounds of the caps)."""
+        """Tags of the chunks completed so far (rejected ones go to
+        ``self.rejected``) and the closed features; drains in rounds of the caps."""
         if getattr(self, "_tags", None) is None or self._tags.size < cap or self._feats.size < closed_cap:
             import torch
             self._tags = np.empty(max(cap, 1), dtype=np.uint64)
+            self._status = np.empty(max(cap, 1), dtype=np.int32)
             # pinned, so the device-to-host copy of closed features is a DMA
             self._feats_t = torch.empty(max(closed_cap, 1) * FEATURE_DTYPE.itemsize, dtype=torch.uint8,
                                         pin_memory=True)
@@ -241,9 +249,13 @@ class HcStream:
         done, feats = [], []
         nd, nc = ctypes.c_int32(), ctypes.c_int32()
         while True:
-            _check(self._lib.hc_stream_poll(self._h, self._tags.ctypes.data, cap, ctypes.byref(nd),
-                                            self._feats.ctypes.data, closed_cap, ctypes.byref(nc)))
-            done += self._tags[: nd.value].tolist()
+            _check(self._lib.hc_stream_poll(self._h, self._tags.ctypes.data, self._status.ctypes.data, cap,
+                                            ctypes.byref(nd), self._feats.ctypes.data, closed_cap, ctypes.byref(nc)))
+            for t, s in zip(self._tags[: nd.value].tolist(), self._status[: nd.value].tolist()):
+                if s == HC_OK:
+                    done.append(t)
+                else:
+                    self.rejected[t] = s
             feats.append(self._feats[: nc.value].copy())
             if nd.value < cap and nc.value < closed_cap:
                 break
@@ -252,6 +264,10 @@ class HcStream:
     def open_hits(self):
         """Hits held open on the device (hc_stream_open_hits)."""
         return int(self._lib.hc_stream_open_hits(self._h))
+
+    def wait(self):
+        """hc_stream_wait: every push enqueued so far has run."""
+        _check(self._lib.hc_stream_wait(self._h))
 
     def reserve(self, max_chunk):
         _check(self._lib.hc_stream_reserve(self._h, int(max_chunk)))
@@ -431,6 +447,134 @@ def cluster_batch(hits, offsets, dts, width=256, height=256, disorder_hint=0, fe
     k = torch.empty(n_chunks, dtype=torch.int32, device=dev)
     hc_cluster_batch(hits, offsets, dts, labels, feats, k, plan, width, height, disorder_hint, None, stream)
     return labels[:n], feats, k
+
+
+# ---- per-cluster products
+BOX_DTYPE = np.dtype([("x_min", "<u2"), ("x_max", "<u2"), ("y_min", "<u2"), ("y_max", "<u2")])
+
+
+class _Filter(ctypes.Structure):
+    _fields_ = [("min_size", ctypes.c_uint32), ("max_size", ctypes.c_uint32),
+                ("min_sum_tot", ctypes.c_uint64), ("max_sum_tot", ctypes.c_uint64),
+                ("toa_from", ctypes.c_uint64), ("toa_to", ctypes.c_uint64)]
+
+
+def _bind_products(lib):
+    if getattr(lib, "_products_bound", False):
+        return lib
+    vp = ctypes.c_void_p
+    lib.hc_products_workspace_size.restype = ctypes.c_size_t
+    lib.hc_products_workspace_size.argtypes = [ctypes.c_int64]
+    lib.hc_cluster_products.restype = ctypes.c_int
+    lib.hc_cluster_products.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.POINTER(_Filter), vp, vp, vp, vp, vp,
+                                        vp, vp, ctypes.c_size_t, vp]
+    lib._products_bound = True
+    return lib
+
+
+def hc_products_workspace_size(n):
+    return int(_bind_products(load_library()).hc_products_workspace_size(int(n)))
+
+
+def hc_cluster_products(hits, n, labels, features, n_clusters, keep_rows, n_keep, boxes=None, grouped=None,
+                        grouped_idx=None, row_start=None, filter=None, workspace=None, stream=None):
+    """Direct call of hc_cluster_products on device tensors.  filter: None or
+    a dict with any of min_size, max_size, min_sum_tot, max_sum_tot,
+    toa_from, toa_to."""
+    import torch
+    lib = _bind_products(load_library())
+    if stream is None:
+        stream = torch.cuda.current_stream(labels.device)
+    f = None
+    if filter is not None:
+        f = _Filter(0, 0xFFFFFFFF, 0, (1 << 64) - 1, 0, (1 << 64) - 1)
+        for k, v in filter.items():
+            setattr(f, k, int(v))
+    if workspace is None:
+        workspace = torch.empty(max(1, hc_products_workspace_size(n)), dtype=torch.uint8, device=labels.device)
+    s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    _check(lib.hc_cluster_products(_ptr(hits), int(n), _ptr(labels), _ptr(features), _ptr(n_clusters),
+                                   ctypes.byref(f) if f is not None else None, _ptr(boxes), _ptr(keep_rows),
+                                   _ptr(n_keep), _ptr(grouped), _ptr(grouped_idx), _ptr(row_start),
+                                   _ptr(workspace), workspace.numel(), s))
+    return workspace
+
+
+# ---- host ingest front end
+class _IngestConfig(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_uint32), ("height", ctypes.c_uint32), ("disorder_hint", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("dt", ctypes.c_uint64), ("max_disorder_ticks", ctypes.c_uint64),
+                ("t_closing", ctypes.c_uint64), ("buffer_hits", ctypes.c_int32), ("reserve_hits", ctypes.c_int32),
+                ("n_buffers", ctypes.c_int32), ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class _IngestStats(ctypes.Structure):
+    _fields_ = [("hits_fed", ctypes.c_int64), ("hits_done", ctypes.c_int64), ("buffers_sent", ctypes.c_int64),
+                ("buffers_done", ctypes.c_int64), ("forced_sends", ctypes.c_int64), ("diverted", ctypes.c_int64),
+                ("waits", ctypes.c_int64)]
+
+
+def _bind_ingest(lib):
+    if getattr(lib, "_ingest_bound", False):
+        return lib
+    vp = ctypes.c_void_p
+    lib.hc_ingest_create.restype = ctypes.c_int
+    lib.hc_ingest_create.argtypes = [ctypes.POINTER(_IngestConfig), vp, ctypes.c_int64, ctypes.POINTER(vp)]
+    lib.hc_ingest_feed.restype = ctypes.c_int
+    lib.hc_ingest_feed.argtypes = [vp, vp, ctypes.c_int64]
+    lib.hc_ingest_finish.restype = ctypes.c_int
+    lib.hc_ingest_finish.argtypes = [vp]
+    lib.hc_ingest_stats_read.restype = ctypes.c_int
+    lib.hc_ingest_stats_read.argtypes = [vp, ctypes.POINTER(_IngestStats)]
+    lib.hc_ingest_destroy.restype = None
+    lib.hc_ingest_destroy.argtypes = [vp]
+    lib._ingest_bound = True
+    return lib
+
+
+class HcIngest:
+    """Host ingest front end (hc_ingest_*): feed host hits in arrival order;
+    labels land in ``labels`` (a host int32 array, indexed by arrival)."""
+
+    def __init__(self, labels, dt, max_disorder_ticks, t_closing, buffer_hits, reserve_hits, width=256,
+                 height=256, disorder_hint=0, n_buffers=0, stream=None):
+        import torch
+        self._lib = _bind_ingest(load_library())
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        c = _IngestConfig()
+        c.width, c.height, c.disorder_hint, c.flags = width, height, disorder_hint, 0
+        c.dt, c.max_disorder_ticks, c.t_closing = int(dt), int(max_disorder_ticks), int(t_closing)
+        c.buffer_hits, c.reserve_hits, c.n_buffers, c.reserved = int(buffer_hits), int(reserve_hits), n_buffers, 0
+        c.stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self._labels = labels
+        h = ctypes.c_void_p()
+        _check(self._lib.hc_ingest_create(ctypes.byref(c), _host_ptr(labels), _host_len(labels, 4),
+                                          ctypes.byref(h)))
+        self._h = h
+
+    def feed(self, hits):
+        """hits: host HIT_DTYPE array (or uint8 tensor of 16-byte records)."""
+        _check(self._lib.hc_ingest_feed(self._h, _host_ptr(hits), _host_len(hits, 16)))
+
+    def finish(self):
+        _check(self._lib.hc_ingest_finish(self._h))
+
+    def stats(self):
+        s = _IngestStats()
+        _check(self._lib.hc_ingest_stats_read(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _IngestStats._fields_}
+
+    def close(self):
+        if self._h:
+            self._lib.hc_ingest_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- served form

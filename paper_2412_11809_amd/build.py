@@ -14,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhc.so")
-SOURCES = ["hc_api.cpp", "hc_sort.hip", "hc_link.hip", "hc_feat.hip", "hc_stream.hip", "hc_batch.hip", "hc_server.hip"]
+SOURCES = ["hc_api.cpp", "hc_sort.hip", "hc_link.hip", "hc_feat.hip", "hc_stream.hip", "hc_batch.hip", "hc_server.hip",
+           "hc_products.hip", "hc_global.hip", "hc_ingest.cpp"]
 ARCH = "gfx950"
 
 

@@ -306,7 +306,8 @@ size_t hc_workspace_size(const hc_opts* opts, int64_t n)
     if (n < 0) return 0;
     const uint32_t W = opts && opts->width ? opts->width : 256;
     const uint32_t H = opts && opts->height ? opts->height : 256;
-    return plan_workspace(n, W, H, opts ? opts->disorder_hint : 0, nullptr, nullptr);
+    const size_t base = plan_workspace(n, W, H, opts ? opts->disorder_hint : 0, nullptr, nullptr);
+    return global_time_of(opts) ? base + plan_global(n, nullptr, nullptr) : base;
 }
 
 int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_features* features,
@@ -327,7 +328,9 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_f
     }
     Work w;
     const uint32_t D = opts ? opts->disorder_hint : 0;
-    const size_t need = plan_workspace(n, W, H, D, &w, nullptr);
+    const bool global = global_time_of(opts);
+    const size_t base_need = plan_workspace(n, W, H, D, &w, nullptr);
+    const size_t need = global ? base_need + plan_global(n, nullptr, nullptr) : base_need;
     void* ws = opts ? opts->workspace : nullptr;
     std::unique_lock<std::mutex> hold;  // a cached workspace stays ours until the launches are enqueued
     if (ws) {
@@ -341,7 +344,7 @@ int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels, hc_f
     plan_workspace(n, W, H, D, &w, (char*)ws);
     w.dt = dt;
     w.link_mode = link_mode_of(opts);
-
+    if (global) return global_cluster(hits, w, (char*)ws + base_need, labels, features, n_clusters, s);
     return enqueue_cluster(hits, w, labels, features, n_clusters, s);
 }
 

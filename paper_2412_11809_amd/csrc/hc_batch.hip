@@ -97,8 +97,8 @@ int plan_batch(const int64_t* offsets, int32_t n_chunks, const uint64_t* dts, co
 {
     const uint32_t W = opts && opts->width ? opts->width : 256;
     const uint32_t H = opts && opts->height ? opts->height : 256;
-    if (W > 65535 || H > 65535 || (opts && !link_flags_valid(opts->flags)))
-        return set_error(HC_ERR_ARG, "bad options");
+    if (W > 65535 || H > 65535 || (opts && !link_flags_valid(opts->flags)) || global_time_of(opts))
+        return set_error(HC_ERR_ARG, "bad options (HC_FLAG_GLOBAL_TIME is for hc_cluster only)");
     segs = make_segs(offsets, n_chunks, dts);
     *bytes = plan_workspace(offsets[n_chunks], W, H, plan_hint(plan, opts), w, base, segs.data(), n_chunks);
     if (w) {

@@ -29,6 +29,7 @@ __device__ inline uint32_t root_hash(uint32_t key) { return (key * 0x9E3779B1u) 
 
 __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t* __restrict__ labels)
 {
+    resolve_count(w);
     static_assert(kFeatHash == 512 && kFeatHash >= kFeatTile, "root_hash yields 9 bits; a tile never fills the table");
     static_assert((uint64_t)kFeatTile * 65535u < (1ull << 32), "paired 32-bit sums must not carry");
     // label + 1 (below 2^31), bit 31 set once the cluster's label hit is seen
@@ -218,6 +219,7 @@ hipError_t launch_features(const Work& w, const int32_t* labels, hipStream_t s)
 // one work-group per feature tile (grid-stride), most tiles have none.
 __global__ __launch_bounds__(64) void k_carries(Work w)
 {
+    resolve_count(w);
     if (w.status->err_range) return;
     for (int64_t k = blockIdx.x; k < w.n_feat_tiles; k += gridDim.x) {
         const int nc = w.tile_ncarry[k];
@@ -254,6 +256,7 @@ hipError_t launch_carries(const Work& w, hipStream_t s)
 // writes the cluster count (or the error status) to the caller.
 __global__ __launch_bounds__(1024) void k_scan_blocks(Work w, int32_t* n_clusters)
 {
+    resolve_count(w);
     __shared__ uint32_t wsum[1024 / kWave];
     const Status* st = w.status;
     if (st->err_range || st->err_internal || st->err_span) {
@@ -287,8 +290,9 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Work w, int32_t* n_cluster
 // kScanBlock input indices (ranks blk_off[b] .. blk_off[b + 1] - 1).
 __global__ __launch_bounds__(kScanThreads) void k_compact(Work w, hc_features* __restrict__ out)
 {
+    resolve_count(w);
     const Status* st = w.status;
-    if (st->err_range || st->err_internal || st->err_span) return;
+    if (st->err_range || st->err_internal || st->err_span || (int)blockIdx.x >= w.n_scan_blocks) return;
     const int b = blockIdx.x, t = threadIdx.x;
     const TileRange tr = tile_range(w, kScanKind, b, kScanBlock);
     const uint32_t r0 = w.blk_off[b], r1 = w.blk_off[b + 1];

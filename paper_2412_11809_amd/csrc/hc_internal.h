@@ -7,6 +7,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "hc.h"
 
@@ -102,6 +103,11 @@ struct SegSpec {
 // Device pointers into one workspace, for n hits.
 struct Work {
     int32_t n;
+    // Non-null (single chunk only): the hit count lives in device memory,
+    // written by an earlier kernel on the same stream; every kernel reads it
+    // first and derives the tile counts from it, while n and the counts below
+    // are capacity bounds that size the grids and the workspace.
+    const int32_t* n_dev;
     uint32_t width, height;
     uint64_t dt;
     int32_t xcd_map;         // 1: contiguous tile ranges per XCD, 0: round-robin
@@ -188,16 +194,27 @@ inline int sort_tile_for(int64_t D)
     return 8192;
 }
 
-// hc_opts.flags: at most one HC_FLAG_LINK_* value; the Work.link_mode it selects.
+// hc_opts.flags: at most one HC_FLAG_LINK_* value, optionally with
+// HC_FLAG_GLOBAL_TIME (hc_cluster only); the Work.link_mode it selects.
 inline bool link_flags_valid(uint32_t f)
 {
-    return f == 0 || f == HC_FLAG_LINK_PIXEL_INDEX || f == HC_FLAG_LINK_WINDOW;
+    const uint32_t link = f & ~HC_FLAG_GLOBAL_TIME;
+    return link == 0 || link == HC_FLAG_LINK_PIXEL_INDEX || link == HC_FLAG_LINK_WINDOW;
 }
 inline int32_t link_mode_of(const hc_opts* o)
 {
     if (!o) return 0;
-    return o->flags == HC_FLAG_LINK_PIXEL_INDEX ? 1 : o->flags == HC_FLAG_LINK_WINDOW ? 2 : 0;
+    const uint32_t link = o->flags & ~HC_FLAG_GLOBAL_TIME;
+    return link == HC_FLAG_LINK_PIXEL_INDEX ? 1 : link == HC_FLAG_LINK_WINDOW ? 2 : 0;
 }
+inline bool global_time_of(const hc_opts* o) { return o && (o->flags & HC_FLAG_GLOBAL_TIME); }
+
+// The Section 2 (iii)(b) clustering (hc_global.hip): its extra workspace
+// (behind the plain path's), and the launch sequence.
+struct GlbWork;
+size_t plan_global(int64_t n, GlbWork* g, char* base);
+int global_cluster(const hc_hit* hits, Work& w, char* extra, int32_t* labels, hc_features* features,
+                   int32_t* n_clusters, hipStream_t s);
 // Segments of the fallback's digit-counter scan (256 counters per block).
 __host__ __device__ inline int32_t fb_scan_segments(int32_t nb)
 {
@@ -214,6 +231,24 @@ bool timing_set(bool on);
 size_t stream_device_bytes(const hc_stream* st);
 size_t stream_bytes_after_push(const hc_stream* st, int64_t n, size_t* transient);
 int64_t stream_open_hits(const hc_stream* st);
+// Pushes enqueued so far, and pushes completed on the device and read back
+// (retiring whatever has completed, without waiting); wait for the oldest
+// push in flight.
+uint64_t stream_pushes_enqueued(const hc_stream* st);
+uint64_t stream_pushes_retired(hc_stream* st);
+int stream_wait_one(hc_stream* st);
+size_t stream_inflight(const hc_stream* st);
+// A completed chunk push, as the server sees it: the push's tag, whether the
+// chunk was accepted, and how many clusters the push closed.
+struct RetiredPush {
+    uint64_t tag;
+    int32_t verdict;
+    int32_t n_closed;
+};
+// Pushes in flight at most (depth); with log_retired every completed chunk
+// push is recorded for stream_take_retired, which appends and clears them.
+void stream_configure(hc_stream* st, int depth, bool log_retired);
+size_t stream_take_retired(hc_stream* st, std::vector<RetiredPush>* out);
 int set_device_error(hipError_t e, const char* what);
 int persistent_grid();
 

@@ -51,6 +51,7 @@ __host__ __device__ inline int link_kernel(const Work& w)
 // bitmap (such tiles go to the fallback).
 __global__ void k_link_halo(Work w)
 {
+    resolve_count(w);
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= w.n_link_tiles || w.status->err_range) return;
     const TileRange tr = tile_range(w, kLinkKind, k, kLinkTile);
@@ -353,6 +354,7 @@ __device__ inline uint32_t pix_rank(uint32_t p, const uint64_t* bm, const uint16
 template <typename PixT>
 __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint32_t magic)
 {
+    resolve_count(w);
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
     constexpr int PER = kLinkTile / kLinkThreads;
     constexpr int LPER = LCAP / kLinkThreads;
@@ -549,6 +551,7 @@ __global__ __launch_bounds__(kLinkThreads, 8) void k_link(Work w, int bm64, uint
 // window holds every hit of the last dt.
 __global__ __launch_bounds__(kLinkThreads, 8) void k_link_window(Work w)
 {
+    resolve_count(w);
     constexpr int LCAP = kLinkTile + kLinkHaloCap;
     constexpr int PER = kLinkTile / kLinkThreads;
     __shared__ uint32_t l_toa[LCAP];
@@ -714,6 +717,7 @@ struct PixSortJob {
 
 __global__ __launch_bounds__(kFbThreads) void k_link_fallback(Work w)
 {
+    resolve_count(w);
     if (!w.status->n_overflow || w.status->err_range) return;  // the common case
     PixSortJob job{w};
     uint64_t* kb[2] = {w.fb_key[0], w.fb_key[1]};
@@ -736,6 +740,7 @@ hipError_t launch_link_fallback(const Work& w, hipStream_t s)
 // reading the count, the edges and the parent chains once).
 __global__ __launch_bounds__(256) void k_union_edges(Work w)
 {
+    resolve_count(w);
     if (w.status->err_range) return;
     const int64_t k = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
     if (k >= w.n_link_tiles) return;
@@ -766,7 +771,8 @@ __global__ __launch_bounds__(kScanThreads) void k_flatten(Work w, int32_t* __res
     static_assert(kScanBlock / 64 <= kWave, "one wave scans the block's mask words");
     __shared__ uint32_t wsum[kScanThreads / kWave];
     __shared__ uint32_t s_wc[kScanBlock / 64];  // roots per mask word
-    if (w.status->err_range) return;
+    resolve_count(w);
+    if (w.status->err_range || (int)blockIdx.x >= w.n_scan_blocks) return;
     const int b = blockIdx.x;
     const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
     const TileRange tr = tile_range(w, kScanKind, b, kScanBlock);

@@ -3,7 +3,12 @@
 // hc_stream (open clusters stay on the device and are stitched exactly across
 // chunks).  Chunks wait per stream in arrival order and are admitted when a
 // device slot is free and the memory they need fits the HBM budget; admitted
-// chunks of different streams run concurrently on the device.
+// chunks of different streams run concurrently on the device, and a stream's
+// own chunks are pipelined: pushes are asynchronous, so the worker copies and
+// enqueues the next chunk while earlier ones still run, and retires pushes
+// (slot release, processing stamp, closed clusters to the host) as their
+// completion is observed.  Final labels go back on a separate copy stream,
+// which never waits for pushes still in flight.
 #include <string.h>
 
 #include <algorithm>
@@ -24,6 +29,7 @@ using namespace hc;
 namespace {
 
 constexpr size_t kMinBlock = 64 << 10;
+constexpr int kServerDepth = 2;  // pushes in flight per stream
 
 size_t block_class(size_t bytes)
 {
@@ -54,7 +60,8 @@ struct Pending {
 struct StreamCtx {
     int id = 0;
     hc_stream* st = nullptr;
-    hipStream_t hs = nullptr;
+    hipStream_t hs = nullptr;  // hits in, pushes
+    hipStream_t cs = nullptr;  // final labels out
     std::thread th;
     std::condition_variable cv;
     std::deque<Req> q;                           // guarded by the server mutex
@@ -63,11 +70,14 @@ struct StreamCtx {
     size_t closed_head = 0;                      // rows of closed.front() already handed out
     std::unordered_map<uint64_t, Pending> pend;  // worker-only, keyed by internal sequence number
     uint64_t seq = 0;
+    int in_device = 0;                           // pushed chunks not yet retired (worker-only)
     void* hits_dev = nullptr;
     size_t hits_bytes = 0;
     size_t state_bytes = 0;  // device bytes of the hc_stream counted in `used`
-    uint64_t* tags_pin = nullptr;      // pinned drain buffers (completed chunk tags,
+    uint64_t* tags_pin = nullptr;      // pinned drain buffers (finished chunk tags,
+    int32_t* status_pin = nullptr;     // their status,
     hc_features* feats_pin = nullptr;  // closed-cluster features)
+    std::vector<RetiredPush> retired;  // scratch
 };
 
 constexpr int kDrainTags = 256, kDrainFeats = 1 << 16;
@@ -97,7 +107,7 @@ struct hc_server {
     uint64_t used = 0, peak = 0, progress = 0;
     int slots_used = 0, peak_slots = 0;
     int64_t submitted = 0, completed = 0, rejected = 0, hits_completed = 0, queued = 0, pending_final = 0;
-    int working = 0;  // requests taken by a worker and not finished
+    int working = 0;  // requests taken by a worker and not yet through their device processing
     std::atomic<uint64_t> ns_admit{0}, ns_push{0}, ns_drain{0}, ns_final{0};
     bool stopping = false;
     std::vector<StreamCtx*> streams;
@@ -140,23 +150,24 @@ struct hc_server {
     }
 
     void worker(StreamCtx* cx);
-    int run_chunk(StreamCtx* cx, const Req& r);
-    void drain(StreamCtx* cx, int32_t* n_closed_out, std::vector<uint64_t>* fin);
-    void finalize(StreamCtx* cx, uint64_t seq);
+    bool try_admit(StreamCtx* cx, const Req& r, Pending* p, size_t* hits_need, uint64_t* charged);
+    void run_chunk(StreamCtx* cx, const Req& r, Pending p, size_t hits_need, uint64_t charged);
+    void advance(StreamCtx* cx);
+    void finish(StreamCtx* cx, uint64_t seq, int32_t status);
 };
 
-// Copy a chunk's final labels to the caller and emit its completion.
-void hc_server::finalize(StreamCtx* cx, uint64_t seq)
+// A chunk is done: final labels to the caller (or its rejection), then its
+// completion record.
+void hc_server::finish(StreamCtx* cx, uint64_t seq, int32_t status)
 {
     auto it = cx->pend.find(seq);
     if (it == cx->pend.end()) return;
     Pending p = it->second;
     cx->pend.erase(it);
     const uint64_t f0 = now_ns();
-    int status = HC_OK;
-    if (p.n > 0) {
-        hipError_t e = hipMemcpyAsync(p.labels_host, p.labels_dev, 4 * (size_t)p.n, hipMemcpyDeviceToHost, cx->hs);
-        if (e == hipSuccess) e = hipStreamSynchronize(cx->hs);
+    if (status == HC_OK && p.n > 0) {
+        hipError_t e = hipMemcpyAsync(p.labels_host, p.labels_dev, 4 * (size_t)p.n, hipMemcpyDeviceToHost, cx->cs);
+        if (e == hipSuccess) e = hipStreamSynchronize(cx->cs);
         if (e != hipSuccess) status = set_device_error(e, "server: label copy");
     }
     hc_completion c{};
@@ -164,10 +175,10 @@ void hc_server::finalize(StreamCtx* cx, uint64_t seq)
     c.stream_id = cx->id;
     c.status = status;
     c.n_hits = p.n;
-    c.n_closed = p.n_closed;
+    c.n_closed = status == HC_OK ? p.n_closed : 0;
     c.t_arrive_ns = p.t_arrive;
     c.t_admit_ns = p.t_admit;
-    c.t_processed_ns = p.t_processed;
+    c.t_processed_ns = p.t_processed ? p.t_processed : now_ns();
     c.t_final_ns = now_ns();
     ns_final += c.t_final_ns - f0;
     std::lock_guard<std::mutex> lk(mu);
@@ -176,89 +187,102 @@ void hc_server::finalize(StreamCtx* cx, uint64_t seq)
     complete(c);
 }
 
-// Move closed clusters to the host and collect the chunks that completed.
-void hc_server::drain(StreamCtx* cx, int32_t* n_closed_out, std::vector<uint64_t>* fin)
+// Retire the pushes that completed: closed clusters to the host, processing
+// stamps, slots released; then the chunks that finished.
+void hc_server::advance(StreamCtx* cx)
 {
-    int32_t total = 0;
+    cx->retired.clear();
+    stream_take_retired(cx->st, &cx->retired);
+    std::vector<std::pair<uint64_t, int32_t>> fin;
+    const uint64_t dr0 = now_ns();
     for (;;) {
         int32_t nd = 0, nc = 0;
-        if (hc_stream_poll(cx->st, cx->tags_pin, kDrainTags, &nd, cx->feats_pin, kDrainFeats, &nc) != HC_OK) break;
+        if (hc_stream_poll(cx->st, cx->tags_pin, cx->status_pin, kDrainTags, &nd, cx->feats_pin, kDrainFeats, &nc) !=
+            HC_OK)
+            break;
         if (nc > 0) {  // copied outside any lock; only the hand-over is guarded
             std::vector<hc_features> blk(cx->feats_pin, cx->feats_pin + nc);
             std::lock_guard<std::mutex> lk(cx->cmu);
             cx->closed.push_back(std::move(blk));
         }
-        total += nc;
-        fin->insert(fin->end(), cx->tags_pin, cx->tags_pin + nd);
+        for (int32_t k = 0; k < nd; k++) fin.emplace_back(cx->tags_pin[k], cx->status_pin[k]);
         if (nd < kDrainTags && nc < kDrainFeats) break;
     }
-    if (n_closed_out) *n_closed_out = total;
+    const uint64_t tp = now_ns();
+    if (!cx->retired.empty() || !fin.empty()) ns_drain += tp - dr0;
+    if (!cx->retired.empty()) {
+        const size_t state_now = stream_device_bytes(cx->st);
+        std::lock_guard<std::mutex> lk(mu);
+        for (const RetiredPush& r : cx->retired) {
+            auto it = cx->pend.find(r.tag);
+            if (it != cx->pend.end()) {
+                it->second.t_processed = tp;
+                it->second.n_closed = r.n_closed;
+                lat_proc.push_back(tp - it->second.t_arrive);
+            }
+            slots_used--;
+            cx->in_device--;
+            working--;
+        }
+        account((int64_t)state_now - (int64_t)cx->state_bytes);
+        cx->state_bytes = state_now;
+        progress++;
+        budget_cv.notify_all();
+        idle_cv.notify_all();
+    }
+    for (const auto& f : fin) finish(cx, f.first, f.second);
 }
 
-int hc_server::run_chunk(StreamCtx* cx, const Req& r)
+// Admission (lock held): a free slot and the memory of this push within the
+// budget.  On success the memory is charged and *p holds the label block.
+bool hc_server::try_admit(StreamCtx* cx, const Req& r, Pending* p, size_t* hits_need, uint64_t* charged)
 {
-    const uint64_t seq = cx->seq++;
-    Pending p{r.tag, r.n, 0, r.labels, nullptr, 0, r.t_arrive, 0, 0};
-    const size_t hits_need = r.n > 0 ? block_class(sizeof(hc_hit) * (size_t)r.n) : 0;
-    const size_t hits_grow = hits_need > cx->hits_bytes ? hits_need - cx->hits_bytes : 0;
+    *hits_need = r.n > 0 ? block_class(sizeof(hc_hit) * (size_t)r.n) : 0;
+    const size_t hits_grow = *hits_need > cx->hits_bytes ? *hits_need - cx->hits_bytes : 0;
     size_t transient = 0;
     const size_t after = r.n > 0 ? stream_bytes_after_push(cx->st, r.n, &transient) : cx->state_bytes;
     const size_t state_grow = after > cx->state_bytes ? after - cx->state_bytes : 0;
-    p.labels_class = r.n > 0 ? block_class(4 * (size_t)r.n) : 0;
-    // admission: a free slot and the memory of this push within the budget
-    const uint64_t a0 = now_ns();
-    {
-        std::unique_lock<std::mutex> lk(mu);
-        for (;;) {
-            // the smallest cached label block that is large enough
-            auto fb = free_blocks.lower_bound(p.labels_class);
-            while (fb != free_blocks.end() && fb->second.empty()) ++fb;
-            const bool reuse = r.n > 0 && fb != free_blocks.end();
-            const uint64_t need = hits_grow + state_grow + transient + (reuse || r.n == 0 ? 0 : p.labels_class);
-            if (slots_used < cfg.max_slots && used + need <= cfg.hbm_budget) {
-                if (reuse) {
-                    p.labels_dev = fb->second.back();
-                    p.labels_class = fb->first;
-                    fb->second.pop_back();
-                }
-                account((int64_t)need);
-                slots_used++;
-                peak_slots = std::max(peak_slots, slots_used);
-                queued--;
-                progress++;
-                break;
-            }
-            if (used + need > cfg.hbm_budget && !free_blocks.empty() && trim_cache() > 0) continue;
-            const uint64_t p0 = progress;
-            budget_cv.wait_for(lk, std::chrono::milliseconds(200));
-            if (progress == p0 && slots_used == 0 && used + need > cfg.hbm_budget) {
-                // nothing in flight can release memory: this chunk can never fit
-                queued--;
-                hc_completion c{};
-                c.tag = r.tag;
-                c.stream_id = cx->id;
-                c.status = HC_ERR_BUDGET;
-                c.n_hits = r.n;
-                c.t_arrive_ns = r.t_arrive;
-                c.t_admit_ns = c.t_processed_ns = c.t_final_ns = now_ns();
-                complete(c);
-                return HC_ERR_BUDGET;
-            }
-        }
+    p->labels_class = r.n > 0 ? block_class(4 * (size_t)r.n) : 0;
+    auto fb = free_blocks.lower_bound(p->labels_class);
+    while (fb != free_blocks.end() && fb->second.empty()) ++fb;
+    const bool reuse = r.n > 0 && fb != free_blocks.end();
+    const uint64_t need = hits_grow + state_grow + transient + (reuse || r.n == 0 ? 0 : p->labels_class);
+    if (slots_used >= cfg.max_slots || used + need > cfg.hbm_budget) {
+        if (used + need > cfg.hbm_budget && !free_blocks.empty() && trim_cache() > 0)
+            return try_admit(cx, r, p, hits_need, charged);
+        return false;
     }
-    p.t_admit = now_ns();
-    ns_admit += p.t_admit - a0;
+    if (reuse) {
+        p->labels_dev = fb->second.back();
+        p->labels_class = fb->first;
+        fb->second.pop_back();
+    }
+    account((int64_t)need);
+    *charged = need - (reuse || r.n == 0 ? 0 : p->labels_class) - hits_grow;  // the stream's share
+    slots_used++;
+    peak_slots = std::max(peak_slots, slots_used);
+    queued--;
+    progress++;
+    return true;
+}
+
+void hc_server::run_chunk(StreamCtx* cx, const Req& r, Pending p, size_t hits_need, uint64_t charged)
+{
+    const uint64_t seq = cx->seq++;
     hipError_t e = hipSuccess;
     int rc = HC_OK;
-    if (hits_grow > 0) {
+    if (hits_need > cx->hits_bytes) {
+        // pushes in flight may still read the old buffer
+        if ((e = hipStreamSynchronize(cx->hs)) != hipSuccess) rc = set_device_error(e, "server: hits buffer");
         (void)hipFree(cx->hits_dev);
         cx->hits_dev = nullptr;
-        if ((e = hipMalloc(&cx->hits_dev, hits_need)) != hipSuccess) {
+        const size_t grow = hits_need - cx->hits_bytes;
+        if (rc == HC_OK && (e = hipMalloc(&cx->hits_dev, hits_need)) != hipSuccess) {
             rc = set_device_error(e, "server: hits buffer");
             std::lock_guard<std::mutex> lk(mu);
-            account(-(int64_t)cx->hits_bytes - (int64_t)hits_grow);
+            account(-(int64_t)cx->hits_bytes - (int64_t)grow);
             cx->hits_bytes = 0;
-        } else {
+        } else if (rc == HC_OK) {
             cx->hits_bytes = hits_need;
         }
     }
@@ -270,23 +294,23 @@ int hc_server::run_chunk(StreamCtx* cx, const Req& r)
             account(-(int64_t)p.labels_class);
         }
     }
+    // the hits buffer is rewritten only behind the earlier pushes on the same stream
     if (rc == HC_OK && r.n > 0 &&
         (e = hipMemcpyAsync(cx->hits_dev, r.hits, sizeof(hc_hit) * (size_t)r.n, hipMemcpyHostToDevice, cx->hs)) !=
             hipSuccess)
         rc = set_device_error(e, "server: hits copy");
-    if (rc == HC_OK) rc = hc_stream_push(cx->st, (const hc_hit*)cx->hits_dev, r.n, (int32_t*)p.labels_dev, seq);
+    if (rc == HC_OK && r.n > 0)
+        rc = hc_stream_push(cx->st, (const hc_hit*)cx->hits_dev, r.n, (int32_t*)p.labels_dev, seq);
     const uint64_t d0 = now_ns();
     ns_push += d0 - p.t_admit;
     const size_t state_now = stream_device_bytes(cx->st);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        account((int64_t)state_now - (int64_t)(cx->state_bytes + state_grow) - (int64_t)transient);
-        cx->state_bytes = state_now;
-        slots_used--;
-        progress++;
-        budget_cv.notify_all();
-    }
+    std::lock_guard<std::mutex> lk(mu);
+    // the growth charged at admission becomes the stream's actual size
+    account((int64_t)state_now - (int64_t)cx->state_bytes - (int64_t)charged);
+    cx->state_bytes = state_now;
     if (rc != HC_OK) {
+        slots_used--;
+        working--;
         hc_completion c{};
         c.tag = r.tag;
         c.stream_id = cx->id;
@@ -295,66 +319,129 @@ int hc_server::run_chunk(StreamCtx* cx, const Req& r)
         c.t_arrive_ns = r.t_arrive;
         c.t_admit_ns = p.t_admit;
         c.t_processed_ns = c.t_final_ns = now_ns();
-        std::lock_guard<std::mutex> lk(mu);
         if (p.labels_dev) free_blocks[p.labels_class].push_back(p.labels_dev);
         complete(c);
-        return rc;
+        idle_cv.notify_all();
+        return;
     }
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        pending_final++;
+    if (r.n == 0) {  // nothing to run: done at once
+        slots_used--;
+        working--;
+        hc_completion c{};
+        c.tag = r.tag;
+        c.stream_id = cx->id;
+        c.status = HC_OK;
+        c.t_arrive_ns = r.t_arrive;
+        c.t_admit_ns = p.t_admit;
+        c.t_processed_ns = c.t_final_ns = now_ns();
+        lat_proc.push_back(c.t_processed_ns - r.t_arrive);
+        complete(c);
+        idle_cv.notify_all();
+        return;
     }
+    pending_final++;
+    cx->in_device++;
     cx->pend.emplace(seq, p);
-    // closed clusters to the host first, then the processing stamp
-    int32_t n_closed = 0;
-    std::vector<uint64_t> fin;
-    const uint64_t dr0 = now_ns();
-    drain(cx, &n_closed, &fin);
-    const uint64_t tp = now_ns();
-    ns_drain += tp - dr0;
-    auto it = cx->pend.find(seq);
-    if (it != cx->pend.end()) {
-        it->second.t_processed = tp;
-        it->second.n_closed = n_closed;
-    }
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        lat_proc.push_back(tp - r.t_arrive);
-    }
-    for (uint64_t t : fin) finalize(cx, t);
-    return HC_OK;
 }
 
 void hc_server::worker(StreamCtx* cx)
 {
     (void)hipSetDevice(device);
     for (;;) {
-        Req r;
+        advance(cx);
+        Req r{};
+        Pending p{};
+        size_t hits_need = 0;
+        uint64_t charged = 0;
+        bool have = false, flush = false, wait_device = false;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cx->cv.wait(lk, [&] { return stopping || !cx->q.empty(); });
-            if (cx->q.empty()) break;  // stopping and nothing left
-            r = cx->q.front();
-            cx->q.pop_front();
-            working++;
-            if (r.flush) queued--;
+            if (!cx->q.empty()) {
+                const Req& front = cx->q.front();
+                if (front.flush) {
+                    if (cx->in_device == 0) {  // behind every chunk queued before it
+                        r = front;
+                        cx->q.pop_front();
+                        queued--;
+                        working++;
+                        have = flush = true;
+                    } else {
+                        wait_device = true;
+                    }
+                } else {
+                    p = Pending{front.tag, front.n, 0, front.labels, nullptr, 0, front.t_arrive, 0, 0};
+                    const uint64_t a0 = now_ns();
+                    if (try_admit(cx, front, &p, &hits_need, &charged)) {
+                        r = front;
+                        cx->q.pop_front();
+                        working++;
+                        have = true;
+                        p.t_admit = now_ns();
+                        ns_admit += p.t_admit - a0;
+                    } else if (cx->in_device > 0) {
+                        wait_device = true;  // our own pushes will free a slot or memory
+                    } else {
+                        const uint64_t p0 = progress;
+                        budget_cv.wait_for(lk, std::chrono::milliseconds(200));
+                        size_t hn;
+                        uint64_t ch;
+                        Pending probe = p;
+                        if (progress == p0 && slots_used == 0 && !stopping) {
+                            // nothing in flight can release memory: this chunk can never fit
+                            const uint64_t a1 = now_ns();
+                            if (!try_admit(cx, front, &probe, &hn, &ch)) {
+                                hc_completion c{};
+                                c.tag = front.tag;
+                                c.stream_id = cx->id;
+                                c.status = HC_ERR_BUDGET;
+                                c.n_hits = front.n;
+                                c.t_arrive_ns = front.t_arrive;
+                                c.t_admit_ns = c.t_processed_ns = c.t_final_ns = a1;
+                                cx->q.pop_front();
+                                queued--;
+                                complete(c);
+                                idle_cv.notify_all();
+                                continue;
+                            }
+                            r = front;
+                            p = probe;
+                            hits_need = hn;
+                            charged = ch;
+                            cx->q.pop_front();
+                            working++;
+                            have = true;
+                            p.t_admit = now_ns();
+                        }
+                    }
+                }
+            } else if (cx->in_device > 0) {
+                wait_device = true;
+            } else if (stopping) {
+                break;  // chunks still waiting for finality are released by hc_server_destroy
+            } else if (!cx->pend.empty()) {
+                // only finality pending: it needs more data or a flush
+                cx->cv.wait_for(lk, std::chrono::milliseconds(50));
+            } else {
+                cx->cv.wait(lk, [&] { return stopping || !cx->q.empty(); });
+            }
         }
         try {
-            if (r.flush) {
-                std::vector<uint64_t> fin;
-                if (hc_stream_flush(cx->st) == HC_OK) drain(cx, nullptr, &fin);
-                for (uint64_t t : fin) finalize(cx, t);
-            } else {
-                run_chunk(cx, r);
+            if (have && flush) {
+                if (hc_stream_flush(cx->st) != HC_OK) (void)hc_last_error();
+                advance(cx);
+                std::lock_guard<std::mutex> lk(mu);
+                working--;
+                progress++;
+                idle_cv.notify_all();
+                budget_cv.notify_all();
+            } else if (have) {
+                run_chunk(cx, r, p, hits_need, charged);
+            } else if (wait_device) {
+                (void)stream_wait_one(cx->st);
             }
         } catch (...) {
             (void)set_error(HC_ERR_DEVICE, "server worker: host exception");
         }
-        std::lock_guard<std::mutex> lk(mu);
-        working--;
-        progress++;
-        idle_cv.notify_all();
-        budget_cv.notify_all();
     }
 }
 
@@ -373,7 +460,7 @@ int hc_server_create(const hc_server_config* cfg, hc_server** out)
         c.max_slots < 0 || c.max_chunk_hits < 0)
         return set_error(HC_ERR_ARG, "bad server configuration");
     if (!c.max_chunk_hits) c.max_chunk_hits = 1 << 20;
-    if (!c.max_slots) c.max_slots = c.n_streams;
+    if (!c.max_slots) c.max_slots = kServerDepth * c.n_streams;
     if (!c.hbm_budget) c.hbm_budget = 16ull << 30;
     if (!c.disorder_hint) c.disorder_hint = 4096;
     hc_server* s = new hc_server();
@@ -388,7 +475,8 @@ int hc_server_create(const hc_server_config* cfg, hc_server** out)
         StreamCtx* cx = new StreamCtx();
         cx->id = i;
         s->streams.push_back(cx);
-        if ((e = hipStreamCreateWithFlags(&cx->hs, hipStreamNonBlocking)) != hipSuccess) {
+        if ((e = hipStreamCreateWithFlags(&cx->hs, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&cx->cs, hipStreamNonBlocking)) != hipSuccess) {
             rc = set_device_error(e, "hipStreamCreate");
             break;
         }
@@ -398,6 +486,7 @@ int hc_server_create(const hc_server_config* cfg, hc_server** out)
         o.disorder_hint = c.disorder_hint;
         o.stream = cx->hs;
         if ((rc = hc_stream_create(&o, c.dt, c.max_disorder_ticks, &cx->st)) != HC_OK) break;
+        stream_configure(cx->st, kServerDepth, true);
         // everything a chunk of max_chunk_hits needs, allocated once
         if ((rc = hc_stream_reserve(cx->st, c.max_chunk_hits)) != HC_OK) break;
         cx->state_bytes = stream_device_bytes(cx->st);
@@ -411,14 +500,16 @@ int hc_server_create(const hc_server_config* cfg, hc_server** out)
         s->account((int64_t)cx->hits_bytes);
         if ((e = hipHostMalloc((void**)&cx->tags_pin, sizeof(uint64_t) * kDrainTags, hipHostMallocDefault)) !=
                 hipSuccess ||
+            (e = hipHostMalloc((void**)&cx->status_pin, sizeof(int32_t) * kDrainTags, hipHostMallocDefault)) !=
+                hipSuccess ||
             (e = hipHostMalloc((void**)&cx->feats_pin, sizeof(hc_features) * kDrainFeats, hipHostMallocDefault)) !=
                 hipSuccess) {
             rc = set_device_error(e, "hipHostMalloc(server drain)");
             break;
         }
-        // two label blocks per stream: the chunk in flight and one awaiting finality
+        // label blocks per stream: the chunks in flight and one awaiting finality
         const size_t lc = block_class(4 * (size_t)c.max_chunk_hits);
-        for (int b = 0; b < 2 && rc == HC_OK; b++) {
+        for (int b = 0; b < kServerDepth + 1 && rc == HC_OK; b++) {
             void* p = nullptr;
             if ((e = hipMalloc(&p, lc)) != hipSuccess) {
                 rc = set_device_error(e, "hipMalloc(server labels)");
@@ -440,8 +531,10 @@ int hc_server_create(const hc_server_config* cfg, hc_server** out)
             if (cx->st) hc_stream_destroy(cx->st);
             (void)hipFree(cx->hits_dev);
             if (cx->tags_pin) (void)hipHostFree(cx->tags_pin);
+            if (cx->status_pin) (void)hipHostFree(cx->status_pin);
             if (cx->feats_pin) (void)hipHostFree(cx->feats_pin);
             if (cx->hs) (void)hipStreamDestroy(cx->hs);
+            if (cx->cs) (void)hipStreamDestroy(cx->cs);
             delete cx;
         }
         delete s;
@@ -566,13 +659,16 @@ void hc_server_destroy(hc_server* s)
         if (cx->th.joinable()) cx->th.join();
     for (StreamCtx* cx : s->streams) {
         (void)hipStreamSynchronize(cx->hs);
+        (void)hipStreamSynchronize(cx->cs);
         for (auto& kv : cx->pend)
             if (kv.second.labels_dev) (void)hipFree(kv.second.labels_dev);
         hc_stream_destroy(cx->st);
         (void)hipFree(cx->hits_dev);
         (void)hipHostFree(cx->tags_pin);
+        (void)hipHostFree(cx->status_pin);
         (void)hipHostFree(cx->feats_pin);
         (void)hipStreamDestroy(cx->hs);
+        (void)hipStreamDestroy(cx->cs);
         delete cx;
     }
     for (auto& kv : s->free_blocks)

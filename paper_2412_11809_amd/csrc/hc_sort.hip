@@ -51,10 +51,11 @@ hipError_t launch_init(const Work& w, hipStream_t s)
 template <int NT, int IPT>
 __global__ __launch_bounds__(NT, NT == 512 ? 6 : 4) void k_tile_sort(const hc_hit* __restrict__ hits, Work w)
 {
+    resolve_count(w);
     constexpr int T = NT * IPT;
     __shared__ uint32_t kr[T];  // ToA - tile minimum, by input position
     __shared__ uint16_t e0[T], e1[T];
-    __shared__ uint16_t cnt[16 * NT];
+    __shared__ uint16_t cnt[cnt_slots(NT)];
     __shared__ uint32_t wsum[NT / kWave];
     __shared__ uint64_t red[NT / kWave];
 
@@ -186,6 +187,7 @@ __device__ inline int merge_swz(int e) { return e ^ ((e >> 5) & 7); }
 template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
 {
+    resolve_count(w);
     constexpr int T = kSortThreads * IPT;
     static_assert(IPT % 4 == 0, "ranks are staged four at a time");
     __shared__ __align__(16) uint32_t nk[T];
@@ -438,6 +440,7 @@ struct ToaSortJob {
 
 __global__ __launch_bounds__(kFbThreads) void k_sort_fallback(const hc_hit* __restrict__ hits, Work w)
 {
+    resolve_count(w);
     if (!w.status->sort_fallback || w.status->err_range) return;  // the common case
     ToaSortJob job{hits, w};
     uint64_t* kb[2] = {w.fb_key[0], w.fb_key[1]};

@@ -89,15 +89,15 @@ def test_stream_rejects_disorder_and_continues(hc):
     st.push(hc.hits_to_device(a), la, 0)
     bad = b[:100].copy()
     bad["toa"][50] = 0  # far below the watermark
-    lbad = torch.empty(bad.size, dtype=torch.int32, device="cuda")
-    with pytest.raises(hc.HcError) as e:
-        st.push(hc.hits_to_device(bad), lbad, 99)
-    assert e.value.code == hc.HC_ERR_DISORDER
+    lbad = torch.full((bad.size,), -5, dtype=torch.int32, device="cuda")
+    st.push(hc.hits_to_device(bad), lbad, 99)  # rejected on the device; reported by poll
     lb = torch.empty(b.size, dtype=torch.int32, device="cuda")
     st.push(hc.hits_to_device(b), lb, 1)
     st.flush()
     done, _ = st.poll()
     assert sorted(done) == [0, 1]
+    assert st.rejected == {99: hc.HC_ERR_DISORDER}
+    assert (lbad.cpu().numpy() == -5).all()
     got = np.concatenate([la.cpu().numpy(), lb.cpu().numpy()])
     want, _ = oracle.cluster(hits, 256, 256, p["dt"])
     assert (got == want).all()
@@ -161,14 +161,15 @@ def test_stream_push_after_flush(hc):
     M = int(a["toa"].max())
     late = a[:50].copy()
     late["toa"] = np.uint64(M + dt)     # exactly dt after the last flushed hit
-    with pytest.raises(hc.HcError) as e:
-        _push_expect(hc, st, late, 9)
-    assert e.value.code == hc.HC_ERR_DISORDER
+    _push_expect(hc, st, late, 9)
+    st.wait()
+    done, _ = st.poll()
+    assert st.rejected == {9: hc.HC_ERR_DISORDER}
     c = a.copy()
     c["toa"] += np.uint64(M + dt + 1 - int(a["toa"].min()))
     lc = _push_expect(hc, st, c, 1)
     st.flush()
-    done, _ = st.poll()
+    done += st.poll()[0]
     assert sorted(done) == [0, 1]
     want, _ = oracle.cluster(np.concatenate([a, c]), 256, 256, dt)
     got = np.concatenate([la.cpu().numpy(), lc.cpu().numpy()])
