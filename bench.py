@@ -155,6 +155,30 @@ def cpu_baseline(hits, p, sample_hits=4_000_000, runs=5):
             "cpu_model": model, "host_cores_usable": usable, "host_cores_total": total}
 
 
+def cpu_lanes_baseline(hits, p, sample_hits=4_000_000, runs=3):
+    """The paper's CPU method (temporal splitting over lanes, border merge
+    cascade; cpu_lanes/) on the same sample as the oracle baseline, with one
+    lane per usable host core: median of `runs` runs."""
+    import cpu_lanes
+    cpu_lanes.load()
+    sample = hits[:sample_hits]
+    model, usable, total = host_cpu()
+    lanes = max(1, usable)
+    window = 64 * p["dt"] * 512  # windows of ~5 ms at 10 Mhit/s
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        cpu_lanes.cluster(sample, p["width"], p["height"], p["dt"], lanes, window)
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    med = ts[len(ts) // 2]
+    return {"value": round(sample.size / med / 1e6, 2), "unit": "Mhit/s", "cores": lanes, "kind": "cpu_lanes",
+            "sample": "the first %d hits of the 10M mixed workload, median of %d runs (%.3f s)" % (
+                sample.size, runs, med),
+            "note": "the paper's multi-lane CPU clustering (temporal splitting, per-window sweep, merge cascade); "
+                    "labels equal to the oracle's (tests/test_cpu_lanes.py)"}
+
+
 # The paper's own figure for this path, with the hardware and clock it states.
 PAPER_FIGURE = {
     "value": 300.0, "unit": "Mhit/s",
@@ -326,44 +350,141 @@ def bench_stream(hc, torch, dev, n_total=200_000_000, chunk=1_000_000):
     labels = torch.full((n_total,), -1, dtype=torch.int32, device=dev)
     st = hc.HcStream(p["dt"], tdis + 1, p["width"], p["height"], p["disorder"])
     st.reserve(chunk)
-    push_ms, open_hw, n_closed = [], 0, 0
-    done = []
+    open_hw, n_closed = 0, 0
+    t_push, lat_ms = {}, []
+
+    def take(tags, feats):
+        nonlocal n_closed
+        now = time.perf_counter()
+        for tg in tags:
+            lat_ms.append((now - t_push.pop(tg)) * 1e3)
+        n_closed += feats.size
+
     n_chunks = (n_total + chunk - 1) // chunk
+    t_start = None
     for c in range(n_chunks):
         a, b = c * chunk, min(n_total, (c + 1) * chunk)
-        t0 = time.perf_counter()
+        t_push[c] = time.perf_counter()
         st.hc_stream_push(d_hits[16 * a:16 * b], b - a, labels[a:b], c)
-        t1 = time.perf_counter()
-        if c > 0:
-            push_ms.append((t1 - t0) * 1e3)
+        if c == 0:  # warm-up push, excluded from the rate
+            st.wait()
+            t_start = time.perf_counter()
         open_hw = max(open_hw, st.open_hits())
-        tags, feats = st.poll()
-        done += tags
-        n_closed += feats.size
-    t0 = time.perf_counter()
+        take(*st.poll())
     st.flush()
     torch.cuda.synchronize(dev)
-    flush_ms = (time.perf_counter() - t0) * 1e3
-    tags, feats = st.poll()
-    done += tags
-    n_closed += feats.size
+    t_end = time.perf_counter()
+    take(*st.poll())
+    rejected = dict(st.rejected)
     st.close()
-    assert sorted(done) == list(range(n_chunks)), "not every chunk completed"
+    assert not rejected, "chunks rejected: %s" % rejected
+    assert not t_push, "not every chunk completed"
     assert int((labels < 0).sum().item()) == 0, "labels left unwritten"
     timed_hits = n_total - min(chunk, n_total)
-    total_ms = sum(push_ms) + flush_ms
-    a = np.array(push_ms)
+    lat = np.array(lat_ms[1:]) if len(lat_ms) > 1 else np.array(lat_ms)
     return {"workload": "Timepix4-shaped 448x512 sensor, %d hits at 300 Mhit/s (195.3125 ps ticks), blobs of "
                         "min(60, Geom(mean 9)) hits, local shuffle <= 16384, dt = 200 ns = 1024 ticks, pushed as "
                         "%d-hit chunks through one hc_stream (exact stitching on the device)" % (n_total, chunk),
             "n_hits": n_total, "chunks": n_chunks, "n_clusters": n_closed, "max_disorder_ticks": tdis + 1,
-            "mhits": round(timed_hits / (total_ms / 1e3) / 1e6, 1),
-            "push_ms": {"p50": round(float(np.quantile(a, 0.5)), 4), "p99": round(float(np.quantile(a, 0.99)), 4),
-                        "max": round(float(a.max()), 4)},
-            "flush_ms": round(flush_ms, 4), "open_hits_high_water": open_hw,
-            "generation_s": round(t_gen, 1),
-            "note": "device-resident: hits in HBM before the first push, labels written to HBM; rate = hits of "
-                    "pushes 2..%d over the summed push and flush times" % n_chunks}
+            "mhits": round(timed_hits / (t_end - t_start) / 1e6, 1),
+            "ms_total": round((t_end - t_start) * 1e3, 2),
+            "chunk_final_latency_ms": {"p50": round(float(np.quantile(lat, 0.5)), 3),
+                                       "p99": round(float(np.quantile(lat, 0.99)), 3)},
+            "open_hits_high_water": open_hw, "generation_s": round(t_gen, 1),
+            "note": "device-resident: hits in HBM before the first push, labels written to HBM, closed features "
+                    "drained to the host between pushes; rate = hits of pushes 2..%d over the wall time from "
+                    "the second push to the end of the flush; latency = push call to the chunk's labels all "
+                    "final (seen by the next poll)" % n_chunks}
+
+
+def bench_variants(hc, torch, dev, hits, p, reps=3):
+    """On the 10M mixed stream (resident in HBM): the Section 2 (iii)(b)
+    clustering (HC_FLAG_GLOBAL_TIME), and the per-cluster products of a
+    default clustering (boxes, a size filter, the kept hits grouped cluster by
+    cluster).  Mean of `reps` timed calls after one warm-up."""
+    import numpy as np
+    n = hits.size
+    W, H, dt, D = p["width"], p["height"], p["dt"], p["disorder"]
+    d = hc.hits_to_device(hits, dev)
+    stream = torch.cuda.current_stream(dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    feats = torch.empty((n, 64), dtype=torch.uint8, device=dev)
+    k = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize(dev)
+        return (time.perf_counter() - t0) / reps
+
+    ws_g = torch.empty(hc.hc_workspace_size(n, W, H, D, hc.HC_FLAG_GLOBAL_TIME), dtype=torch.uint8, device=dev)
+    t_g = timed(lambda: hc.hc_cluster(d, n, dt, labels, feats, k, W, H, D, ws_g, stream, hc.HC_FLAG_GLOBAL_TIME))
+    k_g = int(k.item())
+    del ws_g
+    ws = torch.empty(hc.hc_workspace_size(n, W, H, D), dtype=torch.uint8, device=dev)
+    t_a = timed(lambda: hc.hc_cluster(d, n, dt, labels, feats, k, W, H, D, ws, stream))
+    k_a = int(k.item())
+    boxes = torch.empty((n, 8), dtype=torch.uint8, device=dev)
+    keep = torch.empty(n, dtype=torch.int32, device=dev)
+    nkeep = torch.empty(1, dtype=torch.int32, device=dev)
+    grouped = torch.empty((n, 16), dtype=torch.uint8, device=dev)
+    gidx = torch.empty(n, dtype=torch.int32, device=dev)
+    start = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    pws = torch.empty(hc.hc_products_workspace_size(n), dtype=torch.uint8, device=dev)
+    flt = {"min_size": 3}
+    t_p = timed(lambda: hc.hc_cluster_products(d, n, labels, feats, k, keep, nkeep, boxes=boxes, grouped=grouped,
+                                               grouped_idx=gidx, row_start=start, filter=flt, workspace=pws,
+                                               stream=stream))
+    t_b = timed(lambda: hc.hc_cluster_products(d, n, labels, feats, k, keep, nkeep, boxes=boxes, workspace=pws,
+                                               stream=stream))
+    return {"workload": "the 10M mixed stream of the plain line, resident in HBM",
+            "global_time_iii_b": {"mhits": round(n / t_g / 1e6, 1), "ms": round(t_g * 1e3, 3), "n_clusters": k_g,
+                                  "n_clusters_iii_a": k_a,
+                                  "note": "Section 2 (iii)(b) clusters; the host waits for every refinement round"},
+            "products": {"ms_boxes_filter_grouping": round(t_p * 1e3, 3), "ms_boxes_filter": round(t_b * 1e3, 3),
+                         "kept_clusters": int(nkeep.item()), "filter": "size >= 3",
+                         "note": "after a plain clustering of the same hits; grouping = the kept clusters' hits "
+                                 "in cluster-major order (stable radix sort)"}}
+
+
+def bench_ingest(hc, torch, dev, hits, p, piece=65536, reps=3):
+    """The host ingest front end on the paper's clock: the hits start in a
+    host array (the populated host buffer) and are fed in arrival order in
+    pieces of `piece` hits; buffers of 2M hits are filled by the paper's
+    buffer filling, copied to the device (pinned, on their own stream),
+    clustered with exact stitching, and every label ends on the host at its
+    arrival index.  One untimed warm-up run, then the mean of `reps` runs."""
+    import numpy as np
+    import hitgen
+    n = hits.size
+    t = hitgen.realised_disorder_ticks(hits) + 1
+    b, bt = 2 << 20, 1 << 17
+    labels = torch.empty(n, dtype=torch.int32, pin_memory=True)
+    src = np.ascontiguousarray(hits)
+    times, st = [], None
+    for r in range(reps + 1):
+        ing = hc.HcIngest(labels, p["dt"], t, 64 * p["dt"], b, bt, p["width"], p["height"], p["disorder"])
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for a in range(0, n, piece):
+            ing.feed(src[a:a + piece])
+        ing.finish()
+        t1 = time.perf_counter()
+        st = ing.stats()
+        ing.close()
+        if r:
+            times.append(t1 - t0)
+    ok = int((labels.numpy() >= 0).all())
+    tm = sum(times) / len(times)
+    return {"workload": "the 10M mixed stream of the plain line, fed from host memory in arrival order, pieces of "
+                        "%d hits; buffers b = %d, b_t = %d, t_closing = 64 dt" % (piece, b, bt),
+            "mhits": round(n / tm / 1e6, 1), "ms": round(tm * 1e3, 2), "reps": reps,
+            "buffers_sent": st["buffers_sent"], "diverted_hits": st["diverted"], "labels_complete": bool(ok),
+            "note": "end-to-end: buffer filling on the host, host-to-device copy, clustering, labels back at their "
+                    "arrival indices; warm-up run excluded"}
 
 
 def _served_pools(n_streams, pool, seed):
@@ -592,6 +713,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served-form measurement")
     ap.add_argument("--served-seconds", type=float, default=10.0)
     ap.add_argument("--no-stream", action="store_true", help="skip the Timepix4 stream measurement")
+    ap.add_argument("--no-extras", action="store_true", help="skip the variant, products and ingest measurements")
     ap.add_argument("--stream-hits", type=int, default=200_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run one plain 1 GiB device copy (counter calibration)")
@@ -606,11 +728,12 @@ def main():
         traffic_from(args.traffic_from[0], args.traffic_from[1], args.traffic_command)
         return
     if args.only == "plain":
-        args.no_batch = args.no_served = args.no_stream = True
+        args.no_batch = args.no_served = args.no_stream = args.no_extras = True
     elif args.only in ("batch", "served", "stream"):
         args.steps, args.warmup = 1, 0
         args.no_batch, args.no_served = args.only != "batch", args.only != "served"
         args.no_stream = args.only != "stream"
+        args.no_extras = True
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
@@ -722,6 +845,12 @@ def main():
     if args.only is None:
         out["small"] = bench_small(hc, torch, dev)
         print("small done", file=sys.stderr, flush=True)
+    if not args.no_extras:
+        out["variants"] = bench_variants(hc, torch, dev, hits, p)
+        print("variants done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["ingest"] = bench_ingest(hc, torch, dev, hits, p)
+        print("ingest done", file=sys.stderr, flush=True)
     if not args.no_batch:
         del d_hits, ws, labels, feats
         torch.cuda.empty_cache()
@@ -737,6 +866,7 @@ def main():
         print("stream done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(hits, p)
+        out["cpu_lanes"] = cpu_lanes_baseline(hits, p)
     print(json.dumps(out), flush=True)
 
 
