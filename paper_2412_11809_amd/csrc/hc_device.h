@@ -17,11 +17,15 @@ constexpr int kWave = 64;
 // L2 each).  Give every XCD a contiguous range of tiles, so a tile and its
 // neighbours -- which read each other's data -- share an L2.
 __host__ __device__ inline int xcd_grid(int ntiles) { return 8 * ((ntiles + 7) / 8); }
+// The grid may be larger than xcd_grid(ntiles) (sized for a capacity while
+// the tile count is read on the device): work-groups past each XCD's range
+// get no tile, so no tile is taken twice.
 __device__ inline int xcd_tile(int ntiles, int xcd_map = 1)
 {
     const int b = blockIdx.x;
     if (!xcd_map) return b < ntiles ? b : -1;
     const int per = (ntiles + 7) / 8;
+    if ((b >> 3) >= per) return -1;
     const int t = (b & 7) * per + (b >> 3);
     return t < ntiles ? t : -1;
 }

@@ -113,6 +113,7 @@ __global__ void k_stream_commit(StreamDev* sd, ChunkRec* chunks, int slot, int32
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     StreamDev& d = *sd;
     d.n_closed = 0;
+    d.n_clusters = 0;  // set by the clustering, which a push with nothing to cluster skips
     if (flush) {
         d.verdict = HC_OK;
         d.n_all = d.n_open;
@@ -714,40 +715,46 @@ static int enqueue_push(hc_stream* st, const hc_hit* hits, const int32_t* in_ids
                            st->tdis, st->dt, flush);
     }
     if ((e = hipGetLastError()) != hipSuccess) return give_back(set_device_error(e, "stream append"));
-    Work w;
-    plan_workspace(n_all_bound, st->W, st->H, sort_hint(st), &w, (char*)st->ws);
-    w.dt = st->dt;
-    w.link_mode = st->link_mode;
-    w.n_dev = &st->sd->n_all;
-    if ((rc = enqueue_cluster(st->buf[st->cur], w, st->lab, st->feats, &st->sd->n_clusters, st->s)) != HC_OK)
-        return give_back(rc);
-    const int nb_all = (int)((n_all_bound + 255) / 256);
-    const int nb = (int)((n_all_bound + kCmpBlock - 1) / kCmpBlock);
     const int nxt = 1 - st->cur;
-    {
-        TimedLaunch tl("stream_close", st->s);  // the closing and compaction kernels, together
-        const int32_t* cmin = st->id_mode == 1 ? st->cmin : nullptr;
-        if (cmin) {
-            hipLaunchKernelGGL(k_stream_idmin_init, dim3(nb_all), dim3(256), 0, st->s, st->cmin, st->sd);
-            hipLaunchKernelGGL(k_stream_idmin, dim3(nb_all), dim3(256), 0, st->s, st->lab, w, st->ids[st->cur],
-                               st->sd, st->cmin);
-        }
-        hipLaunchKernelGGL(k_stream_close_hits, dim3(nb_all), dim3(256), 0, st->s, st->lab, w, st->gidx[st->cur],
-                           st->cslot[st->cur], cmin, st->chunks_dev, st->sd, st->dt, flush, st->flags);
-        hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all, st->counts);
-        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, &st->sd->n_all, &st->sd->n_open);
-        hipLaunchKernelGGL(k_scatter_open, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all,
-                           st->counts, st->buf[st->cur], st->gidx[st->cur], st->cslot[st->cur], st->ids[st->cur],
-                           st->buf[nxt], st->gidx[nxt], st->cslot[nxt], st->ids[nxt]);
-        hipLaunchKernelGGL(k_stream_close_feats, dim3(nb_all), dim3(256), 0, st->s, st->feats, st->sd, st->dt, flush,
-                           st->flags);
-        hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all, st->counts);
-        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, &st->sd->n_all, &st->sd->n_closed);
-        hipLaunchKernelGGL(k_scatter_feats, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, st->sd, st->counts,
-                           st->feats, st->gidx[st->cur], cmin, st->queue, st->q_cap);
+    if (n_all_bound == 0) {
+        // a flush with no open hit: nothing to cluster, close or compact
         hipLaunchKernelGGL(k_stream_end, dim3(1), dim3(64), 0, st->s, st->sd);
+        if ((e = hipGetLastError()) != hipSuccess) return give_back(set_device_error(e, "stream close"));
+    } else {
+        Work w;
+        plan_workspace(n_all_bound, st->W, st->H, sort_hint(st), &w, (char*)st->ws);
+        w.dt = st->dt;
+        w.link_mode = st->link_mode;
+        w.n_dev = &st->sd->n_all;
+        if ((rc = enqueue_cluster(st->buf[st->cur], w, st->lab, st->feats, &st->sd->n_clusters, st->s)) != HC_OK)
+            return give_back(rc);
+        const int nb_all = (int)((n_all_bound + 255) / 256);
+        const int nb = (int)((n_all_bound + kCmpBlock - 1) / kCmpBlock);
+        {
+            TimedLaunch tl("stream_close", st->s);  // the closing and compaction kernels, together
+            const int32_t* cmin = st->id_mode == 1 ? st->cmin : nullptr;
+            if (cmin) {
+                hipLaunchKernelGGL(k_stream_idmin_init, dim3(nb_all), dim3(256), 0, st->s, st->cmin, st->sd);
+                hipLaunchKernelGGL(k_stream_idmin, dim3(nb_all), dim3(256), 0, st->s, st->lab, w, st->ids[st->cur],
+                                   st->sd, st->cmin);
+            }
+            hipLaunchKernelGGL(k_stream_close_hits, dim3(nb_all), dim3(256), 0, st->s, st->lab, w, st->gidx[st->cur],
+                               st->cslot[st->cur], cmin, st->chunks_dev, st->sd, st->dt, flush, st->flags);
+            hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all, st->counts);
+            hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, &st->sd->n_all, &st->sd->n_open);
+            hipLaunchKernelGGL(k_scatter_open, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all,
+                               st->counts, st->buf[st->cur], st->gidx[st->cur], st->cslot[st->cur], st->ids[st->cur],
+                               st->buf[nxt], st->gidx[nxt], st->cslot[nxt], st->ids[nxt]);
+            hipLaunchKernelGGL(k_stream_close_feats, dim3(nb_all), dim3(256), 0, st->s, st->feats, st->sd, st->dt, flush,
+                               st->flags);
+            hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all, st->counts);
+            hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, &st->sd->n_all, &st->sd->n_closed);
+            hipLaunchKernelGGL(k_scatter_feats, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, st->sd, st->counts,
+                               st->feats, st->gidx[st->cur], cmin, st->queue, st->q_cap);
+            hipLaunchKernelGGL(k_stream_end, dim3(1), dim3(64), 0, st->s, st->sd);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return give_back(set_device_error(e, "stream close"));
     }
-    if ((e = hipGetLastError()) != hipSuccess) return give_back(set_device_error(e, "stream close"));
     if ((e = hipMemcpyAsync(r->mirror, st->sd, sizeof(StreamDev), hipMemcpyDeviceToHost, st->s)) != hipSuccess ||
         (e = hipMemcpyAsync(r->mirror + sizeof(StreamDev), st->chunks_dev, sizeof(ChunkRec) * st->chunk_cap,
                             hipMemcpyDeviceToHost, st->s)) != hipSuccess ||
