@@ -132,6 +132,26 @@ size_t hc_workspace_size(const hc_opts* opts, int64_t n);
 int hc_cluster(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels,
                hc_features* features, int32_t* n_clusters, const hc_opts* opts);
 
+/* hc_cluster without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as hc_cluster; the
+ * workspace is a fixed scratch array of HC_NOALLOC_SCRATCH_BYTES in device
+ * memory, which each GPU the library runs on holds until the process ends.
+ * opts->workspace must be NULL and HC_FLAG_GLOBAL_TIME is rejected
+ * (HC_ERR_ARG).  A call whose workspace (hc_workspace_size for the same n and
+ * options) exceeds the array returns HC_ERR_WORKSPACE, before any device
+ * work: about 1.3 million hits fit.  Every call on one GPU shares that GPU's
+ * array, whatever stream it runs on, so calls that overlap in time on one GPU
+ * race and return wrong results: the caller serialises them (one stream, or
+ * an event between them).  The first call on a device looks the array's
+ * address up; later calls allocate nothing, neither device nor pinned host
+ * memory. */
+#define HC_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int hc_cluster_noalloc(const hc_hit* hits, int32_t n, uint64_t dt, int32_t* labels,
+                       hc_features* features, int32_t* n_clusters, const hc_opts* opts);
+/* Size of that scratch array in bytes (HC_NOALLOC_SCRATCH_BYTES). */
+size_t hc_noalloc_scratch_bytes(void);
+
 /* ---- Per-cluster products ------------------------------------------------
  *
  * Computed on the device from what hc_cluster wrote (labels, feature table,

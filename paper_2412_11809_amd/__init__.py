@@ -65,6 +65,10 @@ def load_library(path=LIB_PATH):
     lib.hc_cluster.restype = ctypes.c_int
     lib.hc_cluster.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Opts)]
+    lib.hc_cluster_noalloc.restype = ctypes.c_int
+    lib.hc_cluster_noalloc.argtypes = lib.hc_cluster.argtypes
+    lib.hc_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    lib.hc_noalloc_scratch_bytes.argtypes = []
     lib.hc_last_error.restype = ctypes.c_char_p
     lib.hc_version.restype = ctypes.c_char_p
     lib.hc_timing_enable.argtypes = [ctypes.c_int]
@@ -127,6 +131,23 @@ def hc_cluster(hits, n, dt, labels, features, n_clusters, width=256, height=256,
     rc = load_library().hc_cluster(_ptr(hits), int(n), int(dt), _ptr(labels), _ptr(features),
                                    _ptr(n_clusters), ctypes.byref(o))
     _check(rc)
+
+
+def hc_cluster_noalloc(hits, n, dt, labels, features, n_clusters, width=256, height=256, disorder_hint=0,
+                       stream=None, flags=0):
+    """hc_cluster on the library's fixed scratch array (no workspace argument,
+    nothing allocated); same tensors as hc_cluster."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(hits.device)
+    o = _opts(width, height, disorder_hint, None, stream, flags)
+    rc = load_library().hc_cluster_noalloc(_ptr(hits), int(n), int(dt), _ptr(labels), _ptr(features),
+                                           _ptr(n_clusters), ctypes.byref(o))
+    _check(rc)
+
+
+def hc_noalloc_scratch_bytes():
+    return int(load_library().hc_noalloc_scratch_bytes())
 
 
 def hits_to_device(hits, device="cuda"):

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhc.so")
 SOURCES = ["hc_api.cpp", "hc_sort.hip", "hc_link.hip", "hc_feat.hip", "hc_stream.hip", "hc_batch.hip", "hc_server.hip",
-           "hc_products.hip", "hc_global.hip", "hc_ingest.cpp"]
+           "hc_products.hip", "hc_global.hip", "hc_ingest.cpp", "hc_noalloc.hip"]
 ARCH = "gfx950"
 
 
