@@ -450,6 +450,49 @@ def bench_variants(hc, torch, dev, hits, p, reps=3):
                                  "in cluster-major order (stable radix sort)"}}
 
 
+def bench_showers(hc, torch, dev, n=10_000_000, reps=5):
+    """Plain calls on streams with dense showers (hitgen.shower_stream: 30 %
+    of the hits in showers of U{lo..hi} hits within 100 ns), where many link
+    tiles have more than 1024 hits within dt before them: the moderate case
+    is handled by the wide second level tile by tile, the deep one partly by
+    the all-hits fallback.  Mean of `reps` timed calls after one warm-up, and
+    the link kernels' share from HIP events in a separate call."""
+    import hitgen
+    out = {"workload": "256x256 sensor, %d hits at ~10 Mhit/s (the mixed stream plus dense showers: 30 %% of "
+                       "the hits in showers within 100 ns), local shuffle <= 4096, dt = 128 ticks" % n}
+    for name, sizes in (("showers_1500_6000", (1500, 6000)), ("showers_9000_14000", (9000, 14000))):
+        hits = hitgen.shower_stream(n, hitgen.BASE_SEED + 60 + sizes[0], shower_hits=sizes)
+        d = hc.hits_to_device(hits, dev)
+        stream = torch.cuda.current_stream(dev)
+        ws = torch.empty(hc.hc_workspace_size(n, 256, 256, 4096), dtype=torch.uint8, device=dev)
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+        feats = torch.empty((n, 64), dtype=torch.uint8, device=dev)
+        k = torch.empty(1, dtype=torch.int32, device=dev)
+
+        def call():
+            hc.hc_cluster(d, n, 128, labels, feats, k, 256, 256, 4096, ws, stream)
+
+        call()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize(dev)
+        tm = (time.perf_counter() - t0) / reps
+        hc.hc_timing_reset()
+        hc.hc_timing_enable(True)
+        call()
+        torch.cuda.synchronize(dev)
+        hc.hc_timing_enable(False)
+        kt = hc.hc_timing_read()
+        out[name] = {"mhits": round(n / tm / 1e6, 1), "ms": round(tm * 1e3, 3), "n_clusters": int(k.item()),
+                     "link_ms": {kn: round(kt[kn][1], 4) for kn in ("link", "link_wide", "link_fallback")
+                                 if kn in kt}}
+        del d, ws, labels, feats
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_ingest(hc, torch, dev, hits, p, piece=65536, reps=3):
     """The host ingest front end on the paper's clock: the hits start in a
     host array (the populated host buffer) and are fed in arrival order in
@@ -851,6 +894,9 @@ def main():
         torch.cuda.empty_cache()
         out["ingest"] = bench_ingest(hc, torch, dev, hits, p)
         print("ingest done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["showers"] = bench_showers(hc, torch, dev)
+        print("showers done", file=sys.stderr, flush=True)
     if not args.no_batch:
         del d_hits, ws, labels, feats
         torch.cuda.empty_cache()

@@ -202,6 +202,36 @@ def mixed_stream(n, seed, width=256, height=256, span_ticks=640_000_000, disorde
     return _assemble(rng, x, y, t, n, disorder)
 
 
+def shower_stream(n, seed, width=256, height=256, span_ticks=None, disorder=4096,
+                  shower_hits=(1500, 6000), shower_share=0.3, radius=40, jitter=64):
+    """The mixed stream (``mixed_stream``) with dense showers added: about
+    ``shower_share`` of the n hits arrive in showers of U{shower_hits} hits
+    each within ``jitter`` ticks, a random walk reflected inside the square
+    |dx|,|dy| <= radius around a uniform origin.  Every later hit of a shower
+    has hundreds to thousands of earlier hits within dt before it."""
+    rng = np.random.default_rng(seed)
+    if n == 0:
+        return np.empty(0, dtype=HIT_DTYPE)
+    if span_ticks is None:
+        span_ticks = int(round(n / 10e6 * 1e9 / TPX3_TICK_NS))
+    lo, hi = shower_hits
+    sizes = []
+    want = int(n * shower_share)
+    while sum(sizes) < want:
+        sizes.append(int(rng.integers(lo, hi + 1)))
+    sizes = np.array(sizes, dtype=np.int64)
+    t0 = rng.integers(0, max(1, span_ticks), sizes.size).astype(np.uint64)
+    sx, sy, st, _ = _blobs(rng, sizes, width, height, t0, jitter, radius=radius)
+    base = mixed_stream(max(0, n - int(sizes.sum())), int(rng.integers(1 << 62)), width, height,
+                        span_ticks=span_ticks, disorder=0, blob_jitter=jitter,
+                        track_step=max(1, jitter // 2), heavy_radius=15)
+    x = np.concatenate([base["x"].astype(np.int64), sx])
+    y = np.concatenate([base["y"].astype(np.int64), sy])
+    t = np.concatenate([base["toa"], st])
+    p = rng.permutation(x.size)
+    return _assemble(rng, x[p], y[p], t[p], n, disorder)
+
+
 # ---------------------------------------------------------------------------
 # the named workloads
 

@@ -98,6 +98,7 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.edges = (int2*)take(sizeof(int2) * (size_t)x.edge_cap);
     x.tile_nedge = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.overflow_tiles = (int32_t*)take(4 * (size_t)x.n_link_tiles);
+    x.deep_tiles = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.slots = (SlotRec*)take(sizeof(SlotRec) * N);
     x.carries = (SlotRec*)take(sizeof(SlotRec) * (size_t)x.carry_cap);
     x.tile_ncarry = (int32_t*)take(4 * (size_t)x.n_feat_tiles);
@@ -278,6 +279,7 @@ int enqueue_cluster(const hc_hit* hits, const Work& w, int32_t* labels, hc_featu
     HC_LAUNCH(launch_sort_fallback(hits, w, s), "sort_fallback");
     HC_LAUNCH(launch_link_halo(w, s), "link_halo");
     HC_LAUNCH(launch_link(w, s), "link");
+    HC_LAUNCH(launch_link_wide(w, s), "link_wide");
     HC_LAUNCH(launch_link_fallback(w, s), "link_fallback");
     HC_LAUNCH(launch_union_edges(w, s), "union_edges");
     HC_LAUNCH(launch_flatten(w, labels, s), "flatten");

@@ -198,19 +198,11 @@ __device__ inline uint64_t block_max_u64(uint64_t v, uint64_t* red)
 }
 
 // ------------------------------------------------------ LDS radix sort
-// Digit counters of the LDS radix sorts: 16 per thread, in (digit, thread)
-// order, with one spare 16-bit slot after every 16 of them.  The scan reads
-// each thread's 16 consecutive counters; unpadded, the runs of lanes four
-// apart would start in the same LDS bank (an 8-way conflict on every read
-// and write of the scan), padded they start 17 slots apart.
-__host__ __device__ constexpr int cnt_slots(int nt) { return 16 * nt + nt; }
-__device__ inline int cnt_at(int p) { return p + (p >> 4); }
-
 // Stable LSD sort of NT*IPT (u32 key, u16 value) pairs held in LDS buffers
 // (k0, v0) by the low `bits` bits of the key, four bits per pass.  Thread t
 // owns positions [t*IPT, (t+1)*IPT).  (k1, v1) is the second buffer; cnt
 // holds 16*NT u16 counters and wsum NT/64 words.  Returns which buffer
-// (0 or 1) holds the result.  cnt holds cnt_slots(NT) entries.
+// (0 or 1) holds the result.
 template <int NT, int IPT>
 __device__ inline int block_radix_sort(uint32_t* k0, uint16_t* v0, uint32_t* k1, uint16_t* v1,
                                        uint16_t* cnt, uint32_t* wsum, int bits)
@@ -243,8 +235,7 @@ __device__ inline int block_radix_sort(uint32_t* k0, uint16_t* v0, uint32_t* k1,
             c[3] += r == 3 ? inc : 0u;
         }
 #pragma unroll
-        for (int dd = 0; dd < 16; dd++)
-            cnt[cnt_at(dd * NT + t)] = (uint16_t)((c[dd >> 2] >> ((dd & 3) * 8)) & 0xFFu);
+        for (int dd = 0; dd < 16; dd++) cnt[dd * NT + t] = (uint16_t)((c[dd >> 2] >> ((dd & 3) * 8)) & 0xFFu);
         __syncthreads();
         // exclusive scan over cnt in (digit, thread) order; thread t owns 16
         // consecutive counters
@@ -252,19 +243,19 @@ __device__ inline int block_radix_sort(uint32_t* k0, uint16_t* v0, uint32_t* k1,
         uint32_t s = 0;
 #pragma unroll
         for (int i = 0; i < 16; i++) {
-            loc[i] = cnt[cnt_at(t * 16 + i)];
+            loc[i] = cnt[t * 16 + i];
             s += loc[i];
         }
         uint32_t run = block_exclusive_scan<NT>(s, wsum, nullptr);
 #pragma unroll
         for (int i = 0; i < 16; i++) {
-            cnt[cnt_at(t * 16 + i)] = (uint16_t)run;
+            cnt[t * 16 + i] = (uint16_t)run;
             run += loc[i];
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
-            const uint32_t dst = (uint32_t)cnt[cnt_at(d[j] * NT + t)] + lr[j];
+            const uint32_t dst = (uint32_t)cnt[d[j] * NT + t] + lr[j];
             ko[dst] = k[j];
             vo[dst] = v[j];
         }
@@ -278,8 +269,8 @@ __device__ inline int block_radix_sort(uint32_t* k0, uint16_t* v0, uint32_t* k1,
 // stay in place in LDS and are read through the index), the low `bits` bits,
 // four bits per pass.  Half the LDS of sorting (key, index) pairs, which lets
 // more work-groups share a CU.  Thread t owns positions [t*IPT, (t+1)*IPT);
-// e1 is the second buffer, cnt holds cnt_slots(NT) u16 counters and wsum
-// NT/64 words.  Returns which buffer (0 or 1) holds the sorted indices.
+// e1 is the second buffer, cnt holds 16*NT u16 counters and wsum NT/64
+// words.  Returns which buffer (0 or 1) holds the sorted indices.
 template <int NT, int IPT>
 __device__ inline int block_radix_sort_index(const uint32_t* key, uint16_t* e0, uint16_t* e1, uint16_t* cnt,
                                              uint32_t* wsum, int bits)
@@ -309,24 +300,23 @@ __device__ inline int block_radix_sort_index(const uint32_t* key, uint16_t* e0, 
             c[3] += r == 3 ? inc : 0u;
         }
 #pragma unroll
-        for (int dd = 0; dd < 16; dd++)
-            cnt[cnt_at(dd * NT + t)] = (uint16_t)((c[dd >> 2] >> ((dd & 3) * 8)) & 0xFFu);
+        for (int dd = 0; dd < 16; dd++) cnt[dd * NT + t] = (uint16_t)((c[dd >> 2] >> ((dd & 3) * 8)) & 0xFFu);
         __syncthreads();
         // exclusive scan over cnt in (digit, thread) order; thread t owns 16
         // consecutive counters (read twice rather than held in registers)
         uint32_t sum = 0;
 #pragma unroll
-        for (int i = 0; i < 16; i++) sum += cnt[cnt_at(t * 16 + i)];
+        for (int i = 0; i < 16; i++) sum += cnt[t * 16 + i];
         uint32_t run = block_exclusive_scan<NT>(sum, wsum, nullptr);
 #pragma unroll
         for (int i = 0; i < 16; i++) {
-            const uint32_t v = cnt[cnt_at(t * 16 + i)];
-            cnt[cnt_at(t * 16 + i)] = (uint16_t)run;
+            const uint32_t v = cnt[t * 16 + i];
+            cnt[t * 16 + i] = (uint16_t)run;
             run += v;
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < IPT; j++) eo[(uint32_t)cnt[cnt_at((dl[j] & 15u) * NT + t)] + (dl[j] >> 4)] = e[j];
+        for (int j = 0; j < IPT; j++) eo[(uint32_t)cnt[(dl[j] & 15u) * NT + t] + (dl[j] >> 4)] = e[j];
         __syncthreads();
         cur ^= 1;
     }

@@ -72,7 +72,8 @@ struct Status {
     int32_t err_range;      // a hit lies outside the sensor
     int32_t sort_fallback;  // tile sort/merge could not order the input
     int32_t n_overflow;     // link tiles whose halo did not fit
-    int32_t unused_[3];
+    int32_t n_deep;         // of those, tiles whose halo did not fit the wide kernel either
+    int32_t unused_[2];
     int32_t err_internal;   // an index derived from device data was out of range
     int32_t err_span;       // batch sort fallback: a chunk's ToA span too large
     int32_t pad_[8];
@@ -142,6 +143,7 @@ struct Work {
     int2* edges;
     int32_t* tile_nedge;     // cross-tile edges of every link tile
     int32_t* overflow_tiles;
+    int32_t* deep_tiles;     // overflow tiles that go on to the all-hits fallback
     SlotRec* slots;
     SlotRec* carries;
     int32_t* tile_ncarry;    // carries of every feature tile
@@ -169,6 +171,7 @@ hipError_t launch_tile_merge(const Work& w, hipStream_t s);
 hipError_t launch_link_halo(const Work& w, hipStream_t s);
 hipError_t launch_sort_fallback(const hc_hit* hits, const Work& w, hipStream_t s);
 hipError_t launch_link(const Work& w, hipStream_t s);
+hipError_t launch_link_wide(const Work& w, hipStream_t s);
 hipError_t launch_link_fallback(const Work& w, hipStream_t s);
 hipError_t launch_union_edges(const Work& w, hipStream_t s);
 hipError_t launch_flatten(const Work& w, int32_t* labels, hipStream_t s);

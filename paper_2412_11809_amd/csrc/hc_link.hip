@@ -21,8 +21,10 @@
 //     array, and halo hits joined by the tile are queued as cross-tile edges.
 // Sensors too large for the bitmap (or a caller's flag) use k_link_window,
 // which scans each hit's dt window instead.  A tile whose halo does not fit
-// (or whose ToA span exceeds 32 bits) is handled by k_link_fallback: a
-// pixel-sorted copy of all hits plus binary searches.  k_union_edges applies
+// goes to k_link_wide, the same index over the tile and a halo of up to 7168
+// hits in one large work-group; a tile whose halo exceeds even that (or whose
+// ToA span exceeds 32 bits) is handled by k_link_fallback: a pixel-sorted copy
+// of all hits plus binary searches.  k_union_edges applies
 // the queued cross-tile edges with atomic compare-and-swap, and k_flatten
 // writes labels[i] = root(i).
 #include "hc_device.h"
@@ -326,6 +328,16 @@ __device__ inline uint32_t pix_rank(uint32_t p, const uint64_t* bm, const uint16
 {
     const uint32_t wd = p >> 6;
     return wpre[wd] + (uint32_t)__popcll(bm[wd] & ((1ull << (p & 63u)) - 1ull));
+}
+
+// Count one slot at its pixel: its rank, and its place among the slots of
+// that pixel (the 16-bit count it saw; two counters share a word, and counts
+// stay below 2^16, so no carry crosses halves).
+__device__ inline uint32_t pix_count(uint32_t p, const uint64_t* bm, const uint16_t* wpre, uint32_t* pcount)
+{
+    const uint32_t r = pix_rank(p, bm, wpre);
+    const uint32_t half = 16u * (r & 1u);
+    return r | (((atomicAdd(&pcount[r >> 1], 1u << half) >> half) & 0xFFFFu) << 16);
 }
 
 // One work-group per tile of kLinkTile sorted hits (+ halo), all in LDS.
@@ -634,6 +646,254 @@ hipError_t launch_link(const Work& w, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------ wide tiles (halo above kLinkHaloCap)
+// Second level for the tiles whose halo did not fit k_link (more than
+// kLinkHaloCap hits within dt before the tile, as inside a dense shower):
+// one 1024-thread work-group per tile builds the same pixel index (bitmap,
+// prefixes, CSR of (ToA, slot, x mod 4) runs) over the tile and a halo of up
+// to kWideCap - kLinkTile hits, searches the three neighbour rows of every
+// tile hit, joins the candidates in an LDS forest as k_link does, and then
+// joins every slot to the smallest input index of its local tree through the
+// global union-find (k_link left the tile's hits as their own roots).  Every
+// change to the global forest in this launch is a compare-and-swap union, so
+// tiles processed together never undo each other's joins, and each targets
+// its own slot's root rather than one shared root.  Work is proportional to
+// the tile and its halo.
+// Tiles whose halo exceeds even this, or whose ToA span does not fit 32 bits,
+// or whose sensor has no room for the bitmap, go on to k_link_fallback.
+constexpr int kWideThreads = 1024;
+constexpr int kWideCap = 8192;
+constexpr int kWidePer = kWideCap / kWideThreads;
+
+__global__ __launch_bounds__(kWideThreads) void k_link_wide(Work w, int bm64)
+{
+    resolve_count(w);
+    if (!w.status->n_overflow || w.status->err_range) return;  // the common case
+    __shared__ uint2 csr[kWideCap];            // CSR of (ToA - base, slot | (x & 3) << 16); then minima
+    __shared__ int32_t l_par[kWideCap];
+    __shared__ uint16_t pstart[kWideCap + 2];
+    __shared__ uint32_t wsum[kWideThreads / kWave];
+    __shared__ int64_t s_h0;
+    extern __shared__ uint64_t dyn64[];
+    uint64_t* bm = dyn64;
+    uint32_t* bm32 = reinterpret_cast<uint32_t*>(dyn64);
+    uint16_t* wpre = reinterpret_cast<uint16_t*>(dyn64 + bm64);
+    uint32_t* pcount = reinterpret_cast<uint32_t*>(pstart);
+    int32_t* minidx = reinterpret_cast<int32_t*>(csr);
+    const int t = threadIdx.x;
+    const int n_over = w.status->n_overflow;
+    const uint32_t W = w.width;
+    const int H = (int)w.height;
+    for (int q = blockIdx.x; q < n_over; q += gridDim.x) {
+        const int tile = w.overflow_tiles[q];
+        const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
+        const int64_t p0 = tr.start;
+        const int64_t p1 = tr.start + tr.count;
+        const uint64_t dt = seg_dt(w, tr.seg);
+        if (t == 0) {
+            const uint64_t lo = sat_sub_u64(w.s_toa[p0], dt);
+            const int64_t lim = p0 - (kWideCap - kLinkTile) > tr.seg_start ? p0 - (kWideCap - kLinkTile) : tr.seg_start;
+            int64_t a = lim, b = p0;
+            while (a < b) {
+                const int64_t m = (a + b) >> 1;
+                if (w.s_toa[m] < lo) a = m + 1; else b = m;
+            }
+            bool deep = bm64 == 0 || (a == lim && lim > tr.seg_start && w.s_toa[lim - 1] >= lo);
+            deep |= (w.s_toa[p1 - 1] - w.s_toa[a]) > 0xFFFFFFFFull;
+            if (deep) w.deep_tiles[atomicAdd(&w.status->n_deep, 1)] = tile;
+            s_h0 = deep ? -1 : a;
+        }
+        for (int i = t; i < bm64; i += kWideThreads) bm[i] = 0ull;
+        for (int i = t; i < (kWideCap + 2) / 2; i += kWideThreads) pcount[i] = 0u;
+        __syncthreads();
+        const int64_t h0 = s_h0;
+        if (h0 >= 0) {
+            const int L = (int)(p1 - h0);
+            const int hl = (int)(p0 - h0);
+            const uint64_t tbase = w.s_toa[h0];
+            // this thread's slots t + k * kWideThreads (tile and halo alike)
+            uint32_t rel[kWidePer], sxy[kWidePer], sp[kWidePer], srp[kWidePer];
+            int32_t sid[kWidePer];
+#pragma unroll
+            for (int k = 0; k < kWidePer; k++) {
+                const int a = t + k * kWideThreads;
+                sid[k] = -1;
+                if (a < L) {
+                    rel[k] = (uint32_t)(w.s_toa[h0 + a] - tbase);
+                    sxy[k] = w.s_xy[h0 + a];
+                    sid[k] = w.s_idx[h0 + a];
+                    if (sid[k] < 0 || sid[k] >= w.n) {
+                        atomicOr(&w.status->err_internal, 1);
+                        sid[k] = 0;
+                    }
+                    sp[k] = (sxy[k] >> 16) * W + (sxy[k] & 0xFFFFu);
+                    atomicOr(&bm32[sp[k] >> 5], 1u << (sp[k] & 31u));
+                }
+            }
+            __syncthreads();
+            {
+                const int per = (bm64 + kWideThreads - 1) / kWideThreads;
+                const int w0 = t * per;
+                uint32_t c = 0;
+                for (int k = 0; k < per; k++)
+                    if (w0 + k < bm64) c += (uint32_t)__popcll(bm[w0 + k]);
+                uint32_t run = block_exclusive_scan<kWideThreads>(c, wsum, nullptr);
+                for (int k = 0; k < per; k++)
+                    if (w0 + k < bm64) {
+                        wpre[w0 + k] = (uint16_t)run;
+                        run += (uint32_t)__popcll(bm[w0 + k]);
+                    }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kWidePer; k++)
+                if (t + k * kWideThreads < L) srp[k] = pix_count(sp[k], bm, wpre, pcount);
+            __syncthreads();
+            {
+                uint32_t c[kWidePer];
+                uint32_t sum = 0;
+#pragma unroll
+                for (int k = 0; k < kWidePer; k++) {
+                    c[k] = pstart[t * kWidePer + k];
+                    sum += c[k];
+                }
+                uint32_t run = block_exclusive_scan<kWideThreads>(sum, wsum, nullptr);
+#pragma unroll
+                for (int k = 0; k < kWidePer; k++) {
+                    pstart[t * kWidePer + k] = (uint16_t)run;
+                    run += c[k];
+                }
+                if (t == kWideThreads - 1) pstart[kWideCap] = (uint16_t)run;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kWidePer; k++) {
+                const int a = t + k * kWideThreads;
+                if (a < L) {
+                    csr[pstart[srp[k] & 0xFFFFu] + (srp[k] >> 16)] =
+                        make_uint2(rel[k], (uint32_t)a | ((sxy[k] & 3u) << 16));
+                    l_par[a] = a;
+                }
+            }
+            __syncthreads();
+            // ---- candidates of tile hit t (slot hl + t): the first earlier
+            // entry within dt at each of its 9 pixels
+            const uint32_t dt32 = dt < 0xFFFFFFFFull ? (uint32_t)dt : 0xFFFFFFFFu;
+            int cand[9];
+#pragma unroll
+            for (int k = 0; k < 9; k++) cand[k] = -1;
+            const int i = hl + t;
+            if (t < tr.count) {
+                const uint32_t xy = w.s_xy[p0 + t];
+                const uint32_t ti = (uint32_t)(w.s_toa[p0 + t] - tbase);
+                const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
+                const int xlo = x > 0 ? x - 1 : 0;
+                const int xhi = x + 1 < (int)W ? x + 1 : (int)W - 1;
+                const uint32_t rowmask = (1u << (xhi - xlo + 1)) - 1u;
+#pragma unroll
+                for (int rr = 0; rr < 3; rr++) {
+                    const int qy = y - 1 + rr;
+                    if (qy < 0 || qy >= H) continue;
+                    const uint32_t pa = (uint32_t)qy * W + (uint32_t)xlo;
+                    const uint32_t wa = pa >> 6, sh = pa & 63u;
+                    const uint64_t b0 = bm[wa];
+                    uint64_t bits = b0 >> sh;
+                    if (sh > 61u && (int)wa + 1 < bm64) bits |= bm[wa + 1] << (64u - sh);
+                    uint32_t need = (uint32_t)bits & rowmask;
+                    if (!need) continue;
+                    const int rk0 = (int)(wpre[wa] + (uint32_t)__popcll(b0 & ((1ull << sh) - 1ull)));
+                    const int s0 = pstart[rk0];
+                    const int s1 = pstart[rk0 + __popc(need)];
+                    for (int j = s0; j < s1 && need; j++) {
+                        const uint2 e = csr[j];
+                        const int u = (int)(e.y & 0xFFFFu);
+                        const uint32_t dx = ((e.y >> 16) - (uint32_t)xlo) & 3u;
+                        if (((need >> dx) & 1u) && u < i && ti - e.x <= dt32) {
+                            need &= ~(1u << dx);
+#pragma unroll
+                            for (int c = 0; c < 3; c++)
+                                if ((uint32_t)c == dx) cand[rr * 3 + c] = u;
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // the CSR is read no more
+            // ---- the joins in the LDS forest (roots are the earliest slots):
+            // hang under the smallest candidate, then hook roots in rounds
+            if (t < tr.count) {
+                int mn = i;
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    if (cand[k] >= 0 && cand[k] < mn) mn = cand[k];
+                l_par[i] = mn;
+            }
+            __syncthreads();
+            while (true) {
+                for (int x = t; x < L; x += kWideThreads) {
+                    int p = l_par[x];
+                    while (true) {
+                        const int g = l_par[p];
+                        if (g == p) break;
+                        l_par[x] = g;
+                        p = g;
+                    }
+                }
+                __syncthreads();
+                bool changed = false;
+                if (t < tr.count) {
+                    const int pi = l_par[i];
+#pragma unroll
+                    for (int k = 0; k < 9; k++) {
+                        if (cand[k] < 0) continue;
+                        const int pc = l_par[cand[k]];
+                        if (pc != pi) {
+                            atomicMin(&l_par[pc > pi ? pc : pi], pc > pi ? pi : pc);
+                            changed = true;
+                        } else {
+                            cand[k] = -1;  // joined (see link_union_publish)
+                        }
+                    }
+                }
+                if (!__syncthreads_or(changed)) break;
+            }
+            // ---- smallest input index per local tree; every slot joins it
+            // through the global union-find (compare-and-swap only)
+            for (int x = t; x < L; x += kWideThreads) minidx[x] = 0x7FFFFFFF;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kWidePer; k++) {
+                const int a = t + k * kWideThreads;
+                if (a < L) atomicMin(&minidx[l_par[a]], sid[k]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kWidePer; k++) {
+                const int a = t + k * kWideThreads;
+                if (a < L) {
+                    const int32_t m = minidx[l_par[a]];
+                    if (m != sid[k]) gunion(w.gparent, sid[k], m, &w.status->err_internal);
+                }
+            }
+        }
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
+hipError_t launch_link_wide(const Work& w, hipStream_t s)
+{
+    TimedLaunch tl("link_wide", s);
+    const uint64_t pixels = (uint64_t)w.width * w.height;
+    const int bm64 = pixels <= kLinkMaxPixels ? (int)((pixels + 63) / 64) : 0;
+    const size_t dyn = (size_t)bm64 * 8 + (((size_t)bm64 * 2 + 7) & ~(size_t)7);
+    // a tile per work-group and pass; few tiles overflow, so a small input
+    // gets a small grid (the launch costs less when nothing overflows)
+    const int pg = persistent_grid();
+    const int want = (w.n_link_tiles + 3) / 4;
+    const int grid = want < 1 ? 1 : want > pg ? pg : want;
+    hipLaunchKernelGGL(k_link_wide, dim3(grid), dim3(kWideThreads), dyn, s, w, bm64);
+    return hipGetLastError();
+}
+
 // ------------------------------------------- link fallback (big halos)
 // Hits sorted by (pixel, sorted position); for each hit of an overflowed
 // tile and each of its 9 pixels, the latest earlier hit at that pixel is
@@ -651,19 +911,19 @@ struct PixSortJob {
     __device__ int plan(RadixState& st, RadixLds&)
     {
         if (threadIdx.x == 0) {
-            const bool on = w.status->n_overflow > 0 && w.status->err_range == 0;
+            const bool on = w.status->n_deep > 0 && w.status->err_range == 0;
             st.active = on ? 1 : 0;
             st.key_min = 0;
             const uint64_t top = (uint64_t)w.width * w.height - 1;
             const int bits = top == 0 ? 0 : 64 - __builtin_clzll(top);
             st.passes = bits <= 8 ? 1 : (bits + 7) / 8;
         }
-        return w.status->n_overflow;
+        return w.status->n_deep;
     }
     __device__ void store(int64_t, uint64_t, uint32_t) const {}
     __device__ void extra(int q, const uint64_t* keys, const uint32_t* vals, RadixLds&)
     {
-        const int tile = w.overflow_tiles[q];
+        const int tile = w.deep_tiles[q];
         const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
         const int64_t p0 = tr.start;
         const int64_t p1 = tr.start + tr.count;
@@ -718,7 +978,7 @@ struct PixSortJob {
 __global__ __launch_bounds__(kFbThreads) void k_link_fallback(Work w)
 {
     resolve_count(w);
-    if (!w.status->n_overflow || w.status->err_range) return;  // the common case
+    if (!w.status->n_deep || w.status->err_range) return;  // the common case
     PixSortJob job{w};
     uint64_t* kb[2] = {w.fb_key[0], w.fb_key[1]};
     uint32_t* vb[2] = {w.fb_val[0], w.fb_val[1]};

@@ -21,7 +21,7 @@ namespace hc {
 struct RadixLds {
     uint32_t k0[kFbBlock], k1[kFbBlock];
     uint16_t v0[kFbBlock], v1[kFbBlock];
-    uint16_t cnt[cnt_slots(kFbThreads)];
+    uint16_t cnt[16 * kFbThreads];
     uint32_t wsum[kFbThreads / kWave];
     uint64_t key[kFbBlock];
     uint32_t val[kFbBlock];

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 6 : 4) void k_tile_sort(const hc_hi
     constexpr int T = NT * IPT;
     __shared__ uint32_t kr[T];  // ToA - tile minimum, by input position
     __shared__ uint16_t e0[T], e1[T];
-    __shared__ uint16_t cnt[cnt_slots(NT)];
+    __shared__ uint16_t cnt[16 * NT];
     __shared__ uint32_t wsum[NT / kWave];
     __shared__ uint64_t red[NT / kWave];
 

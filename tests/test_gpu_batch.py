@@ -198,3 +198,14 @@ def test_batch_64_chunks_full_size(hc):
     with ThreadPoolExecutor(8) as ex:
         want = list(ex.map(lambda cd: oracle.cluster(cd[0], 256, 256, int(cd[1])), zip(chunks, dts)))
     compare(got, k, want, "batch full size")
+
+
+def test_batch_dense_shower_chunks(hc):
+    """Chunks with dense showers: wide and deep link tiles inside a batch,
+    whose halos must stop at their chunk's first hit."""
+    chunks = [hitgen.shower_stream(m, hitgen.BASE_SEED + 70 + c, shower_hits=sh)
+              for c, (m, sh) in enumerate([(150_000, (1500, 6000)), (3_000, (1100, 2000)), (200_000, (9000, 14000)),
+                                           (90_000, (2500, 4000))])]
+    dts = [128, 64, 128, 320]
+    got, k = run(hc, chunks, dts, hint=4096)
+    compare(got, k, expect(chunks, dts), "showers")

@@ -190,6 +190,22 @@ def test_mixed_10m_full_size(hc):
     assert (got <= np.arange(got.size)).all()
 
 
+# ---- dense showers: tiles with more than 1024 hits within dt before them go
+# to the wide second level (halo up to 7168 hits), deeper ones on to the
+# all-hits fallback; both search variants, and a batch of shower chunks
+@pytest.mark.parametrize("showers", [(1500, 6000), (9000, 14000)])
+@pytest.mark.parametrize("flags", [0, 2])
+def test_dense_showers(hc, showers, flags):
+    hits = hitgen.shower_stream(600_000, seed=hitgen.BASE_SEED + 40 + showers[0], shower_hits=showers)
+    assert_parity(hc, hits, 256, 256, 128, 4096, flags=flags)
+
+
+def test_dense_showers_timepix4_sensor(hc):
+    hits = hitgen.shower_stream(500_000, seed=hitgen.BASE_SEED + 47, width=448, height=512,
+                                shower_hits=(2000, 7000), radius=60)
+    assert_parity(hc, hits, 448, 512, 1024, 4096)
+
+
 # ---- each neighbour search forced on every tile (pixel index, window scan),
 # and sensors at and beyond the window scan's 14-bit limit
 @pytest.mark.parametrize("case", ["blobs_100k", "mixed_10m", "single_pixel", "dense", "timepix4", "same_toa"])
