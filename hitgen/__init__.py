@@ -351,7 +351,8 @@ def timepix4_stream(n=200_000_000, seed=BASE_SEED + 4, window=1 << 20, workers=8
 
     Window w draws clusters whose seed ToAs lie in [w * S, (w + 1) * S), S
     being the time 300 Mhit/s needs for ``window`` hits; the stream stops after
-    n hits (the last window truncated in generation order).  The ToA sort is
+    n hits, at a ToA (the earliest hits of the last window), so the rate
+    holds to the end.  The ToA sort is
     done window by window: hits below the next window's start are final,
     later ones wait for the next window, which makes the result the stable
     ToA order of the whole stream.  The local shuffle (stable sort on
@@ -375,17 +376,18 @@ def timepix4_stream(n=200_000_000, seed=BASE_SEED + 4, window=1 << 20, workers=8
                     futs[k] = ex.submit(_tpx4_window, seed, k, window, span)
             if left > 0:
                 raw = futs.pop(w).result()
-                if raw.size > left:
-                    raw = raw[:left]
+                take = min(left, raw.size)
                 left -= raw.size
             else:
                 futs.pop(w).cancel()
                 raw = np.empty(0, dtype=HIT_DTYPE)
+                take = 0
             pool = np.concatenate([carry, raw])
             pool = pool[np.argsort(pool["toa"], kind="stable")]
             last = left <= 0
             if last:
-                done, carry = pool, pool[:0]
+                # the stream stops at a ToA: the earliest hits up to n in all
+                done, carry = pool[: carry.size + take], pool[:0]
             else:
                 cut = int(np.searchsorted(pool["toa"], np.uint64((w + 1) * span), side="left"))
                 done, carry = pool[:cut], pool[cut:]

@@ -282,6 +282,32 @@ class HcStream:
                 break
         return done, np.concatenate(feats)
 
+    def drain(self, cap=1 << 12, closed_cap=1 << 18):
+        """Like ``poll``, but the closed features are only copied into the
+        pinned staging buffer (and overwritten by the next call): returns the
+        completed tags and the number of closed clusters drained."""
+        if getattr(self, "_tags", None) is None or self._tags.size < cap or self._feats.size < closed_cap:
+            import torch
+            self._tags = np.empty(max(cap, 1), dtype=np.uint64)
+            self._status = np.empty(max(cap, 1), dtype=np.int32)
+            self._feats_t = torch.empty(max(closed_cap, 1) * FEATURE_DTYPE.itemsize, dtype=torch.uint8,
+                                        pin_memory=True)
+            self._feats = self._feats_t.numpy().view(FEATURE_DTYPE)
+        done, n_closed = [], 0
+        nd, nc = ctypes.c_int32(), ctypes.c_int32()
+        while True:
+            _check(self._lib.hc_stream_poll(self._h, self._tags.ctypes.data, self._status.ctypes.data, cap,
+                                            ctypes.byref(nd), self._feats.ctypes.data, closed_cap, ctypes.byref(nc)))
+            for t, st in zip(self._tags[: nd.value].tolist(), self._status[: nd.value].tolist()):
+                if st == HC_OK:
+                    done.append(t)
+                else:
+                    self.rejected[t] = st
+            n_closed += nc.value
+            if nd.value < cap and nc.value < closed_cap:
+                break
+        return done, n_closed
+
     def open_hits(self):
         """Hits held open on the device (hc_stream_open_hits)."""
         return int(self._lib.hc_stream_open_hits(self._h))

@@ -275,14 +275,28 @@ int hc_ingest_feed(hc_ingest* g, const hc_hit* hits, int64_t n)
     int rc = HC_OK;
     for (int64_t k = 0; k < n; k++) {
         if (g->cur < 0 && (rc = take_slot(g, &g->cur)) != HC_OK) return rc;
+        Slot& buf = g->slots[g->cur];
+        if (buf.count < b - bt) {
+            // first part of the buffer: every hit is taken and toa_max tracked,
+            // so a whole run of hits moves in one copy.  No hit of the run can
+            // trigger the send below (toa_max already covers it).
+            const int64_t m = n - k < (b - bt) - buf.count ? n - k : (b - bt) - buf.count;
+            ::memcpy(buf.h_hits + buf.count, hits + k, sizeof(hc_hit) * (size_t)m);
+            uint64_t mx = g->has_max ? g->toa_max : 0;
+            for (int64_t j = 0; j < m; j++) {
+                buf.h_ids[buf.count + j] = (int32_t)(g->fed + j);
+                mx = hits[k + j].toa > mx ? hits[k + j].toa : mx;
+            }
+            g->toa_max = mx;
+            g->has_max = true;
+            buf.count += m;
+            g->fed += m;
+            k += m - 1;
+            continue;
+        }
         const hc_hit& h = hits[k];
         const int32_t id = (int32_t)(g->fed++);
-        Slot& buf = g->slots[g->cur];
-        if (buf.count < b - bt) {  // first part of the buffer: take every hit, track toa_max
-            add(g, g->cur, h, id);
-            if (!g->has_max || h.toa > g->toa_max) g->toa_max = h.toa;
-            g->has_max = true;
-        } else if (h.toa < (~0ull - g->toa_max < tc ? ~0ull : g->toa_max + tc) && buf.count < b) {
+        if (h.toa < (~0ull - g->toa_max < tc ? ~0ull : g->toa_max + tc) && buf.count < b) {
             add(g, g->cur, h, id);  // may still close a cluster that the buffer holds
         } else {
             if (g->nxt < 0 && (rc = take_slot(g, &g->nxt)) != HC_OK) return rc;

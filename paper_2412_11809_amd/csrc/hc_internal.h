@@ -31,7 +31,7 @@ constexpr int kFbThreads = 512;
 constexpr int kFbMaxPasses = 8;       // 8-bit digits of a 64-bit key
 constexpr int kFbScanSeg = 16384;     // digit counters per parallel scan task
 constexpr int kFbGroup = 32;          // blocks per histogram / scatter task (fewer cross-XCD fences)
-constexpr int kMaxNeighbourTiles = 16; // sort merge looks at most this far
+constexpr int kMaxNeighbourTiles = 64; // sort merge looks at most this far (tiles apart in ToA cost one check)
 
 // Partial or final integer features of one cluster (64 bytes).
 struct SlotRec {

@@ -14,11 +14,13 @@
 //                 and writes the element's sorted record at that rank.
 //                 This is exact whenever tiles more than m apart do not
 //                 interleave, which the kernel verifies from the tile min/max
-//                 keys: tile minima ascend and the max of tile i lies below
-//                 the min of tile i+m+1 (then every element of a tile more
-//                 than m tiles away is smaller, resp. larger, than every
-//                 element of this one); a displacement of at most m*T/2
-//                 positions guarantees it.
+//                 keys: the max of tile i lies below the min of tile i+m+1,
+//                 and the tile minima ascend from tile m+1 on (then every
+//                 tile more than m places after tile i lies wholly above
+//                 it, so every element of a tile more than m tiles away is
+//                 smaller, resp. larger, than every element of this one); a
+//                 displacement of at most m*T/2 positions guarantees it.
+//                 The first m+1 tiles need no order among themselves.
 //   k_sort_fallback  if any check failed (or a tile's ToA range exceeds 32
 //                 bits), re-sorts everything with a ticketed LSD radix sort;
 //                 otherwise it exits at once.
@@ -203,7 +205,10 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
 
     if (t == 0) {
         bool bad = false;
-        if (j + 1 < nt) {  // tile minima ascend (maxima need not: a short last tile may end early)
+        // tile minima ascend from the chunk's tile m + 1 on (maxima need not:
+        // a short last tile may end early); the first m + 1 tiles may be in
+        // any order among themselves -- a stream's open hits before its chunk
+        if (j + 1 < nt && j - t0 >= m + 1) {
             const TileInfo tn = w.tiles[j + 1];
             bad |= key_less(tn.base, tn.min_idx, tj.base, tj.min_idx);
         }

@@ -176,44 +176,76 @@ __global__ void k_stream_idmin(const int32_t* __restrict__ lab, const Work w, co
 }
 
 // A hit is final when its cluster is closed: write its stream-global label
-// into its chunk's buffer.  keep[i] = 1 for hits that stay open.
-__global__ void k_stream_close_hits(const int32_t* __restrict__ lab, const Work w, const int32_t* __restrict__ gidx,
-                                    const int32_t* __restrict__ cslot, const int32_t* __restrict__ cmin,
-                                    ChunkRec* chunks, const StreamDev* sd, uint64_t dt, int flush, uint8_t* keep)
+// into its chunk's buffer.  keep[i] = 1 for hits that stay open.  Every chunk
+// counts its hits whose labels are not final yet; the decrements go through
+// a small per-work-group table in LDS (a work-group's hits mostly come from
+// one or two chunks), one global atomic per chunk and work-group, since
+// atomics on one address from every wave serialise in the L2.
+constexpr int kCloseThreads = 256;
+constexpr int kCloseBlock = 2048;
+constexpr int kCloseSlots = 8;
+
+__global__ __launch_bounds__(kCloseThreads) void k_stream_close_hits(const int32_t* __restrict__ lab, const Work w,
+                                                                     const int32_t* __restrict__ gidx,
+                                                                     const int32_t* __restrict__ cslot,
+                                                                     const int32_t* __restrict__ cmin,
+                                                                     ChunkRec* chunks, const StreamDev* sd,
+                                                                     uint64_t dt, int flush, uint8_t* keep)
 {
+    __shared__ int32_t s_slot[kCloseSlots];
+    __shared__ int32_t s_cnt[kCloseSlots];
     const int n_all = sd->n_all;
     if (sd->n_clusters < 0) return;  // the clustering failed; the host reports it
+    if ((int64_t)blockIdx.x * kCloseBlock >= n_all) return;
+    if (threadIdx.x < kCloseSlots) {
+        s_slot[threadIdx.x] = -1;
+        s_cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
     const bool has_wmark = sd->has_wmark;
     const uint64_t wmark = sd->wmark;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
-    bool closed = false;
-    int32_t slot = -1;
-    if (i < n_all) {
-        int32_t r = lab[i];
-        if (r < 0 || r > i) {
-            atomicOr(&w.status->err_internal, 1);
-            r = i;
+    for (int q = 0; q < kCloseBlock / kCloseThreads; q++) {
+        const int64_t i = (int64_t)blockIdx.x * kCloseBlock + q * kCloseThreads + threadIdx.x;
+        bool closed = false;
+        int32_t slot = -1;
+        if (i < n_all) {
+            int32_t r = lab[i];
+            if (r < 0 || r > i) {
+                atomicOr(&w.status->err_internal, 1);
+                r = (int32_t)i;
+            }
+            const uint32_t rank = root_rank(w, 0, 0, r);
+            closed = flush || (has_wmark && sat_add_u64(w.slots[rank].toa_max, dt) <= wmark);
+            if (closed) {
+                slot = cslot[i];
+                ChunkRec* ch = chunks + slot;
+                ch->labels[gidx[i] - ch->base] = cmin ? cmin[rank] : gidx[r];
+            }
+            keep[i] = closed ? 0 : 1;
         }
-        const uint32_t rank = root_rank(w, 0, 0, r);
-        closed = flush || (has_wmark && sat_add_u64(w.slots[rank].toa_max, dt) <= wmark);
-        if (closed) {
-            slot = cslot[i];
-            ChunkRec* ch = chunks + slot;
-            ch->labels[gidx[i] - ch->base] = cmin ? cmin[rank] : gidx[r];
+        // one count per chunk per wave, added into the work-group's table
+        unsigned long long pending = __ballot(closed);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int32_t sl = __shfl(slot, leader, kWave);
+            const unsigned long long same = __ballot(closed && slot == sl);
+            if (lane == leader) {
+                const int32_t c = (int32_t)__popcll(same);
+                int e = -1;
+                for (int k = 0; k < kCloseSlots && e < 0; k++) {
+                    const int32_t old = atomicCAS(&s_slot[k], -1, sl);
+                    if (old == -1 || old == sl) e = k;
+                }
+                if (e >= 0) atomicAdd(&s_cnt[e], c);
+                else atomicSub(&chunks[sl].open, c);  // more chunks than table entries here
+            }
+            pending &= ~same;
         }
-        keep[i] = closed ? 0 : 1;
     }
-    // one decrement per chunk per wave (a wave's hits mostly share a chunk),
-    // not one atomic per hit on the same counter
-    unsigned long long pending = __ballot(closed);
-    while (pending) {
-        const int leader = __ffsll((long long)pending) - 1;
-        const int32_t s = __shfl(slot, leader, kWave);
-        const unsigned long long same = __ballot(closed && slot == s);
-        if (lane == leader) atomicSub(&chunks[s].open, (int32_t)__popcll(same));
-        pending &= ~same;
-    }
+    __syncthreads();
+    if (threadIdx.x < kCloseSlots && s_slot[threadIdx.x] >= 0)
+        atomicSub(&chunks[s_slot[threadIdx.x]].open, s_cnt[threadIdx.x]);
 }
 
 // flag[k] = 1 for clusters (feature rows, ascending label) that are closed
@@ -738,8 +770,9 @@ static int enqueue_push(hc_stream* st, const hc_hit* hits, const int32_t* in_ids
                 hipLaunchKernelGGL(k_stream_idmin, dim3(nb_all), dim3(256), 0, st->s, st->lab, w, st->ids[st->cur],
                                    st->sd, st->cmin);
             }
-            hipLaunchKernelGGL(k_stream_close_hits, dim3(nb_all), dim3(256), 0, st->s, st->lab, w, st->gidx[st->cur],
-                               st->cslot[st->cur], cmin, st->chunks_dev, st->sd, st->dt, flush, st->flags);
+            hipLaunchKernelGGL(k_stream_close_hits, dim3((int)((n_all_bound + kCloseBlock - 1) / kCloseBlock)),
+                               dim3(kCloseThreads), 0, st->s, st->lab, w, st->gidx[st->cur], st->cslot[st->cur], cmin,
+                               st->chunks_dev, st->sd, st->dt, flush, st->flags);
             hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all, st->counts);
             hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, &st->sd->n_all, &st->sd->n_open);
             hipLaunchKernelGGL(k_scatter_open, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all,

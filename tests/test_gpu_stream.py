@@ -45,8 +45,8 @@ def run_stream(hc, hits, sizes, w, h, dt, tdis, hint):
     return labels, feats, done
 
 
-def check(hc, hits, sizes, w, h, dt, hint):
-    tdis = hitgen.realised_disorder_ticks(hits) + 1
+def check(hc, hits, sizes, w, h, dt, hint, t_scale=1):
+    tdis = (hitgen.realised_disorder_ticks(hits) + 1) * t_scale
     got_l, got_f, done = run_stream(hc, hits, sizes, w, h, dt, tdis, hint)
     want_l, want_f = oracle.cluster(hits, w, h, dt)
     assert sorted(done) == list(range(len(sizes)))
@@ -112,6 +112,17 @@ def test_stream_timepix4_1m_chunks(hc):
     hits = np.concatenate(list(hitgen.timepix4_stream(n=n, seed=hitgen.BASE_SEED + 14)))
     p = hitgen.TPX4_PARAMS
     check(hc, hits, [1_000_000] * 16, p["width"], p["height"], p["dt"], p["disorder"])
+
+
+def test_stream_large_disorder_bound(hc):
+    """A declared disorder bound ten times the realised one keeps about ten
+    times more hits open (about 200k ahead of every 1M-hit chunk): the sort
+    of open hits + chunk then reaches across dozens of tiles, and the result
+    is still the whole-stream oracle's."""
+    n = 8_000_000
+    hits = np.concatenate(list(hitgen.timepix4_stream(n=n, seed=hitgen.BASE_SEED + 15)))
+    p = hitgen.TPX4_PARAMS
+    check(hc, hits, [1_000_000] * 8, p["width"], p["height"], p["dt"], p["disorder"], t_scale=10)
 
 
 def _push_expect(hc, st, hits, tag):

@@ -2,8 +2,12 @@
 element against the m neighbour tiles on each side): whenever the check on
 the tile minimum/maximum keys passes, the ranks are exactly the positions in
 (toa, index) order, and a displacement of at most m*T/2 always passes it --
-also when the last tile is short.  Also the merge-path form of the
-neighbour counts (equal shares of the merged sequence per thread)."""
+also when the last tile is short.  The check: tile j's maximum lies below
+the minimum of tile j+m+1, and the tile minima ascend from tile m+1 on
+(together: every tile m+1 or more places after j lies wholly above j).  The
+first m+1 tiles may be in any order among themselves, as in a stream's
+buffer whose open hits precede the new chunk.  Also the merge-path form of
+the neighbour counts (equal shares of the merged sequence per thread)."""
 import numpy as np
 import pytest
 
@@ -22,7 +26,7 @@ def tile_ranks(toa, T, m):
         keys = list(zip(toa[a:b][o].tolist(), (a + o).tolist()))
         tiles.append(keys)
     for j in range(nt):
-        if j + 1 < nt and tiles[j + 1][0] < tiles[j][0]:
+        if j + 1 < nt and j >= m + 1 and tiles[j + 1][0] < tiles[j][0]:
             return None
         if j + m + 1 < nt and not tiles[j][-1] < tiles[j + m + 1][0]:
             return None
@@ -60,6 +64,55 @@ def test_ranks_exact_when_check_passes(seed):
         assert r is not None, "displacement within the bound must pass the check"
     if r is not None:
         assert np.array_equal(r, true_ranks(toa))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_ranks_exact_with_unordered_prefix(seed):
+    """A prefix of hits whose ToAs interleave with the following ones (a
+    stream's open hits before a chunk), then a locally shuffled tail: the
+    relaxed check passes with m covering the prefix, and the ranks are exact;
+    any other input that passes is exact too."""
+    rng = np.random.default_rng(500 + seed)
+    T = int(rng.choice([8, 16]))
+    pre = int(rng.integers(1, 3 * T))
+    tail = int(rng.integers(T, 8 * T))
+    D = int(rng.integers(0, T))
+    toa_tail = np.sort(rng.integers(0, 4 * tail, tail)).astype(np.int64)
+    toa_tail = toa_tail[np.argsort(np.arange(tail) + rng.integers(0, D + 1, tail), kind="stable")]
+    # the prefix lies among the tail's first hits in ToA
+    toa_pre = rng.integers(0, max(1, int(toa_tail[: pre + 1].max())) + 1, pre).astype(np.int64)
+    toa = np.concatenate([toa_pre, toa_tail])
+    m = max(1, -(-2 * (D + pre) // T))
+    r = tile_ranks(toa, T, m)
+    assert r is not None
+    assert np.array_equal(r, true_ranks(toa))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_any_input_passing_the_check_is_exact(seed):
+    rng = np.random.default_rng(900 + seed)
+    passed = 0
+    for _ in range(300):
+        T = int(rng.choice([4, 8]))
+        n = int(rng.integers(1, 10 * T))
+        m = int(rng.integers(1, 4))
+        kind = int(rng.integers(0, 3))
+        if kind == 0:  # random
+            toa = rng.integers(0, 3 * n, n).astype(np.int64)
+        elif kind == 1:  # scrambled head, sorted rest
+            toa = np.sort(rng.integers(0, 3 * n, n)).astype(np.int64)
+            h = int(rng.integers(0, n + 1))
+            toa[:h] = rng.permutation(toa[:h])
+        else:  # sorted with random swaps anywhere
+            toa = np.sort(rng.integers(0, 3 * n, n)).astype(np.int64)
+            for _ in range(int(rng.integers(0, 4))):
+                a, b = rng.integers(0, n, 2)
+                toa[a], toa[b] = toa[b], toa[a]
+        r = tile_ranks(toa, T, m)
+        if r is not None:
+            passed += 1
+            assert np.array_equal(r, true_ranks(toa)), (T, m, toa.tolist())
+    assert passed > 50
 
 
 def test_short_last_tile_passes():
