@@ -586,8 +586,6 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
     period = span + tdis + 4096  # ToA offset between passes
     dt = 128
     rng = np.random.default_rng([seed, 9])
-    mean_chunk = (1_000_000 - 4000) / np.log(1_000_000 / 4000)
-    lam = rate_mhits * 1e6 / n_streams / mean_chunk  # chunks per second per stream
 
     def pinned_hits(a):
         t = torch.empty(a.nbytes, dtype=torch.uint8, pin_memory=True)
@@ -599,6 +597,12 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
     labels = [[torch.empty(pool, dtype=torch.int32, pin_memory=True) for _ in range(2)] for _ in pools]
 
     plans = [_chunk_plan(rng, pool) for _ in range(n_streams)]  # drawn either way: same later chunks
+    # chunks per second per stream for the offered hit rate: a pass of the
+    # pool ends with a shortened chunk, so the mean chunk is that of the plans
+    # (estimated over 2000 of them, on a generator of its own)
+    sim = np.random.default_rng([seed, 11])
+    mean_chunk = pool * 2000 / sum(len(_chunk_plan(sim, pool)) for _ in range(2000))
+    lam = rate_mhits * 1e6 / n_streams / mean_chunk
     sat = None
     if not rate_only:
         sat_mhits, seq_mhits, sat = _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels,
@@ -690,7 +694,8 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
                        "replayed with a ToA offset per pass" % (n_streams, rate_mhits / n_streams, rate_mhits, pool),
            "seconds": seconds, "chunks": int(comps.size), "rejected": int((comps["status"] != 0).sum()),
            "hits_served": hits_done,
-           "offered_mhits": rate_mhits, "achieved_mhits": round(hits_done / t_span / 1e6, 1),
+           "offered_mhits": rate_mhits, "offered_chunks_per_s": round(lam * n_streams, 1),
+           "achieved_mhits": round(hits_done / t_span / 1e6, 1),
            "processing_latency_ms": {"p50": q(proc, 0.5), "p99": q(proc, 0.99)},
            "final_latency_ms": {"p50": q(fin, 0.5), "p99": q(fin, 0.99)},
            "hbm_peak_bytes": int(stats["hbm_peak"]), "peak_slots_in_use": int(stats["peak_slots_in_use"]),

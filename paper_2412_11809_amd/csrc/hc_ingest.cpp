@@ -29,13 +29,15 @@ using namespace hc;
 
 namespace {
 
-// One buffer: pinned host hits and arrival indices and their device copies,
+// One buffer: pinned host hits and runs of arrival indices, their device copies,
 // from filling until the push that reads them has run on the device.
 struct Slot {
     hc_hit* h_hits = nullptr;
-    int32_t* h_ids = nullptr;
+    int2* h_runs = nullptr;       // arrival ids as runs: (position, id) where a run starts
+    int32_t n_runs = 0;
     hc_hit* d_hits = nullptr;
     int32_t* d_ids = nullptr;
+    int2* d_runs = nullptr;
     hipEvent_t copied = nullptr;  // the H2D copy has read the host buffer
     int64_t count = 0;
     uint64_t push = 0;            // stream push that reads the device copies
@@ -43,12 +45,29 @@ struct Slot {
 };
 
 // One sent buffer until its labels are all final: where the device writes
-// them, and the arrival index of every position.
+// them, the arrival ids as runs (position, id) of consecutive ids, and its
+// number of hits.
 struct Chunk {
     uint64_t seq = 0;
     int32_t* d_labels = nullptr;
-    std::vector<int32_t> ids;
+    std::vector<int2> runs;
+    int64_t count = 0;
 };
+
+// Per-hit arrival ids of a buffer from its runs: position i takes the id of
+// the last run starting at or before it, plus its distance from that start.
+__global__ void k_ingest_ids(const int2* __restrict__ runs, int32_t n_runs, int32_t count, int32_t* ids)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count || n_runs <= 0) return;
+    int32_t lo = 0, hi = n_runs;  // the first run starting after i
+    while (lo < hi) {
+        const int32_t m = (lo + hi) >> 1;
+        if (runs[m].x <= i) lo = m + 1; else hi = m;
+    }
+    const int2 r = runs[lo > 0 ? lo - 1 : 0];
+    ids[i] = r.y + (i - r.x);
+}
 
 }  // namespace
 
@@ -84,9 +103,10 @@ static int fail_ing(hc_ingest* g, int code, const std::string& msg)
 static void free_slot(Slot& sl)
 {
     if (sl.h_hits) (void)hipHostFree(sl.h_hits);
-    if (sl.h_ids) (void)hipHostFree(sl.h_ids);
+    if (sl.h_runs) (void)hipHostFree(sl.h_runs);
     (void)hipFree(sl.d_hits);
     (void)hipFree(sl.d_ids);
+    (void)hipFree(sl.d_runs);
     if (sl.copied) (void)hipEventDestroy(sl.copied);
 }
 
@@ -108,18 +128,15 @@ static int collect(hc_ingest* g)
             if (it == g->chunks.end()) continue;
             if (g->status[k] != HC_OK)
                 return fail_ing(g, g->status[k], "ingest: a buffer was rejected (input not t-ordered within t?)");
-            const int64_t m = (int64_t)it->ids.size();
+            const int64_t m = it->count;
             hipError_t e = hipMemcpyAsync(g->h_labels, it->d_labels, 4 * (size_t)m, hipMemcpyDeviceToHost, g->ls);
             if (e == hipSuccess) e = hipStreamSynchronize(g->ls);
             if (e != hipSuccess) return fail_ing(g, HC_ERR_DEVICE, "ingest: label copy");
-            // place by arrival index; runs of consecutive indices move in one copy
-            const int32_t* id = it->ids.data();
-            int64_t j = 0;
-            while (j < m) {
-                int64_t e2 = j + 1;
-                while (e2 < m && id[e2] == id[e2 - 1] + 1) e2++;
-                ::memcpy(g->labels_out + id[j], g->h_labels + j, 4 * (size_t)(e2 - j));
-                j = e2;
+            // place by arrival index, one copy per run of consecutive indices
+            const std::vector<int2>& rs = it->runs;
+            for (size_t q = 0; q < rs.size(); q++) {
+                const int64_t end = q + 1 < rs.size() ? rs[q + 1].x : m;
+                ::memcpy(g->labels_out + rs[q].y, g->h_labels + rs[q].x, 4 * (size_t)(end - rs[q].x));
             }
             g->stats.hits_done += m;
             g->stats.buffers_done++;
@@ -142,6 +159,7 @@ static int take_slot(hc_ingest* g, int* out)
                 if (e != hipSuccess) return fail_ing(g, HC_ERR_DEVICE, "ingest: copy event");
                 sl.state = Slot::kFilling;
                 sl.count = 0;
+                sl.n_runs = 0;
                 *out = i;
                 return HC_OK;
             }
@@ -168,11 +186,18 @@ static int send(hc_ingest* g, int i)
     } else if (hipMalloc(&ch.d_labels, 4 * (size_t)g->cfg.buffer_hits) != hipSuccess) {
         return fail_ing(g, HC_ERR_DEVICE, "ingest: hipMalloc(labels)");
     }
-    ch.ids.assign(sl.h_ids, sl.h_ids + sl.count);
+    ch.runs.assign(sl.h_runs, sl.h_runs + sl.n_runs);
+    ch.count = sl.count;
     hipError_t e = hipMemcpyAsync(sl.d_hits, sl.h_hits, sizeof(hc_hit) * (size_t)sl.count, hipMemcpyHostToDevice,
                                   g->cs);
+    // the arrival ids go up as runs and are expanded into per-hit ids there
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.d_ids, sl.h_ids, 4 * (size_t)sl.count, hipMemcpyHostToDevice, g->cs);
+        e = hipMemcpyAsync(sl.d_runs, sl.h_runs, sizeof(int2) * (size_t)sl.n_runs, hipMemcpyHostToDevice, g->cs);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_ingest_ids, dim3((unsigned)((sl.count + 255) / 256)), dim3(256), 0, g->cs, sl.d_runs,
+                           sl.n_runs, (int32_t)sl.count, sl.d_ids);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipEventRecord(sl.copied, g->cs);
     if (e == hipSuccess) e = hipStreamWaitEvent(g->s, sl.copied, 0);
     if (e != hipSuccess) {
@@ -192,11 +217,23 @@ static int send(hc_ingest* g, int i)
     return collect(g);
 }
 
+// The arrival ids of hits appended at the buffer's end from id on: they
+// extend the last run when they continue it, else open a new one (at most one
+// run per hit, so the run arrays of b entries always suffice).
+static void add_ids(Slot& sl, int32_t id)
+{
+    if (sl.n_runs > 0) {
+        const int2 last = sl.h_runs[sl.n_runs - 1];
+        if (last.y + (sl.count - last.x) == id) return;  // consecutive: the run goes on
+    }
+    sl.h_runs[sl.n_runs++] = make_int2((int)sl.count, id);
+}
+
 static void add(hc_ingest* g, int i, const hc_hit& h, int32_t id)
 {
     Slot& sl = g->slots[i];
     sl.h_hits[sl.count] = h;
-    sl.h_ids[sl.count] = id;
+    add_ids(sl, id);
     sl.count++;
 }
 
@@ -238,9 +275,10 @@ int hc_ingest_create(const hc_ingest_config* cfg, int32_t* labels_out, int64_t l
     for (Slot& sl : g->slots) {
         if (rc != HC_OK) break;
         if ((e = hipHostMalloc((void**)&sl.h_hits, sizeof(hc_hit) * b, hipHostMallocDefault)) != hipSuccess ||
-            (e = hipHostMalloc((void**)&sl.h_ids, 4 * b, hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc((void**)&sl.h_runs, sizeof(int2) * b, hipHostMallocDefault)) != hipSuccess ||
             (e = hipMalloc(&sl.d_hits, sizeof(hc_hit) * b)) != hipSuccess ||
             (e = hipMalloc(&sl.d_ids, 4 * b)) != hipSuccess ||
+            (e = hipMalloc(&sl.d_runs, sizeof(int2) * b)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming)) != hipSuccess)
             rc = set_device_error(e, "ingest buffers");
     }
@@ -282,11 +320,9 @@ int hc_ingest_feed(hc_ingest* g, const hc_hit* hits, int64_t n)
             // trigger the send below (toa_max already covers it).
             const int64_t m = n - k < (b - bt) - buf.count ? n - k : (b - bt) - buf.count;
             ::memcpy(buf.h_hits + buf.count, hits + k, sizeof(hc_hit) * (size_t)m);
+            add_ids(buf, (int32_t)g->fed);
             uint64_t mx = g->has_max ? g->toa_max : 0;
-            for (int64_t j = 0; j < m; j++) {
-                buf.h_ids[buf.count + j] = (int32_t)(g->fed + j);
-                mx = hits[k + j].toa > mx ? hits[k + j].toa : mx;
-            }
+            for (int64_t j = 0; j < m; j++) mx = hits[k + j].toa > mx ? hits[k + j].toa : mx;
             g->toa_max = mx;
             g->has_max = true;
             buf.count += m;
