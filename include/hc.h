@@ -242,6 +242,18 @@ int hc_stream_create(const hc_opts* opts, uint64_t dt, uint64_t max_disorder_tic
  * HC_ERR_DEVICE after a device failure. */
 int hc_stream_push(hc_stream* s, const hc_hit* hits, int32_t n, int32_t* labels, uint64_t tag);
 
+/* Several chunks in one push: k (1..16) chunks stored back to back at hits
+ * (device memory), chunk j with counts[j] > 0 hits, its labels to labels[j]
+ * (device int32[counts[j]]) and reported under tags[j]; counts, labels and
+ * tags are host arrays, read before the call returns.  The result is that of
+ * k hc_stream_push calls in order -- each chunk accepted or rejected on its
+ * own, against the watermark the chunks before it set -- with one pass of
+ * device work, which spares small chunks the fixed cost of a push (the
+ * serving loop merges queued chunks of a stream this way).  Not for streams
+ * that take ids (HC_ERR_ARG). */
+int hc_stream_push_chunks(hc_stream* s, const hc_hit* hits, int32_t k, const int32_t* counts,
+                          int32_t* const* labels, const uint64_t* tags);
+
 /* hc_stream_push with caller-chosen ids (device int32[n], non-negative):
  * a cluster's label -- in the labels buffers and in the closed features --
  * is then the smallest id among its hits instead of the smallest global
@@ -402,6 +414,8 @@ void hc_batch_graph_destroy(hc_batch_graph* graph);
  * slots is free and the device memory it needs (its hits and labels, plus the
  * growth of its stream's state) fits in `hbm_budget` beside everything the
  * server already holds; otherwise it waits, in arrival order per stream.
+ * Chunks of a stream queued together share one push, and one slot, as long
+ * as they fit in max_chunk_hits together (at most 16 chunks).
  *
  * Host buffers: hits[n] is copied to the device after admission and labels[n]
  * receives the chunk's final (stream-global) labels; both belong to the
@@ -414,7 +428,7 @@ typedef struct hc_server hc_server;
 typedef struct {
     uint32_t width, height;      /* sensor of every stream (0 => 256) */
     int32_t n_streams;           /* stream ids 0 .. n_streams - 1 (1..256) */
-    int32_t max_slots;           /* chunks in device processing at once (0 => n_streams) */
+    int32_t max_slots;           /* pushes in device processing at once (0 => 2 * n_streams) */
     uint64_t dt;                 /* time window of the clusters, ticks */
     uint64_t max_disorder_ticks; /* t of every stream (see hc_stream_create) */
     uint64_t hbm_budget;         /* bytes of device memory the server may hold (0 => 16 GiB) */
@@ -447,6 +461,7 @@ typedef struct {
     /* worker time summed over streams, ns: waiting for admission, copying
      * hits in and pushing, moving closed clusters out, copying final labels */
     uint64_t ns_admit_wait, ns_push, ns_drain, ns_final;
+    int64_t pushes; /* device pushes (one push carries the chunks of a stream queued together) */
 } hc_server_stats;
 
 /* Monotonic clock (ns) for t_arrive stamps. */

@@ -214,6 +214,10 @@ def _bind_stream(lib):
     lib.hc_stream_push.restype = ctypes.c_int
     lib.hc_stream_push.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_uint64]
+    lib.hc_stream_push_chunks.restype = ctypes.c_int
+    lib.hc_stream_push_chunks.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_uint64)]
     lib.hc_stream_poll.restype = ctypes.c_int
     lib.hc_stream_poll.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_int32,
@@ -255,6 +259,15 @@ class HcStream:
 
     def push(self, hits, labels, tag):
         self.hc_stream_push(hits, hits.numel() // 16, labels, tag)
+
+    def hc_stream_push_chunks(self, hits, counts, labels, tags):
+        """k chunks back to back in the device buffer hits; labels: one device
+        int32 tensor per chunk; counts and tags: sequences of k integers."""
+        k = len(counts)
+        c = (ctypes.c_int32 * k)(*[int(x) for x in counts])
+        lp = (ctypes.c_void_p * k)(*[_ptr(x) for x in labels])
+        t = (ctypes.c_uint64 * k)(*[int(x) for x in tags])
+        _check(self._lib.hc_stream_push_chunks(self._h, _ptr(hits), k, c, lp, t))
 
     def poll(self, cap=1 << 12, closed_cap=1 << 16):
         """Tags of the chunks completed so far (rejected ones go to
@@ -646,7 +659,7 @@ class _ServerStats(ctypes.Structure):
                 ("processing_p50", ctypes.c_uint64), ("processing_p99", ctypes.c_uint64),
                 ("final_p50", ctypes.c_uint64), ("final_p99", ctypes.c_uint64),
                 ("ns_admit_wait", ctypes.c_uint64), ("ns_push", ctypes.c_uint64), ("ns_drain", ctypes.c_uint64),
-                ("ns_final", ctypes.c_uint64)]
+                ("ns_final", ctypes.c_uint64), ("pushes", ctypes.c_int64)]
 
 
 def _bind_server(lib):

@@ -241,13 +241,17 @@ uint64_t stream_pushes_enqueued(const hc_stream* st);
 uint64_t stream_pushes_retired(hc_stream* st);
 int stream_wait_one(hc_stream* st);
 size_t stream_inflight(const hc_stream* st);
-// A completed chunk push, as the server sees it: the push's tag, whether the
-// chunk was accepted, and how many clusters the push closed.
+// A chunk of a completed push, as the server sees it: its tag, whether it was
+// accepted, how many clusters the push closed (counted for the push's last
+// chunk, 0 for the others), and whether it is the push's last chunk.
 struct RetiredPush {
     uint64_t tag;
     int32_t verdict;
     int32_t n_closed;
+    int32_t last;
 };
+// Chunks one push may carry.
+constexpr int kMaxPushChunks = 16;
 // Pushes in flight at most (depth); with log_retired every completed chunk
 // push is recorded for stream_take_retired, which appends and clears them.
 void stream_configure(hc_stream* st, int depth, bool log_retired);

@@ -5,10 +5,13 @@
 // device slot is free and the memory they need fits the HBM budget; admitted
 // chunks of different streams run concurrently on the device, and a stream's
 // own chunks are pipelined: pushes are asynchronous, so the worker copies and
-// enqueues the next chunk while earlier ones still run, and retires pushes
+// enqueues the next push while earlier ones still run, and retires pushes
 // (slot release, processing stamp, closed clusters to the host) as their
-// completion is observed.  Final labels go back on a separate copy stream,
-// which never waits for pushes still in flight.
+// completion is observed.  Chunks of one stream that are queued together are
+// merged into one push (up to the reserved chunk size), each still accepted
+// or rejected on its own: a push has a fixed cost of some tens of kernels,
+// which small chunks would otherwise pay one by one.  Final labels go back on
+// a separate copy stream, which never waits for pushes still in flight.
 #include <string.h>
 
 #include <algorithm>
@@ -107,6 +110,7 @@ struct hc_server {
     uint64_t used = 0, peak = 0, progress = 0;
     int slots_used = 0, peak_slots = 0;
     int64_t submitted = 0, completed = 0, rejected = 0, hits_completed = 0, queued = 0, pending_final = 0;
+    int64_t pushes = 0;  // device pushes enqueued
     int working = 0;  // requests taken by a worker and not yet through their device processing
     std::atomic<uint64_t> ns_admit{0}, ns_push{0}, ns_drain{0}, ns_final{0};
     bool stopping = false;
@@ -151,7 +155,10 @@ struct hc_server {
 
     void worker(StreamCtx* cx);
     bool try_admit(StreamCtx* cx, const Req& r, Pending* p, size_t* hits_need, uint64_t* charged);
-    void run_chunk(StreamCtx* cx, const Req& r, Pending p, size_t hits_need, uint64_t charged);
+    bool try_admit_more(StreamCtx* cx, const Req& r, int64_t hits_before, Pending* p, size_t* hits_need,
+                        uint64_t* charged);
+    void run_push(StreamCtx* cx, std::vector<Req>& rs, std::vector<Pending>& ps, size_t hits_need,
+                  uint64_t charged);
     void advance(StreamCtx* cx);
     void finish(StreamCtx* cx, uint64_t seq, int32_t status);
 };
@@ -220,9 +227,11 @@ void hc_server::advance(StreamCtx* cx)
                 it->second.n_closed = r.n_closed;
                 lat_proc.push_back(tp - it->second.t_arrive);
             }
-            slots_used--;
-            cx->in_device--;
             working--;
+            if (r.last) {  // one slot per push
+                slots_used--;
+                cx->in_device--;
+            }
         }
         account((int64_t)state_now - (int64_t)cx->state_bytes);
         cx->state_bytes = state_now;
@@ -266,9 +275,44 @@ bool hc_server::try_admit(StreamCtx* cx, const Req& r, Pending* p, size_t* hits_
     return true;
 }
 
-void hc_server::run_chunk(StreamCtx* cx, const Req& r, Pending p, size_t hits_need, uint64_t charged)
+// Admission of one more queued chunk into the push being formed (lock held):
+// no slot of its own, only the memory it adds (the push's hits, its labels,
+// the stream state for the larger push) within the budget.
+bool hc_server::try_admit_more(StreamCtx* cx, const Req& r, int64_t hits_before, Pending* p, size_t* hits_need,
+                               uint64_t* charged)
 {
-    const uint64_t seq = cx->seq++;
+    const size_t need_h = block_class(sizeof(hc_hit) * (size_t)(hits_before + r.n));
+    const size_t held_h = std::max(*hits_need, cx->hits_bytes);
+    const size_t hits_grow = need_h > held_h ? need_h - held_h : 0;
+    size_t tr0 = 0, tr1 = 0;
+    const size_t s0 = stream_bytes_after_push(cx->st, hits_before, &tr0);
+    const size_t s1 = stream_bytes_after_push(cx->st, hits_before + r.n, &tr1);
+    const size_t state_grow = (s1 > s0 ? s1 - s0 : 0) + (tr1 > tr0 ? tr1 - tr0 : 0);
+    p->labels_class = block_class(4 * (size_t)r.n);
+    auto fb = free_blocks.lower_bound(p->labels_class);
+    while (fb != free_blocks.end() && fb->second.empty()) ++fb;
+    const bool reuse = fb != free_blocks.end();
+    const uint64_t need = hits_grow + state_grow + (reuse ? 0 : p->labels_class);
+    if (used + need > cfg.hbm_budget) return false;
+    if (reuse) {
+        p->labels_dev = fb->second.back();
+        p->labels_class = fb->first;
+        fb->second.pop_back();
+    }
+    account((int64_t)need);
+    *hits_need = std::max(*hits_need, need_h);
+    *charged += state_grow;  // the stream's share, reconciled after the push
+    queued--;
+    return true;
+}
+
+// One push of the admitted chunks rs (one stream, in order, none empty
+// unless it is alone): hits copied in behind each other, labels blocks,
+// one hc_stream push, and each chunk pending until its labels are final.
+void hc_server::run_push(StreamCtx* cx, std::vector<Req>& rs, std::vector<Pending>& ps, size_t hits_need,
+                         uint64_t charged)
+{
+    const int k = (int)rs.size();
     hipError_t e = hipSuccess;
     int rc = HC_OK;
     if (hits_need > cx->hits_bytes) {
@@ -278,70 +322,82 @@ void hc_server::run_chunk(StreamCtx* cx, const Req& r, Pending p, size_t hits_ne
         cx->hits_dev = nullptr;
         const size_t grow = hits_need - cx->hits_bytes;
         if (rc == HC_OK && (e = hipMalloc(&cx->hits_dev, hits_need)) != hipSuccess) {
+            cx->hits_dev = nullptr;
             rc = set_device_error(e, "server: hits buffer");
+        }
+        if (rc == HC_OK) {
+            cx->hits_bytes = hits_need;
+        } else {
             std::lock_guard<std::mutex> lk(mu);
             account(-(int64_t)cx->hits_bytes - (int64_t)grow);
             cx->hits_bytes = 0;
-        } else if (rc == HC_OK) {
-            cx->hits_bytes = hits_need;
         }
     }
-    if (rc == HC_OK && r.n > 0 && !p.labels_dev) {
-        if ((e = hipMalloc(&p.labels_dev, p.labels_class)) != hipSuccess) {
-            p.labels_dev = nullptr;
-            rc = set_device_error(e, "server: labels buffer");
-            std::lock_guard<std::mutex> lk(mu);
-            account(-(int64_t)p.labels_class);
+    int64_t total = 0;
+    for (int j = 0; j < k; j++) total += rs[j].n;
+    for (int j = 0; j < k && rc == HC_OK; j++)
+        if (rs[j].n > 0 && !ps[j].labels_dev) {
+            if ((e = hipMalloc(&ps[j].labels_dev, ps[j].labels_class)) != hipSuccess) {
+                ps[j].labels_dev = nullptr;
+                rc = set_device_error(e, "server: labels buffer");
+            }
         }
+    // the hits buffer is rewritten only behind the earlier pushes on the same
+    // stream; chunks that lie back to back in host memory go in one copy
+    for (int j = 0, at = 0; j < k && rc == HC_OK;) {
+        int j1 = j + 1;
+        int64_t m = rs[j].n;
+        while (j1 < k && rs[j1].hits == rs[j1 - 1].hits + rs[j1 - 1].n) m += rs[j1++].n;
+        if (m > 0 && (e = hipMemcpyAsync((hc_hit*)cx->hits_dev + at, rs[j].hits, sizeof(hc_hit) * (size_t)m,
+                                         hipMemcpyHostToDevice, cx->hs)) != hipSuccess)
+            rc = set_device_error(e, "server: hits copy");
+        at += (int)m;
+        j = j1;
     }
-    // the hits buffer is rewritten only behind the earlier pushes on the same stream
-    if (rc == HC_OK && r.n > 0 &&
-        (e = hipMemcpyAsync(cx->hits_dev, r.hits, sizeof(hc_hit) * (size_t)r.n, hipMemcpyHostToDevice, cx->hs)) !=
-            hipSuccess)
-        rc = set_device_error(e, "server: hits copy");
-    if (rc == HC_OK && r.n > 0)
-        rc = hc_stream_push(cx->st, (const hc_hit*)cx->hits_dev, r.n, (int32_t*)p.labels_dev, seq);
+    std::vector<uint64_t> seqs(k);
+    for (int j = 0; j < k; j++) seqs[j] = cx->seq++;
+    if (rc == HC_OK && total > 0) {
+        int32_t counts[kMaxPushChunks];
+        int32_t* labs[kMaxPushChunks];
+        for (int j = 0; j < k; j++) {
+            counts[j] = rs[j].n;
+            labs[j] = (int32_t*)ps[j].labels_dev;
+        }
+        rc = hc_stream_push_chunks(cx->st, (const hc_hit*)cx->hits_dev, k, counts, labs, seqs.data());
+    }
     const uint64_t d0 = now_ns();
-    ns_push += d0 - p.t_admit;
+    ns_push += d0 - ps[0].t_admit;
     const size_t state_now = stream_device_bytes(cx->st);
     std::lock_guard<std::mutex> lk(mu);
     // the growth charged at admission becomes the stream's actual size
     account((int64_t)state_now - (int64_t)cx->state_bytes - (int64_t)charged);
     cx->state_bytes = state_now;
-    if (rc != HC_OK) {
+    if (rc != HC_OK || total == 0) {  // nothing runs: every chunk is done at once
         slots_used--;
-        working--;
-        hc_completion c{};
-        c.tag = r.tag;
-        c.stream_id = cx->id;
-        c.status = rc;
-        c.n_hits = r.n;
-        c.t_arrive_ns = r.t_arrive;
-        c.t_admit_ns = p.t_admit;
-        c.t_processed_ns = c.t_final_ns = now_ns();
-        if (p.labels_dev) free_blocks[p.labels_class].push_back(p.labels_dev);
-        complete(c);
+        for (int j = 0; j < k; j++) {
+            working--;
+            hc_completion c{};
+            c.tag = rs[j].tag;
+            c.stream_id = cx->id;
+            c.status = rc;
+            c.n_hits = rs[j].n;
+            c.t_arrive_ns = rs[j].t_arrive;
+            c.t_admit_ns = ps[j].t_admit;
+            c.t_processed_ns = c.t_final_ns = now_ns();
+            if (rc == HC_OK) lat_proc.push_back(c.t_processed_ns - rs[j].t_arrive);
+            if (ps[j].labels_dev) free_blocks[ps[j].labels_class].push_back(ps[j].labels_dev);
+            else if (rc != HC_OK && rs[j].n > 0) account(-(int64_t)ps[j].labels_class);  // its block never came
+            complete(c);
+        }
         idle_cv.notify_all();
         return;
     }
-    if (r.n == 0) {  // nothing to run: done at once
-        slots_used--;
-        working--;
-        hc_completion c{};
-        c.tag = r.tag;
-        c.stream_id = cx->id;
-        c.status = HC_OK;
-        c.t_arrive_ns = r.t_arrive;
-        c.t_admit_ns = p.t_admit;
-        c.t_processed_ns = c.t_final_ns = now_ns();
-        lat_proc.push_back(c.t_processed_ns - r.t_arrive);
-        complete(c);
-        idle_cv.notify_all();
-        return;
-    }
-    pending_final++;
+    pushes++;
     cx->in_device++;
-    cx->pend.emplace(seq, p);
+    for (int j = 0; j < k; j++) {
+        pending_final++;
+        cx->pend.emplace(seqs[j], ps[j]);
+    }
 }
 
 void hc_server::worker(StreamCtx* cx)
@@ -354,6 +410,8 @@ void hc_server::worker(StreamCtx* cx)
         size_t hits_need = 0;
         uint64_t charged = 0;
         bool have = false, flush = false, wait_device = false;
+        std::vector<Req> rs;
+        std::vector<Pending> ps;
         {
             std::unique_lock<std::mutex> lk(mu);
             if (!cx->q.empty()) {
@@ -424,6 +482,24 @@ void hc_server::worker(StreamCtx* cx)
             } else {
                 cx->cv.wait(lk, [&] { return stopping || !cx->q.empty(); });
             }
+            if (have && !flush) {
+                // the chunks queued behind it join its push while they fit
+                rs.push_back(r);
+                ps.push_back(p);
+                int64_t total = r.n;
+                while (r.n > 0 && (int)rs.size() < kMaxPushChunks && !cx->q.empty()) {
+                    const Req& nx = cx->q.front();
+                    if (nx.flush || nx.n == 0 || total + nx.n > cfg.max_chunk_hits) break;
+                    Pending pn{nx.tag, nx.n, 0, nx.labels, nullptr, 0, nx.t_arrive, 0, 0};
+                    if (!try_admit_more(cx, nx, total, &pn, &hits_need, &charged)) break;
+                    pn.t_admit = now_ns();
+                    rs.push_back(nx);
+                    ps.push_back(pn);
+                    cx->q.pop_front();
+                    working++;
+                    total += nx.n;
+                }
+            }
         }
         try {
             if (have && flush) {
@@ -435,7 +511,7 @@ void hc_server::worker(StreamCtx* cx)
                 idle_cv.notify_all();
                 budget_cv.notify_all();
             } else if (have) {
-                run_chunk(cx, r, p, hits_need, charged);
+                run_push(cx, rs, ps, hits_need, charged);
             } else if (wait_device) {
                 (void)stream_wait_one(cx->st);
             }
@@ -642,6 +718,7 @@ int hc_server_stats_read(hc_server* s, hc_server_stats* out)
     st.ns_push = s->ns_push;
     st.ns_drain = s->ns_drain;
     st.ns_final = s->ns_final;
+    st.pushes = s->pushes;
     *out = st;
     return HC_OK;
 }

@@ -16,11 +16,15 @@
 // rest stays open (stable compaction).
 //
 // Pushes are asynchronous: the stream's state (open-hit count, next global
-// index, M, the closed-feature ring's tail) lives in device memory, a commit
-// kernel accepts or rejects each chunk on the device, and the clustering
-// kernels read their hit count from there (the host sizes the grids with an
-// upper bound).  After each push a pinned copy of that state and of the
-// chunk table is taken; the host reads it once the push's event completes.
+// index, M, the closed-feature ring's tail) lives in device memory, the last
+// work-group of the append kernel accepts or rejects each chunk on the
+// device, and the clustering kernels read their hit count from there (the
+// host sizes the grids with an upper bound).  The closing is two kernels: one
+// pass decides every hit and cluster and counts per work-group (the last
+// work-group turns the counts into offsets), one pass moves the open hits and
+// the closed clusters' records.  After each push one pinned copy of the state
+// and the chunk table is taken; the host reads it once the push's event
+// completes.
 #include <string.h>
 
 #include <deque>
@@ -31,6 +35,23 @@
 
 namespace hc {
 
+// A push carries one chunk, or several chunks of the stream back to back
+// (kMaxPushChunks at most), each accepted or rejected on its own exactly as
+// if it had been pushed alone, in order.
+
+// The chunks of one push (a kernel argument): chunk j is hits
+// [start[j], start[j + 1]) of the push's input, registered in chunk slot
+// slot[j] with the caller's label buffer labels[j].
+struct PushChunks {
+    int32_t k;
+    int32_t start[kMaxPushChunks + 1];
+    int32_t slot[kMaxPushChunks];
+    int32_t* labels[kMaxPushChunks];
+};
+
+// chunk flags raised by its hits
+constexpr int32_t kOffSensor = 1, kBadId = 2, kLate = 4;
+
 struct StreamDev {
     // across pushes
     int32_t n_open;               // open hits at the front of the current buffer
@@ -40,50 +61,100 @@ struct StreamDev {
     int32_t has_M, has_floor;
     long long q_tail;             // closed-feature records written so far (ring slot q_tail % q_cap)
     // the current push
-    unsigned long long chunk_max; // largest ToA of the chunk being appended
-    int32_t disorder, range;      // raised by the chunk's hits
-    int32_t n_all;                // hits the push clusters: the open ones, plus the chunk if accepted
-    int32_t verdict;              // HC_OK, or why the chunk was rejected
+    int32_t n_all;                // hits the push clusters: the open ones, plus its accepted chunks
     int32_t n_closed;             // clusters closed by the push
     int32_t n_clusters;           // clusters of the buffer (or an error status)
-    unsigned long long wmark;     // closing watermark of the push (valid when has_wmark)
     int32_t has_wmark;
-    int32_t bad_id;               // a caller-supplied id of the chunk is negative
+    unsigned long long wmark;     // closing watermark of the push (valid when has_wmark)
+    uint32_t ticket;              // work-groups of the running kernel done so far (last one resets it)
+    // per chunk of the push: ~(smallest ToA) and largest ToA (0 when unset),
+    // flags; then, from the commit, its buffer position (-1: rejected) and the
+    // global index of its first hit
+    unsigned long long c_inv_min[kMaxPushChunks], c_max[kMaxPushChunks];
+    int32_t c_flags[kMaxPushChunks], c_dest[kMaxPushChunks], c_base[kMaxPushChunks];
 };
+
+// The stream state and the chunk table share one device block (state at
+// offset 0, table at kStateHdr), read back by one copy after every push.
+constexpr size_t kStateHdr = 1024;
+static_assert(sizeof(StreamDev) <= kStateHdr, "state header");
+
+// Whether this work-group is the last of `active` to get here.  What a
+// work-group hands to the last one it writes from its first wave (after
+// reducing it in the group), so one fence per group suffices: every such write is visible
+// to the work-group that gets true, which also resets the ticket for the next
+// kernel.  No work-group waits for another.
+__device__ inline bool last_group(StreamDev* sd, uint32_t active)
+{
+    __shared__ int s_last;
+    __syncthreads();  // every wave of the group is past its work
+    if (threadIdx.x < kWave) __threadfence();  // the first wave's writes (the group's results)
+    if (threadIdx.x == 0) {
+        s_last = atomicAdd(&sd->ticket, 1u) == active - 1;
+        if (s_last) sd->ticket = 0;
+    }
+    __syncthreads();
+    if (s_last) __threadfence();
+    return s_last;
+}
 
 struct ChunkRec {
     int32_t* labels;  // caller's buffer for the chunk's labels
     int64_t base;     // global index of the chunk's first hit (-1: rejected)
     int32_t count;
     int32_t open;     // hits whose label is not final yet
+    int32_t verdict;  // HC_OK, or why the chunk was rejected
+    int32_t unused_;
 };
 
 constexpr int kCmpBlock = 2048;
 constexpr int kCmpThreads = 256;
+// per-block count entries for `cap` hits (one array each for hits and rows)
+constexpr int64_t count_slots(int64_t cap) { return (cap + kCmpBlock - 1) / kCmpBlock + 1; }
 
 __device__ inline uint64_t sat_add_u64(uint64_t a, uint64_t b) { return ~0ull - a < b ? ~0ull : a + b; }
 
-// Copy the chunk behind the open hits and check it against the stream's
-// contract: every hit on the sensor, and above the watermark M - t (once
-// M >= t) and, after a flush, above the floor.
+__device__ void commit_chunks(StreamDev* sd, ChunkRec* chunks, const PushChunks& pc, uint64_t tdis);
+
+// The ToA threshold of the stream's contract: later hits need toa > thr
+// (has_thr), from the watermark M - t once M >= t and the floor after a flush.
+__device__ inline bool contract_threshold(const StreamDev& d, uint64_t tdis, uint64_t* thr)
+{
+    const bool has_w = d.has_M && d.M >= tdis;
+    uint64_t t = has_w ? d.M - tdis : 0;
+    bool has = has_w;
+    if (d.has_floor) {
+        if (!has || d.floor > t) t = d.floor;
+        has = true;
+    }
+    *thr = t;
+    return has;
+}
+
+// A push of one chunk: copy it behind the open hits and check it against the
+// stream's contract (every hit on the sensor, and above the threshold).  A
+// work-group takes kAppendBlock hits; the last one to finish commits the
+// chunk.
+constexpr int kAppendBlock = 2048;
+
 __global__ __launch_bounds__(256) void k_stream_append(const hc_hit* __restrict__ in,
-                                                       const int32_t* __restrict__ in_ids, int n, hc_hit* buf,
-                                                       int32_t* gidx, int32_t* ids, int32_t* cslot, int slot,
-                                                       StreamDev* sd, uint64_t tdis, uint32_t W, uint32_t H)
+                                                       const int32_t* __restrict__ in_ids, const PushChunks pc,
+                                                       hc_hit* buf, int32_t* gidx, int32_t* ids, int32_t* cslot,
+                                                       StreamDev* sd, ChunkRec* chunks, uint64_t tdis, uint32_t W,
+                                                       uint32_t H)
 {
     __shared__ uint64_t red[256 / kWave];
+    const int n = pc.start[1];
+    const int slot = pc.slot[0];
     const int n_open = sd->n_open;
     const int32_t base = sd->next_g;
-    const bool has_w = sd->has_M && sd->M >= tdis;
-    uint64_t thr = has_w ? sd->M - tdis : 0;
-    bool has_thr = has_w;
-    if (sd->has_floor) {
-        if (!has_thr || sd->floor > thr) thr = sd->floor;
-        has_thr = true;
-    }
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t thr;
+    const bool has_thr = contract_threshold(*sd, tdis, &thr);
     uint64_t mx = 0;
-    if (i < n) {
+    bool bad_id = false, late = false, off = false;
+    for (int q = 0; q < kAppendBlock / 256; q++) {
+        const int i = blockIdx.x * kAppendBlock + q * 256 + threadIdx.x;
+        if (i >= n) break;
         const hc_hit h = in[i];
         buf[n_open + i] = h;
         gidx[n_open + i] = base + i;
@@ -91,65 +162,172 @@ __global__ __launch_bounds__(256) void k_stream_append(const hc_hit* __restrict_
         if (ids) {
             const int32_t id = in_ids ? in_ids[i] : base + i;
             ids[n_open + i] = id;
-            if (id < 0) atomicOr(&sd->bad_id, 1);
+            bad_id |= id < 0;
         }
-        mx = h.toa;
-        if (has_thr && h.toa <= thr) atomicOr(&sd->disorder, 1);
-        if (h.x >= W || h.y >= H) atomicOr(&sd->range, 1);
+        mx = h.toa > mx ? h.toa : mx;
+        late |= has_thr && h.toa <= thr;
+        off |= h.x >= W || h.y >= H;
     }
     mx = block_max_u64<256>(mx, red);
-    if (threadIdx.x == 0) atomicMax(&sd->chunk_max, (unsigned long long)mx);
+    bad_id = __syncthreads_or(bad_id);
+    late = __syncthreads_or(late);
+    off = __syncthreads_or(off);
+    if (threadIdx.x == 0) {  // the group's results, from its first wave (see last_group)
+        atomicMax(&sd->c_max[0], (unsigned long long)mx);
+        const int32_t f = (off ? kOffSensor : 0) | (bad_id ? kBadId : 0) | (late ? kLate : 0);
+        if (f) atomicOr(&sd->c_flags[0], f);
+    }
+    if (last_group(sd, gridDim.x) && threadIdx.x == 0) commit_chunks(sd, chunks, pc, tdis);
 }
 
-// Accept or reject the appended chunk (one thread): an accepted chunk is
-// registered in the chunk table and joins the clustered hits, M advances and
-// the closing watermark follows; a rejected one is left out (its hits sit
-// beyond n_all), so the push only re-clusters the open hits and closes
-// nothing new.  A flush clusters the open hits, closes all of them and sets
-// the floor M + dt for whatever is pushed later.
-__global__ void k_stream_commit(StreamDev* sd, ChunkRec* chunks, int slot, int32_t* labels, int n, uint64_t tdis,
-                                uint64_t dt, int flush)
+// The chunks of a push in LDS, and the chunk of input hit i.
+__device__ inline void load_chunks(const PushChunks& pc, int32_t* s_start, int32_t* s_slot)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (threadIdx.x <= (unsigned)pc.k) s_start[threadIdx.x] = pc.start[threadIdx.x];
+    if (threadIdx.x < (unsigned)pc.k) s_slot[threadIdx.x] = pc.slot[threadIdx.x];
+    __syncthreads();
+}
+
+__device__ inline int chunk_of(const int32_t* s_start, int k, int i)
+{
+    int j = 0;
+    while (j + 1 < k && i >= s_start[j + 1]) j++;
+    return j;
+}
+
+// A push of several chunks, first pass: each chunk's smallest and largest ToA
+// and flags (its acceptance depends on the chunks before it, so the contract
+// is checked by the commit, which the last work-group runs).
+__global__ __launch_bounds__(256) void k_stream_chunk_stats(const hc_hit* __restrict__ in,
+                                                            const int32_t* __restrict__ in_ids, const PushChunks pc,
+                                                            StreamDev* sd, ChunkRec* chunks, int ids_mode,
+                                                            uint64_t tdis, uint32_t W, uint32_t H)
+{
+    __shared__ int32_t s_start[kMaxPushChunks + 1], s_slot[kMaxPushChunks];
+    __shared__ unsigned long long s_inv_min[kMaxPushChunks], s_max[kMaxPushChunks];
+    __shared__ int32_t s_flags[kMaxPushChunks];
+    if (threadIdx.x < kMaxPushChunks) {
+        s_inv_min[threadIdx.x] = 0;
+        s_max[threadIdx.x] = 0;
+        s_flags[threadIdx.x] = 0;
+    }
+    load_chunks(pc, s_start, s_slot);
+    const int n = s_start[pc.k];
+    for (int q = 0; q < kAppendBlock / 256; q++) {
+        const int i = blockIdx.x * kAppendBlock + q * 256 + threadIdx.x;
+        if (i >= n) break;
+        const int j = chunk_of(s_start, pc.k, i);
+        const hc_hit h = in[i];
+        atomicMax(&s_inv_min[j], ~(unsigned long long)h.toa);
+        atomicMax(&s_max[j], (unsigned long long)h.toa);
+        const int32_t f = ((h.x >= W || h.y >= H) ? kOffSensor : 0) | ((ids_mode && in_ids && in_ids[i] < 0) ? kBadId : 0);
+        if (f) atomicOr(&s_flags[j], f);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)pc.k) {  // first wave (k <= kMaxPushChunks < kWave)
+        const int j = threadIdx.x;
+        if (s_max[j] || s_inv_min[j]) {
+            atomicMax(&sd->c_inv_min[j], s_inv_min[j]);
+            atomicMax(&sd->c_max[j], s_max[j]);
+        }
+        if (s_flags[j]) atomicOr(&sd->c_flags[j], s_flags[j]);
+    }
+    if (last_group(sd, gridDim.x) && threadIdx.x == 0) commit_chunks(sd, chunks, pc, tdis);
+}
+
+// Second pass: the hits of every accepted chunk behind the open hits and the
+// accepted chunks before it.
+__global__ __launch_bounds__(256) void k_stream_place(const hc_hit* __restrict__ in, const int32_t* __restrict__ in_ids,
+                                                      const PushChunks pc, const StreamDev* sd, hc_hit* buf,
+                                                      int32_t* gidx, int32_t* ids, int32_t* cslot)
+{
+    __shared__ int32_t s_start[kMaxPushChunks + 1], s_slot[kMaxPushChunks];
+    __shared__ int32_t s_dest[kMaxPushChunks], s_base[kMaxPushChunks];
+    if (threadIdx.x < (unsigned)pc.k) {
+        s_dest[threadIdx.x] = sd->c_dest[threadIdx.x];
+        s_base[threadIdx.x] = sd->c_base[threadIdx.x];
+    }
+    load_chunks(pc, s_start, s_slot);
+    const int n = s_start[pc.k];
+    for (int q = 0; q < kAppendBlock / 256; q++) {
+        const int i = blockIdx.x * kAppendBlock + q * 256 + threadIdx.x;
+        if (i >= n) break;
+        const int j = chunk_of(s_start, pc.k, i);
+        if (s_dest[j] < 0) continue;
+        const int off = i - s_start[j];
+        const int p = s_dest[j] + off;
+        buf[p] = in[i];
+        gidx[p] = s_base[j] + off;
+        cslot[p] = s_slot[j];
+        if (ids) ids[p] = in_ids ? in_ids[i] : s_base[j] + off;
+    }
+}
+
+// Accept or reject the chunks of a push in order (one thread), each as if it
+// had been pushed alone: an accepted chunk is registered in the chunk table,
+// gets the next global indices and buffer positions, and M advances (which
+// raises the threshold for the chunks after it); a rejected one is left out
+// (its hits are not clustered) and closes nothing.  The closing watermark
+// follows the final M.
+__device__ void commit_chunks(StreamDev* sd, ChunkRec* chunks, const PushChunks& pc, uint64_t tdis)
+{
     StreamDev& d = *sd;
     d.n_closed = 0;
     d.n_clusters = 0;  // set by the clustering, which a push with nothing to cluster skips
-    if (flush) {
-        d.verdict = HC_OK;
-        d.n_all = d.n_open;
-        d.has_wmark = 0;
-        d.wmark = 0;
-        if (d.has_M) {
-            d.floor = sat_add_u64(d.M, dt);
-            d.has_floor = 1;
+    int32_t n_all = d.n_open;
+    uint64_t thr;
+    bool has_thr = contract_threshold(d, tdis, &thr);
+    for (int j = 0; j < pc.k; j++) {
+        const int32_t cnt = pc.start[j + 1] - pc.start[j];
+        const int32_t f = d.c_flags[j];
+        const bool late = (f & kLate) || (has_thr && ~d.c_inv_min[j] <= thr);
+        const int32_t v = (f & kBadId) ? HC_ERR_ARG : (f & kOffSensor) ? HC_ERR_RANGE : late ? HC_ERR_DISORDER : HC_OK;
+        if (v == HC_OK) {
+            chunks[pc.slot[j]] = ChunkRec{pc.labels[j], (int64_t)d.next_g, cnt, cnt, HC_OK, 0};
+            d.c_dest[j] = n_all;
+            d.c_base[j] = d.next_g;
+            n_all += cnt;
+            d.next_g += cnt;
+            const unsigned long long mx = d.c_max[j];
+            d.M = d.has_M ? (mx > d.M ? mx : d.M) : mx;
+            d.has_M = 1;
+            has_thr = contract_threshold(d, tdis, &thr);
+        } else {
+            chunks[pc.slot[j]] = ChunkRec{pc.labels[j], -1, cnt, 0, v, 0};
+            d.c_dest[j] = -1;
         }
-        return;
+        d.c_inv_min[j] = 0;  // neutral for the next push
+        d.c_max[j] = 0;
+        d.c_flags[j] = 0;
     }
-    const int v = d.bad_id ? HC_ERR_ARG : d.range ? HC_ERR_RANGE : d.disorder ? HC_ERR_DISORDER : HC_OK;
-    d.verdict = v;
-    if (v == HC_OK) {
-        chunks[slot] = ChunkRec{labels, (int64_t)d.next_g, n, n};
-        d.n_all = d.n_open + n;
-        d.next_g += n;
-        d.M = d.has_M ? (d.chunk_max > d.M ? d.chunk_max : d.M) : d.chunk_max;
-        d.has_M = 1;
-    } else {
-        chunks[slot] = ChunkRec{labels, -1, n, 0};
-        d.n_all = d.n_open;
-    }
+    d.n_all = n_all;
     d.has_wmark = d.has_M && d.M >= tdis;
     d.wmark = d.has_wmark ? d.M - tdis : 0;
 }
 
-// End of a push: advance the ring's tail, clear the chunk flags.
-__global__ void k_stream_end(StreamDev* sd)
+// A flush (one thread): nothing is appended; the open hits are clustered and
+// all of them closed, and the floor M + dt applies to whatever comes later.
+__global__ void k_stream_commit_flush(StreamDev* sd, uint64_t dt)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    sd->q_tail += sd->n_closed;
-    sd->chunk_max = 0;
-    sd->disorder = 0;
-    sd->range = 0;
-    sd->bad_id = 0;
+    StreamDev& d = *sd;
+    d.n_closed = 0;
+    d.n_clusters = 0;
+    d.n_all = d.n_open;
+    d.has_wmark = 0;
+    d.wmark = 0;
+    if (d.has_M) {
+        d.floor = sat_add_u64(d.M, dt);
+        d.has_floor = 1;
+    }
+}
+
+// End of a push: advance the ring's tail.
+__device__ inline void end_push(StreamDev* sd) { sd->q_tail += sd->n_closed; }
+
+__global__ void k_stream_end(StreamDev* sd)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) end_push(sd);
 }
 
 __global__ void k_stream_set_qtail(StreamDev* sd, long long v)
@@ -175,36 +353,66 @@ __global__ void k_stream_idmin(const int32_t* __restrict__ lab, const Work w, co
     atomicMin(&cmin[root_rank(w, 0, 0, r)], ids[i]);
 }
 
-// A hit is final when its cluster is closed: write its stream-global label
-// into its chunk's buffer.  keep[i] = 1 for hits that stay open.  Every chunk
-// counts its hits whose labels are not final yet; the decrements go through
-// a small per-work-group table in LDS (a work-group's hits mostly come from
-// one or two chunks), one global atomic per chunk and work-group, since
-// atomics on one address from every wave serialise in the L2.
+// The closing of a push, one pass over the clustered hits and the feature
+// rows (both in blocks of kCloseBlock).  A hit is final when its cluster is
+// closed: its stream-global label goes into its chunk's buffer, and keep[i] =
+// 1 for the hits that stay open; fflag[k] = 1 for the closed clusters
+// (feature rows, ascending label).  Every chunk counts its hits whose labels
+// are not final yet; the decrements go through a small per-work-group table
+// in LDS (a work-group's hits mostly come from one or two chunks), one global
+// atomic per chunk and work-group, since atomics on one address from every
+// wave serialise in the L2.  Each work-group counts its kept hits and closed
+// rows; the last one to finish turns both count arrays into exclusive
+// offsets for the stable compactions and writes the totals.
 constexpr int kCloseThreads = 256;
 constexpr int kCloseBlock = 2048;
 constexpr int kCloseSlots = 8;
+static_assert(kCloseBlock == kCmpBlock, "closing and compaction share their blocks");
 
-__global__ __launch_bounds__(kCloseThreads) void k_stream_close_hits(const int32_t* __restrict__ lab, const Work w,
-                                                                     const int32_t* __restrict__ gidx,
-                                                                     const int32_t* __restrict__ cslot,
-                                                                     const int32_t* __restrict__ cmin,
-                                                                     ChunkRec* chunks, const StreamDev* sd,
-                                                                     uint64_t dt, int flush, uint8_t* keep)
+__device__ inline void scan_counts_in_place(uint32_t* c, int nb, int32_t* total_out, uint32_t* wsum)
+{
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += kCloseThreads) {
+        const int i = c0 + threadIdx.x;
+        const uint32_t v = i < nb ? c[i] : 0u;
+        uint32_t total;
+        const uint32_t e = block_exclusive_scan<kCloseThreads>(v, wsum, &total);
+        if (i < nb) c[i] = carry + e;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *total_out = (int32_t)carry;
+}
+
+__global__ __launch_bounds__(kCloseThreads) void k_stream_close(const int32_t* __restrict__ lab, const Work w,
+                                                                const int32_t* __restrict__ gidx,
+                                                                const int32_t* __restrict__ cslot,
+                                                                const int32_t* __restrict__ cmin,
+                                                                const hc_features* __restrict__ f,
+                                                                ChunkRec* chunks, StreamDev* sd, uint64_t dt,
+                                                                int flush, uint8_t* keep, uint8_t* fflag,
+                                                                uint32_t* hcount, uint32_t* fcount)
 {
     __shared__ int32_t s_slot[kCloseSlots];
     __shared__ int32_t s_cnt[kCloseSlots];
+    __shared__ uint32_t wsum[kCloseThreads / kWave];
     const int n_all = sd->n_all;
     if (sd->n_clusters < 0) return;  // the clustering failed; the host reports it
-    if ((int64_t)blockIdx.x * kCloseBlock >= n_all) return;
+    if (n_all == 0) {                // nothing clustered: nothing stays open or closes
+        if (blockIdx.x == 0 && threadIdx.x == 0) sd->n_open = 0;
+        return;
+    }
+    const int nb = (n_all + kCloseBlock - 1) / kCloseBlock;
+    if ((int)blockIdx.x >= nb) return;
     if (threadIdx.x < kCloseSlots) {
         s_slot[threadIdx.x] = -1;
         s_cnt[threadIdx.x] = 0;
     }
     __syncthreads();
+    const int K = sd->n_clusters;
     const bool has_wmark = sd->has_wmark;
     const uint64_t wmark = sd->wmark;
     const int lane = threadIdx.x & (kWave - 1);
+    uint32_t kept = 0, fclosed = 0;
     for (int q = 0; q < kCloseBlock / kCloseThreads; q++) {
         const int64_t i = (int64_t)blockIdx.x * kCloseBlock + q * kCloseThreads + threadIdx.x;
         bool closed = false;
@@ -223,6 +431,11 @@ __global__ __launch_bounds__(kCloseThreads) void k_stream_close_hits(const int32
                 ch->labels[gidx[i] - ch->base] = cmin ? cmin[rank] : gidx[r];
             }
             keep[i] = closed ? 0 : 1;
+            kept += closed ? 0u : 1u;
+            // feature row i (rows beyond the clusters are never closed)
+            const bool fc = i < K && (flush || (has_wmark && sat_add_u64(f[i].toa_max, dt) <= wmark));
+            fflag[i] = fc ? 1 : 0;
+            fclosed += fc ? 1u : 0u;
         }
         // one count per chunk per wave, added into the work-group's table
         unsigned long long pending = __ballot(closed);
@@ -243,56 +456,18 @@ __global__ __launch_bounds__(kCloseThreads) void k_stream_close_hits(const int32
             pending &= ~same;
         }
     }
-    __syncthreads();
+    uint32_t kt, ft;
+    (void)block_exclusive_scan<kCloseThreads>(kept, wsum, &kt);
+    (void)block_exclusive_scan<kCloseThreads>(fclosed, wsum, &ft);
+    if (threadIdx.x == 0) {
+        hcount[blockIdx.x] = kt;
+        fcount[blockIdx.x] = ft;
+    }
     if (threadIdx.x < kCloseSlots && s_slot[threadIdx.x] >= 0)
         atomicSub(&chunks[s_slot[threadIdx.x]].open, s_cnt[threadIdx.x]);
-}
-
-// flag[k] = 1 for clusters (feature rows, ascending label) that are closed
-__global__ void k_stream_close_feats(const hc_features* __restrict__ f, const StreamDev* sd, uint64_t dt, int flush,
-                                     uint8_t* flag)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= sd->n_all) return;
-    const int K = sd->n_clusters;
-    const bool hw = sd->has_wmark;
-    const uint64_t wmark = sd->wmark;
-    flag[k] = (k < K && (flush || (hw && sat_add_u64(f[k].toa_max, dt) <= wmark))) ? 1 : 0;
-}
-
-// Stable compaction by flag over the first *n_dev items, in three steps:
-// per-block counts, one work-group scan of the counts, scatter.
-__global__ __launch_bounds__(kCmpThreads) void k_flag_count(const uint8_t* __restrict__ flag, const int32_t* n_dev,
-                                                            uint32_t* counts)
-{
-    __shared__ uint32_t wsum[kCmpThreads / kWave];
-    const int n = *n_dev;
-    if ((int64_t)blockIdx.x * kCmpBlock >= n) return;
-    const int64_t b0 = (int64_t)blockIdx.x * kCmpBlock;
-    uint32_t c = 0;
-    for (int q = 0; q < kCmpBlock / kCmpThreads; q++) {
-        const int64_t i = b0 + q * kCmpThreads + threadIdx.x;
-        c += (i < n && flag[i]) ? 1u : 0u;
-    }
-    uint32_t total;
-    block_exclusive_scan<kCmpThreads>(c, wsum, &total);
-    if (threadIdx.x == 0) counts[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(1024) void k_flag_scan(uint32_t* counts, const int32_t* n_dev, int32_t* total_out)
-{
-    __shared__ uint32_t wsum[1024 / kWave];
-    const int nb = (*n_dev + kCmpBlock - 1) / kCmpBlock;
-    uint32_t carry = 0;
-    for (int c0 = 0; c0 < nb; c0 += 1024) {
-        const int i = c0 + threadIdx.x;
-        const uint32_t v = i < nb ? counts[i] : 0u;
-        uint32_t total;
-        const uint32_t e = block_exclusive_scan<1024>(v, wsum, &total);
-        if (i < nb) counts[i] = carry + e;
-        carry += total;
-    }
-    if (threadIdx.x == 0) *total_out = (int32_t)carry;
+    if (!last_group(sd, (uint32_t)nb)) return;
+    scan_counts_in_place(hcount, nb, &sd->n_open, wsum);
+    scan_counts_in_place(fcount, nb, &sd->n_closed, wsum);
 }
 
 // position of every flagged item of this block (PER consecutive items per thread)
@@ -312,38 +487,35 @@ __device__ inline void flag_scatter(const uint8_t* __restrict__ flag, int n, con
         if (bits & (1u << q)) emit(i0 + q, pos++);
 }
 
-__global__ __launch_bounds__(kCmpThreads) void k_scatter_open(const uint8_t* __restrict__ flag, const int32_t* n_dev,
-                                                              const uint32_t* offs, const hc_hit* __restrict__ sb,
-                                                              const int32_t* __restrict__ sg,
-                                                              const int32_t* __restrict__ sc,
-                                                              const int32_t* __restrict__ si, hc_hit* db,
-                                                              int32_t* dg, int32_t* dc, int32_t* di)
+// Both stable compactions of a push: the open hits to the front of the other
+// buffer, the closed clusters' features (with their stream-global labels) to
+// the ring; the last work-group to finish ends the push.
+__global__ __launch_bounds__(kCmpThreads) void k_stream_scatter(
+    const uint8_t* __restrict__ keep, const uint8_t* __restrict__ fflag, const uint32_t* hoff, const uint32_t* foff,
+    StreamDev* sd, const hc_hit* __restrict__ sb, const int32_t* __restrict__ sg, const int32_t* __restrict__ sc,
+    const int32_t* __restrict__ si, hc_hit* db, int32_t* dg, int32_t* dc, int32_t* di,
+    const hc_features* __restrict__ f, const int32_t* __restrict__ cmin, hc_features* q, int64_t q_cap)
 {
-    const int n = *n_dev;
-    if ((int64_t)blockIdx.x * kCmpBlock >= n) return;
-    flag_scatter(flag, n, offs, [&](int64_t i, uint64_t p) {
+    const int n = sd->n_all;
+    const int nb = (n + kCmpBlock - 1) / kCmpBlock;
+    if (sd->n_clusters < 0 || nb == 0) {  // nothing to move
+        if (blockIdx.x == 0 && threadIdx.x == 0) end_push(sd);
+        return;
+    }
+    if ((int)blockIdx.x >= nb) return;
+    const int64_t tail = sd->q_tail;
+    flag_scatter(keep, n, hoff, [&](int64_t i, uint64_t p) {
         db[p] = sb[i];
         dg[p] = sg[i];
         dc[p] = sc[i];
         if (si) di[p] = si[i];
     });
-}
-
-__global__ __launch_bounds__(kCmpThreads) void k_scatter_feats(const uint8_t* __restrict__ flag, const StreamDev* sd,
-                                                               const uint32_t* offs,
-                                                               const hc_features* __restrict__ f,
-                                                               const int32_t* __restrict__ gidx,
-                                                               const int32_t* __restrict__ cmin, hc_features* q,
-                                                               int64_t q_cap)
-{
-    const int n = sd->n_all;
-    if ((int64_t)blockIdx.x * kCmpBlock >= n) return;
-    const int64_t tail = sd->q_tail;
-    flag_scatter(flag, n, offs, [&](int64_t k, uint64_t p) {
+    flag_scatter(fflag, n, foff, [&](int64_t k, uint64_t p) {
         hc_features r = f[k];
-        r.label = cmin ? cmin[k] : gidx[r.label];  // row k is the cluster of rank k
+        r.label = cmin ? cmin[k] : sg[r.label];  // row k is the cluster of rank k
         q[(tail + (int64_t)p) % q_cap] = r;
     });
+    if (last_group(sd, (uint32_t)nb) && threadIdx.x == 0) end_push(sd);
 }
 
 }  // namespace hc
@@ -372,9 +544,10 @@ struct ChunkHost {
 // chunk table taken at its end.
 struct PushRec {
     uint64_t seq = 0;
-    int slot = -1;          // chunk slot; -1 for a flush
-    uint64_t tag = 0;
-    int32_t n = 0;
+    int k = 0;              // chunks of the push (0 for a flush)
+    int slot[kMaxPushChunks];
+    uint64_t tag[kMaxPushChunks];
+    int32_t n = 0;          // their hits
     int mirror_chunks = 0;  // chunk-table entries in the mirror
     hipEvent_t ev = nullptr;
     char* mirror = nullptr;
@@ -410,7 +583,8 @@ struct hc_stream {
     // ring of closed-cluster records (device); the host has consumed q_head
     hc_features* queue = nullptr;
     int64_t q_cap = 0, q_head = 0;
-    // chunk table
+    // device state block: the state, then the chunk table
+    char* state = nullptr;
     ChunkRec* chunks_dev = nullptr;
     int chunk_cap = 0;
     std::vector<ChunkHost> chunks;
@@ -451,8 +625,7 @@ static void free_all(hc_stream* st)
     (void)hipFree(st->counts);
     (void)hipFree(st->ws);
     (void)hipFree(st->queue);
-    (void)hipFree(st->chunks_dev);
-    (void)hipFree(st->sd);
+    (void)hipFree(st->state);
     for (PushRec* r : st->inflight) free_rec(r);
     for (PushRec* r : st->spare) free_rec(r);
     st->inflight.clear();
@@ -466,13 +639,14 @@ static void retire(hc_stream* st, PushRec* r)
 {
     StreamDev d;
     ::memcpy(&d, r->mirror, sizeof(StreamDev));
-    const ChunkRec* cr = reinterpret_cast<const ChunkRec*>(r->mirror + sizeof(StreamDev));
+    const ChunkRec* cr = reinterpret_cast<const ChunkRec*>(r->mirror + kStateHdr);
     if (d.n_clusters < 0) st->failed = true;
-    if (r->slot >= 0 && d.verdict != HC_OK) {
-        ChunkHost& c = st->chunks[r->slot];
-        st->done.emplace_back(c.tag, d.verdict);
-        c.active = false;
-    }
+    for (int j = 0; j < r->k; j++)
+        if (cr[r->slot[j]].verdict != HC_OK) {
+            ChunkHost& c = st->chunks[r->slot[j]];
+            st->done.emplace_back(c.tag, cr[r->slot[j]].verdict);
+            c.active = false;
+        }
     st->n_open_known = d.n_open;
     st->q_tail_known = d.q_tail;
     for (int c = 0; c < r->mirror_chunks; c++) {
@@ -483,7 +657,10 @@ static void retire(hc_stream* st, PushRec* r)
         }
     }
     st->retired = r->seq + 1;
-    if (st->log_retired && r->slot >= 0) st->retired_log.push_back(RetiredPush{r->tag, d.verdict, d.n_closed});
+    if (st->log_retired)  // the push's closed clusters count for its last chunk
+        for (int j = 0; j < r->k; j++)
+            st->retired_log.push_back(
+                RetiredPush{r->tag[j], cr[r->slot[j]].verdict, j == r->k - 1 ? d.n_closed : 0, j == r->k - 1});
 }
 
 // Retire completed pushes in order; with `all`, wait for every push.
@@ -607,10 +784,10 @@ static int ensure_capacity(hc_stream* st, int64_t n_all)
         st->cmin = nullptr;
         st->cap = 0;
         if (st->id_mode == 1 && (rc = dev_alloc(&st->cmin, nc)) != HC_OK) return rc;
-        if ((rc = dev_alloc(&st->flags, nc)) != HC_OK) return rc;
+        if ((rc = dev_alloc(&st->flags, 2 * nc)) != HC_OK) return rc;
         if ((rc = dev_alloc(&st->lab, nc)) != HC_OK) return rc;
         if ((rc = dev_alloc(&st->feats, nc)) != HC_OK) return rc;
-        if ((rc = dev_alloc(&st->counts, (nc + kCmpBlock - 1) / kCmpBlock + 1)) != HC_OK) return rc;
+        if ((rc = dev_alloc(&st->counts, 2 * count_slots(nc))) != HC_OK) return rc;
         st->cap = nc;
     }
     const size_t need = plan_workspace(n_all, st->W, st->H, sort_hint(st), nullptr, nullptr);
@@ -670,26 +847,35 @@ static int ensure_queue(hc_stream* st, int64_t n_all)
 // `ws` bytes, a ring of `q` records and `chunks` chunk slots.
 static size_t footprint(int64_t cap, size_t ws, int64_t q, int chunks, bool ids = false)
 {
-    const size_t per_hit = 2 * (sizeof(hc_hit) + 4 + 4) + 1 + 4 + sizeof(hc_features) + (ids ? 3 * 4 : 0);
-    return (size_t)cap * per_hit + 4 * (size_t)((cap + kCmpBlock - 1) / kCmpBlock + 1) + ws +
-           sizeof(hc_features) * (size_t)q + sizeof(ChunkRec) * (size_t)chunks + sizeof(StreamDev);
+    const size_t per_hit = 2 * (sizeof(hc_hit) + 4 + 4) + 2 + 4 + sizeof(hc_features) + (ids ? 3 * 4 : 0);
+    return (size_t)cap * per_hit + 4 * 2 * (size_t)count_slots(cap) + ws + sizeof(hc_features) * (size_t)q +
+           sizeof(ChunkRec) * (size_t)chunks + kStateHdr;
 }
 
+// The state block with room for twice the chunk slots (64 at first): the
+// state and the table so far are carried over, a new stream's state is zero.
 static int grow_chunks(hc_stream* st)
 {
     hipError_t e;
     int rc = reap(st, true);
     if (rc != HC_OK) return rc;
     const int nc = st->chunk_cap ? st->chunk_cap * 2 : 64;
-    ChunkRec* d;
-    if ((rc = dev_alloc(&d, nc)) != HC_OK) return rc;
-    if (st->chunk_cap &&
-        (e = hipMemcpy(d, st->chunks_dev, sizeof(ChunkRec) * st->chunk_cap, hipMemcpyDeviceToDevice)) != hipSuccess) {
+    char* d;
+    if ((rc = dev_alloc(&d, kStateHdr + sizeof(ChunkRec) * (size_t)nc)) != HC_OK) return rc;
+    if (st->state)
+        e = hipMemcpyAsync(d, st->state, kStateHdr + sizeof(ChunkRec) * (size_t)st->chunk_cap, hipMemcpyDeviceToDevice,
+                           st->s);
+    else
+        e = hipMemsetAsync(d, 0, kStateHdr, st->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->s);
+    if (e != hipSuccess) {
         (void)hipFree(d);
         return set_device_error(e, "stream chunk table");
     }
-    (void)hipFree(st->chunks_dev);
-    st->chunks_dev = d;
+    (void)hipFree(st->state);
+    st->state = d;
+    st->sd = reinterpret_cast<StreamDev*>(d);
+    st->chunks_dev = reinterpret_cast<ChunkRec*>(d + kStateHdr);
     st->chunks.resize(nc);
     st->chunk_cap = nc;
     return HC_OK;
@@ -706,7 +892,7 @@ static int take_rec(hc_stream* st, PushRec** out)
     }
     hipError_t e = hipSuccess;
     if (!r->ev) e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
-    const size_t need = sizeof(StreamDev) + sizeof(ChunkRec) * (size_t)st->chunk_cap;
+    const size_t need = kStateHdr + sizeof(ChunkRec) * (size_t)st->chunk_cap;
     if (e == hipSuccess && r->mirror_bytes < need) {
         if (r->mirror) (void)hipHostFree(r->mirror);
         r->mirror = nullptr;
@@ -722,12 +908,15 @@ static int take_rec(hc_stream* st, PushRec** out)
     return HC_OK;
 }
 
-// Enqueue one push (or, with flush, the closing of every open cluster):
-// append + commit, the plain clustering over the device-resident count,
-// closing and compaction, then the pinned read-back of state and chunk table.
-static int enqueue_push(hc_stream* st, const hc_hit* hits, const int32_t* in_ids, int32_t n, int slot,
-                        int32_t* labels, uint64_t tag, int64_t n_all_bound, int flush)
+// Enqueue one push of the chunks pc (k = 0: a flush, the closing of every
+// open cluster): append + commit, the plain clustering over the
+// device-resident count, closing and compaction, then the pinned read-back of
+// state and chunk table.
+static int enqueue_push(hc_stream* st, const hc_hit* hits, const int32_t* in_ids, const PushChunks& pc,
+                        const uint64_t* tags, int64_t n_all_bound)
 {
+    const int32_t n = pc.start[pc.k];
+    const int nb_in = (n + kAppendBlock - 1) / kAppendBlock;
     hipError_t e;
     PushRec* r = nullptr;
     int rc = take_rec(st, &r);
@@ -739,12 +928,18 @@ static int enqueue_push(hc_stream* st, const hc_hit* hits, const int32_t* in_ids
     };
     {
         TimedLaunch tl("stream_append", st->s);
-        if (!flush && n > 0)
-            hipLaunchKernelGGL(k_stream_append, dim3((n + 255) / 256), dim3(256), 0, st->s, hits, in_ids, n,
-                               st->buf[st->cur], st->gidx[st->cur], st->ids[st->cur], st->cslot[st->cur], slot,
-                               st->sd, st->tdis, st->W, st->H);
-        hipLaunchKernelGGL(k_stream_commit, dim3(1), dim3(64), 0, st->s, st->sd, st->chunks_dev, slot, labels, n,
-                           st->tdis, st->dt, flush);
+        if (pc.k == 0) {
+            hipLaunchKernelGGL(k_stream_commit_flush, dim3(1), dim3(64), 0, st->s, st->sd, st->dt);
+        } else if (pc.k == 1) {  // n > 0: a chunk of nothing never gets here
+            hipLaunchKernelGGL(k_stream_append, dim3(nb_in), dim3(256), 0, st->s, hits, in_ids, pc, st->buf[st->cur],
+                               st->gidx[st->cur], st->ids[st->cur], st->cslot[st->cur], st->sd, st->chunks_dev,
+                               st->tdis, st->W, st->H);
+        } else {
+            hipLaunchKernelGGL(k_stream_chunk_stats, dim3(nb_in), dim3(256), 0, st->s, hits, in_ids, pc, st->sd,
+                               st->chunks_dev, st->id_mode == 1 ? 1 : 0, st->tdis, st->W, st->H);
+            hipLaunchKernelGGL(k_stream_place, dim3(nb_in), dim3(256), 0, st->s, hits, in_ids, pc, st->sd,
+                               st->buf[st->cur], st->gidx[st->cur], st->ids[st->cur], st->cslot[st->cur]);
+        }
     }
     if ((e = hipGetLastError()) != hipSuccess) return give_back(set_device_error(e, "stream append"));
     const int nxt = 1 - st->cur;
@@ -770,39 +965,35 @@ static int enqueue_push(hc_stream* st, const hc_hit* hits, const int32_t* in_ids
                 hipLaunchKernelGGL(k_stream_idmin, dim3(nb_all), dim3(256), 0, st->s, st->lab, w, st->ids[st->cur],
                                    st->sd, st->cmin);
             }
-            hipLaunchKernelGGL(k_stream_close_hits, dim3((int)((n_all_bound + kCloseBlock - 1) / kCloseBlock)),
-                               dim3(kCloseThreads), 0, st->s, st->lab, w, st->gidx[st->cur], st->cslot[st->cur], cmin,
-                               st->chunks_dev, st->sd, st->dt, flush, st->flags);
-            hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all, st->counts);
-            hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, &st->sd->n_all, &st->sd->n_open);
-            hipLaunchKernelGGL(k_scatter_open, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all,
-                               st->counts, st->buf[st->cur], st->gidx[st->cur], st->cslot[st->cur], st->ids[st->cur],
-                               st->buf[nxt], st->gidx[nxt], st->cslot[nxt], st->ids[nxt]);
-            hipLaunchKernelGGL(k_stream_close_feats, dim3(nb_all), dim3(256), 0, st->s, st->feats, st->sd, st->dt, flush,
-                               st->flags);
-            hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, &st->sd->n_all, st->counts);
-            hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st->s, st->counts, &st->sd->n_all, &st->sd->n_closed);
-            hipLaunchKernelGGL(k_scatter_feats, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, st->sd, st->counts,
-                               st->feats, st->gidx[st->cur], cmin, st->queue, st->q_cap);
-            hipLaunchKernelGGL(k_stream_end, dim3(1), dim3(64), 0, st->s, st->sd);
+            // keep/flag bytes and per-block counts: hits in the first half, feature rows in the second
+            uint8_t* fflag = st->flags + st->cap;
+            uint32_t* fcount = st->counts + count_slots(st->cap);
+            hipLaunchKernelGGL(k_stream_close, dim3(nb), dim3(kCloseThreads), 0, st->s, st->lab, w, st->gidx[st->cur],
+                               st->cslot[st->cur], cmin, st->feats, st->chunks_dev, st->sd, st->dt, pc.k == 0, st->flags,
+                               fflag, st->counts, fcount);
+            hipLaunchKernelGGL(k_stream_scatter, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, fflag, st->counts,
+                               fcount, st->sd, st->buf[st->cur], st->gidx[st->cur], st->cslot[st->cur],
+                               st->ids[st->cur], st->buf[nxt], st->gidx[nxt], st->cslot[nxt], st->ids[nxt], st->feats,
+                               cmin, st->queue, st->q_cap);
         }
         if ((e = hipGetLastError()) != hipSuccess) return give_back(set_device_error(e, "stream close"));
     }
-    if ((e = hipMemcpyAsync(r->mirror, st->sd, sizeof(StreamDev), hipMemcpyDeviceToHost, st->s)) != hipSuccess ||
-        (e = hipMemcpyAsync(r->mirror + sizeof(StreamDev), st->chunks_dev, sizeof(ChunkRec) * st->chunk_cap,
-                            hipMemcpyDeviceToHost, st->s)) != hipSuccess ||
+    if ((e = hipMemcpyAsync(r->mirror, st->state, kStateHdr + sizeof(ChunkRec) * st->chunk_cap, hipMemcpyDeviceToHost,
+                            st->s)) != hipSuccess ||
         (e = hipEventRecord(r->ev, st->s)) != hipSuccess)
         return give_back(set_device_error(e, "stream read-back"));
     r->seq = st->seq++;
-    r->slot = slot;
-    r->tag = tag;
-    r->n = flush ? 0 : n;
+    r->k = pc.k;
+    r->n = n;
     r->mirror_chunks = st->chunk_cap;
     st->inflight.push_back(r);
-    if (slot >= 0) {
-        st->chunks[slot].tag = tag;
-        st->chunks[slot].reg_seq = r->seq;
-        st->chunks[slot].active = true;
+    for (int j = 0; j < pc.k; j++) {
+        r->slot[j] = pc.slot[j];
+        r->tag[j] = tags[j];
+        ChunkHost& c = st->chunks[pc.slot[j]];
+        c.tag = tags[j];
+        c.reg_seq = r->seq;
+        c.active = true;
     }
     st->cur = nxt;
     return HC_OK;
@@ -898,13 +1089,10 @@ int hc_stream_create(const hc_opts* opts, uint64_t dt, uint64_t max_disorder_tic
         return set_error(HC_ERR_ARG, "bad stream options");
     }
     hipError_t e;
-    int rc = dev_alloc(&st->sd, 1);
-    if (rc == HC_OK && (e = hipMemsetAsync(st->sd, 0, sizeof(StreamDev), st->s)) != hipSuccess)
-        rc = set_device_error(e, "stream state");
-    if (rc == HC_OK && (e = hipStreamCreateWithFlags(&st->ds, hipStreamNonBlocking)) != hipSuccess)
+    int rc = HC_OK;
+    if ((e = hipStreamCreateWithFlags(&st->ds, hipStreamNonBlocking)) != hipSuccess)
         rc = set_device_error(e, "hipStreamCreate");
-    if (rc == HC_OK) rc = grow_chunks(st);
-    if (rc == HC_OK && (e = hipStreamSynchronize(st->s)) != hipSuccess) rc = set_device_error(e, "stream create");
+    if (rc == HC_OK) rc = grow_chunks(st);  // the state block, zeroed
     if (rc != HC_OK) {
         free_all(st);
         delete st;
@@ -928,19 +1116,27 @@ static int enter_id_mode(hc_stream* st)
     return rc;
 }
 
-static int push_impl(hc_stream* st, const hc_hit* hits, const int32_t* ids, int32_t n, int32_t* labels,
-                     uint64_t tag)
+// One push of k chunks stored back to back at hits (and ids), chunk j with
+// counts[j] hits, labels[j] and tags[j].
+static int push_chunks(hc_stream* st, const hc_hit* hits, const int32_t* ids, int k, const int32_t* counts,
+                       int32_t* const* labels, const uint64_t* tags)
 {
     if (!st) return set_error(HC_ERR_ARG, "stream is NULL");
     if (st->failed) return set_error(HC_ERR_DEVICE, "stream failed earlier");
-    if (n < 0 || (n > 0 && (!hits || !labels || (st->id_mode == 1 && !ids))))
-        return set_error(HC_ERR_ARG, "bad chunk arguments");
+    if (k < 1 || k > kMaxPushChunks || !counts) return set_error(HC_ERR_ARG, "bad chunk list");
+    int64_t n = 0;
+    for (int j = 0; j < k; j++) {
+        if (counts[j] < 0 || (counts[j] > 0 && !labels[j])) return set_error(HC_ERR_ARG, "bad chunk arguments");
+        if (k > 1 && counts[j] == 0) return set_error(HC_ERR_ARG, "an empty chunk in a push of several");
+        n += counts[j];
+    }
+    if (n > 0 && (!hits || (st->id_mode == 1 && !ids))) return set_error(HC_ERR_ARG, "bad chunk arguments");
     const int mode = ids ? 1 : 0;
     if (n > 0 && st->id_mode >= 0 && st->id_mode != mode)
         return set_error(HC_ERR_ARG, "a stream takes ids with every push or with none");
     if (st->pushed + n > 0x7FFFFFFF) return set_error(HC_ERR_OVERFLOW, "more than 2^31 - 1 hits in the stream");
     if (n == 0) {
-        st->done.emplace_back(tag, HC_OK);
+        st->done.emplace_back(tags[0], HC_OK);
         return HC_OK;
     }
     int rc = HC_OK;
@@ -954,13 +1150,17 @@ static int push_impl(hc_stream* st, const hc_hit* hits, const int32_t* ids, int3
     rc = reap(st, false);
     while (rc == HC_OK && (int)st->inflight.size() >= st->depth) rc = reap_one(st);
     if (rc != HC_OK) return rc;
-    int slot = -1;
-    for (int c = 0; c < st->chunk_cap && slot < 0; c++)
-        if (!st->chunks[c].active) slot = c;
-    if (slot < 0) {
-        if ((rc = grow_chunks(st)) != HC_OK) return rc;
-        for (int c = 0; c < st->chunk_cap && slot < 0; c++)
-            if (!st->chunks[c].active) slot = c;
+    PushChunks pc{};
+    pc.k = k;
+    for (int j = 0, c = 0; j < k; j++) {
+        for (;;) {
+            while (c < st->chunk_cap && st->chunks[c].active) c++;
+            if (c < st->chunk_cap) break;
+            if ((rc = grow_chunks(st)) != HC_OK) return rc;
+        }
+        pc.slot[j] = c++;
+        pc.start[j + 1] = pc.start[j] + counts[j];
+        pc.labels[j] = labels[j];
     }
     if ((rc = ensure_capacity(st, open_bound(st) + n)) != HC_OK) return rc;
     if ((rc = ensure_queue(st, open_bound(st) + n)) != HC_OK) return rc;
@@ -968,9 +1168,22 @@ static int push_impl(hc_stream* st, const hc_hit* hits, const int32_t* ids, int3
     // the bound and changes the sort hint: size the workspace for the final plan
     const int64_t n_all = open_bound(st) + n;
     if ((rc = ensure_capacity(st, n_all)) != HC_OK) return rc;
-    if ((rc = enqueue_push(st, hits, ids, n, slot, labels, tag, n_all, 0)) != HC_OK) return rc;
+    if ((rc = enqueue_push(st, hits, ids, pc, tags, n_all)) != HC_OK) return rc;
     st->pushed += n;
     return HC_OK;
+}
+
+static int push_impl(hc_stream* st, const hc_hit* hits, const int32_t* ids, int32_t n, int32_t* labels,
+                     uint64_t tag)
+{
+    return push_chunks(st, hits, ids, 1, &n, &labels, &tag);
+}
+
+int hc_stream_push_chunks(hc_stream* st, const hc_hit* hits, int32_t k, const int32_t* counts,
+                          int32_t* const* labels, const uint64_t* tags)
+{
+    if (k < 1 || k > kMaxPushChunks || !counts || !labels || !tags) return set_error(HC_ERR_ARG, "bad chunk list");
+    return push_chunks(st, hits, nullptr, k, counts, labels, tags);
 }
 
 int hc_stream_push(hc_stream* st, const hc_hit* hits, int32_t n, int32_t* labels, uint64_t tag)
@@ -1032,7 +1245,8 @@ int hc_stream_flush(hc_stream* st)
     if ((rc = ensure_queue(st, open_bound(st))) != HC_OK) return rc;
     const int64_t n_all = open_bound(st);
     if ((rc = ensure_capacity(st, n_all)) != HC_OK) return rc;
-    if ((rc = enqueue_push(st, nullptr, nullptr, 0, -1, nullptr, 0, n_all, 1)) != HC_OK) return rc;
+    const PushChunks none{};  // k = 0: a flush
+    if ((rc = enqueue_push(st, nullptr, nullptr, none, nullptr, n_all)) != HC_OK) return rc;
     return hc_stream_wait(st);
 }
 

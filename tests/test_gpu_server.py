@@ -140,3 +140,75 @@ def test_server_rejections(hc):
     f = f[np.argsort(f["label"], kind="stable")]
     assert f.tobytes() == want_f.tobytes()
     srv.close()
+
+
+@pytest.mark.parametrize("read_while_serving", [True, False])
+def test_server_closed_records_read_while_serving(hc, read_while_serving):
+    """A stream that closes about 333k clusters, its closed-cluster records
+    read while it is served or only at the end: either way every record
+    arrives once and equals the oracle's, and the labels are the oracle's."""
+    import torch
+    n, m = 2_000_000, 100_000
+    h = hitgen.blob_stream(n, [hitgen.BASE_SEED + 7, 0], span_ticks=n * 64, disorder=512)
+    tdis = hitgen.realised_disorder_ticks(h) + 1
+    srv = hc.HcServer(1, DT, tdis, disorder_hint=512, max_chunk_hits=m)
+    lab = torch.full((n,), -5, dtype=torch.int32, pin_memory=True)
+    hits = pinned_copy(h)
+    got, comp = [], []
+    for c, at in enumerate(range(0, n, m)):
+        srv.submit(0, hits[16 * at:16 * (at + m)], lab[at:at + m], tag=c)
+        if read_while_serving:
+            got.append(srv.closed(0))
+            comp.append(srv.poll())
+    srv.flush(0)
+    srv.wait_idle(120000)
+    comp.append(srv.poll())
+    got.append(srv.closed(0))
+    srv.close()
+    comp = np.concatenate(comp)
+    assert len(comp) == n // m and (comp["status"] == 0).all()
+    want_l, want_f = oracle.cluster(h, 256, 256, DT)
+    assert np.array_equal(lab.numpy(), want_l)
+    f = np.concatenate(got)
+    assert f.size == want_f.size
+    f = f[np.argsort(f["label"], kind="stable")]
+    assert f.tobytes() == want_f.tobytes()
+
+
+def test_server_merges_queued_chunks(hc):
+    """Small chunks queued behind a running push are merged into fewer pushes,
+    each chunk still accepted or rejected on its own: a late chunk among them
+    is rejected, every other chunk's labels and the closed clusters equal the
+    oracle's over the accepted chunks."""
+    import torch
+    n = 400_000
+    h = hitgen.blob_stream(n, [hitgen.BASE_SEED + 8, 0], span_ticks=n * 64, disorder=512)
+    tdis = hitgen.realised_disorder_ticks(h) + 1
+    srv = hc.HcServer(1, DT, tdis, max_slots=1, disorder_hint=512)
+    hits = pinned_copy(h)
+    lab = torch.full((n,), -5, dtype=torch.int32, pin_memory=True)
+    late = h[:300].copy()
+    late["toa"] = 0
+    lab_late = torch.full((300,), -5, dtype=torch.int32, pin_memory=True)
+    m, c = 5000, 0
+    for at in range(0, n, m):
+        srv.submit(0, hits[16 * at:16 * (at + m)], lab[at:at + m], tag=c)
+        c += 1
+        if c == 40:
+            srv.submit(0, late, lab_late, tag=1000)
+    srv.flush(0)
+    srv.wait_idle(120000)
+    comp = srv.poll()
+    stats = srv.stats()
+    f = srv.closed(0)
+    srv.close()
+    status = {int(x["tag"]): int(x["status"]) for x in comp}
+    assert len(status) == n // m + 1 and status.pop(1000) == hc.HC_ERR_DISORDER
+    assert set(status.values()) == {0}
+    print("pushes %d for %d chunks" % (stats["pushes"], n // m + 1), flush=True)
+    assert stats["pushes"] < n // m
+    assert (lab_late.numpy() == -5).all()
+    want_l, want_f = oracle.cluster(h, 256, 256, DT)
+    assert np.array_equal(lab.numpy(), want_l)
+    f = f[np.argsort(f["label"], kind="stable")]
+    assert f.tobytes() == want_f.tobytes()

@@ -8,6 +8,8 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
+DT_STREAM = 128
+
 
 @pytest.fixture(scope="module")
 def hc():
@@ -185,4 +187,89 @@ def test_stream_push_after_flush(hc):
     want, _ = oracle.cluster(np.concatenate([a, c]), 256, 256, dt)
     got = np.concatenate([la.cpu().numpy(), lc.cpu().numpy()])
     assert np.array_equal(got, want)
+    st.close()
+
+
+def test_stream_push_chunks_equals_one_by_one(hc):
+    """Several chunks per push give what pushing them one by one gives: the
+    same labels, statuses and closed clusters, equal to the oracle over the
+    accepted chunks.  Planted rejections: a chunk below every watermark, one
+    off the sensor, and one that is late only against a chunk accepted
+    earlier in the same push."""
+    import torch
+    base = hitgen.blob_stream(300_000, [hitgen.BASE_SEED + 9, 1], span_ticks=300_000 * 64, disorder=512)
+    tdis = hitgen.realised_disorder_ticks(base) + 1
+    rng = np.random.default_rng(19)
+    chunks, at = [], 0
+    while at < base.size:
+        m = int(min(base.size - at, rng.integers(1, 24_000)))
+        chunks.append(base[at:at + m])
+        at += m
+    assert len(chunks) > 20
+    late = base[:500].copy()
+    late["toa"] = 0
+    off = base[1000:1200].copy()
+    off["x"] = 300
+    ref = len(chunks) // 3
+    seq_late = chunks[ref][:1].copy()  # late against chunk `ref` only (same push below)
+    seq_late["toa"] = int(chunks[ref]["toa"].max()) - tdis - 1
+    assert int(seq_late["toa"][0]) > int(np.concatenate(chunks[:ref])["toa"].max()) - tdis
+    chunks = chunks[:ref + 1] + [seq_late] + chunks[ref + 1:]
+    mid = 2 * len(chunks) // 3
+    chunks = chunks[:mid] + [late, off] + chunks[mid:]
+    want_status = {ref + 1: hc.HC_ERR_DISORDER, mid: hc.HC_ERR_DISORDER, mid + 1: hc.HC_ERR_RANGE}
+    # pushes of 1..16 chunks; `ref` and the chunk after it share one
+    groups, j = [], 0
+    while j < len(chunks):
+        g = int(rng.integers(1, 17))
+        if j <= ref < j + g <= ref + 1:
+            g = ref + 2 - j
+        groups.append(list(range(j, min(len(chunks), j + g))))
+        j += g
+    assert any(ref in g and ref + 1 in g for g in groups) and any(len(g) > 8 for g in groups)
+
+    def serve(multi):
+        st = hc.HcStream(DT_STREAM, tdis, 256, 256, 512)
+        labs = [torch.full((c.size,), -7, dtype=torch.int32, device="cuda") for c in chunks]
+        feats = []
+        for g in (groups if multi else [[i] for i in range(len(chunks))]):
+            d = hc.hits_to_device(np.concatenate([chunks[i] for i in g]))
+            if multi:
+                st.hc_stream_push_chunks(d, [chunks[i].size for i in g], [labs[i] for i in g], g)
+            else:
+                st.push(d, labs[g[0]], g[0])
+            feats.append(st.poll()[1])
+            torch.cuda.synchronize()  # d may go
+        st.flush()
+        feats.append(st.poll()[1])
+        torch.cuda.synchronize()
+        out = [lab.cpu().numpy() for lab in labs]
+        rejected = dict(st.rejected)
+        st.close()
+        f = np.concatenate(feats)
+        return out, rejected, f[np.argsort(f["label"], kind="stable")]
+
+    one_l, one_r, one_f = serve(False)
+    mul_l, mul_r, mul_f = serve(True)
+    assert one_r == want_status and mul_r == want_status
+    for i in range(len(chunks)):
+        assert np.array_equal(one_l[i], mul_l[i]), "chunk %d" % i
+    assert one_f.tobytes() == mul_f.tobytes()
+    for i in want_status:
+        assert (mul_l[i] == -7).all()
+    kept = [i for i in range(len(chunks)) if i not in want_status]
+    want_l, want_f = oracle.cluster(np.concatenate([chunks[i] for i in kept]), 256, 256, DT_STREAM)
+    assert np.array_equal(np.concatenate([mul_l[i] for i in kept]), want_l)
+    assert mul_f.tobytes() == want_f.tobytes()
+
+
+def test_stream_push_chunks_argument_errors(hc):
+    import torch
+    st = hc.HcStream(DT_STREAM, 1 << 20, 256, 256, 512)
+    d = torch.zeros(16 * 40, dtype=torch.uint8, device="cuda")
+    lab = [torch.empty(20, dtype=torch.int32, device="cuda") for _ in range(17)]
+    for counts in ([], [20] * 17, [20, 0]):
+        with pytest.raises(hc.HcError) as ei:
+            st.hc_stream_push_chunks(d, counts, lab[:len(counts)], list(range(len(counts))))
+        assert ei.value.code == hc.HC_ERR_ARG
     st.close()
