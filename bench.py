@@ -704,30 +704,41 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
         out.update({"saturated_mhits": round(sat_mhits, 1), "one_stream_at_a_time_mhits": round(seq_mhits, 1),
                     "saturated_speedup": round(sat_mhits / seq_mhits, 2),
                     "saturated_hbm_peak_bytes": int(sat["hbm_peak"]),
+                    "saturated_pass_mhits": sat["pass_mhits"], "saturated_pushes": int(sat["pushes"]),
+                    "saturated_chunks": sum(len(p) for p in plans),
                     "saturated_worker_ms": {k: round(sat[k] / 1e6, 2) for k in ("ns_admit_wait", "ns_push",
                                                                                "ns_drain", "ns_final")}})
     return out
 
 
-def _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels, plans):
+def _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels, plans, passes=3):
     """One pass of every stream submitted to the server at once (saturated
-    rate), then the same chunks pushed through one hc_stream at a time."""
-    srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
-    t0 = hc.hc_server_now_ns()
-    for s in range(n_streams):
-        at = 0
-        for c, m in enumerate(plans[s]):
-            srv.submit(s, copies[s][0][0][16 * at:16 * (at + m)], labels[s][0][at:at + m], c, t0)
-            at += m
-    for s in range(n_streams):
-        srv.flush(s)
-    srv.wait_idle(600000)
-    t1 = hc.hc_server_now_ns()
-    comp = srv.poll(1 << 16)
-    sat = srv.stats()
-    srv.close()
-    assert (comp["status"] == 0).all()
-    sat_mhits = n_streams * pool / ((t1 - t0) / 1e9) / 1e6
+    rate; one untimed warm-up pass, then the median of `passes` timed ones,
+    each on a new server), then the same chunks pushed through one hc_stream
+    at a time."""
+    rates, sats = [], []
+    for rep in range(passes + 1):
+        srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
+        t0 = hc.hc_server_now_ns()
+        for s in range(n_streams):
+            at = 0
+            for c, m in enumerate(plans[s]):
+                srv.submit(s, copies[s][0][0][16 * at:16 * (at + m)], labels[s][0][at:at + m], c, t0)
+                at += m
+        for s in range(n_streams):
+            srv.flush(s)
+        srv.wait_idle(600000)
+        t1 = hc.hc_server_now_ns()
+        comp = srv.poll(1 << 16)
+        sat = srv.stats()
+        srv.close()
+        assert (comp["status"] == 0).all() and comp.size == sum(len(p) for p in plans)
+        if rep:
+            rates.append(n_streams * pool / ((t1 - t0) / 1e9) / 1e6)
+            sats.append(sat)
+    order = sorted(range(passes), key=lambda i: rates[i])
+    sat_mhits, sat = rates[order[passes // 2]], sats[order[passes // 2]]
+    sat["pass_mhits"] = [round(r, 1) for r in rates]
 
     t0 = time.perf_counter()
     for s in range(n_streams):
