@@ -87,6 +87,7 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
         }
     }
     x.tiles = (TileInfo*)take(sizeof(TileInfo) * (size_t)x.n_sort_tiles);
+    x.tile_q = (uint32_t*)take(4 * (size_t)kTileQ * (size_t)x.n_sort_tiles);
     x.ts_rel = (uint32_t*)take(4 * N);
     x.ts_pay = (uint2*)take(8 * N);
     x.s_toa = (uint64_t*)take(8 * N);

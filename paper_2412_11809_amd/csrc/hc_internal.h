@@ -41,6 +41,8 @@ struct SlotRec {
 };
 static_assert(sizeof(SlotRec) == 64, "slot record is one cache line");
 
+constexpr int kTileQ = 16;  // parts of a sorted tile described by their last key
+
 struct TileInfo {
     uint64_t base;     // smallest ToA in the tile
     uint64_t max_toa;  // largest ToA
@@ -132,6 +134,7 @@ struct Work {
 
     Status* status;
     TileInfo* tiles;
+    uint32_t* tile_q;     // per sort tile, kTileQ keys: the last key of each of kTileQ equal parts (sorted, relative)
     uint32_t* ts_rel;     // tile-sorted ToA relative to the tile minimum
     uint2* ts_pay;        // tile-sorted payload: (local index | ToT << 16, x | y << 16)
     uint64_t* s_toa;

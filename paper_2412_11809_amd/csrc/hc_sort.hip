@@ -6,12 +6,15 @@
 // exploited directly:
 //   k_tile_sort   sorts tiles of T consecutive input hits in LDS (stable radix
 //                 sort on ToA relative to the tile minimum), writes the tile in
-//                 sorted order plus its min/max keys;
+//                 sorted order plus its min/max keys and the last key of each
+//                 of its kTileQ equal parts;
 //   k_tile_rank   gives every element its global rank: all of its tile's
 //                 predecessors plus, for each of the m neighbour tiles on both
 //                 sides, the number of smaller keys there (a merge path of the
-//                 two sorted tiles in LDS; binary searches for short tiles),
-//                 and writes the element's sorted record at that rank.
+//                 two sorted tiles in LDS, over only the neighbour's parts that
+//                 can interleave with this tile, found from their last keys;
+//                 binary searches for short tiles), and writes the element's
+//                 sorted record at that rank.
 //                 This is exact whenever tiles more than m apart do not
 //                 interleave, which the kernel verifies from the tile min/max
 //                 keys: the max of tile i lies below the min of tile i+m+1,
@@ -130,6 +133,11 @@ __global__ __launch_bounds__(NT, NT == 512 ? 6 : 4) void k_tile_sort(const hc_hi
         }
     }
     if (bad) atomicOr(&w.status->err_range, 1);
+    if (t < kTileQ) {  // the last key of each of the kTileQ parts
+        const int S = (cnt_e + kTileQ - 1) / kTileQ;
+        const int e = (t + 1) * S - 1 < cnt_e - 1 ? (t + 1) * S - 1 : cnt_e - 1;
+        w.tile_q[(int64_t)tile * kTileQ + t] = kr[sv[e]];
+    }
     if (t == 0) {
         TileInfo ti;
         ti.base = tmin;
@@ -249,12 +257,33 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_rank(Work w)
             if (i == j) continue;
             const TileInfo ti = w.tiles[i];
             if (disjoint(i, ti)) continue;
-            const int64_t ibase = jr.seg_start + (int64_t)(i - t0) * T;
-            __syncthreads();  // nk and below of the previous neighbour are no longer read
-            for (int e = t; e < ti.count; e += kSortThreads) nk[merge_swz(e)] = w.ts_rel[ibase + e];
-            __syncthreads();
             const bool earlier = i < j;
-            const int na = tj.count, nb = ti.count;
+            // only the parts of the neighbour that can interleave with this
+            // tile: parts whose last key goes before this tile's first key go
+            // before all of it; parts after the first one whose last key does
+            // not go before this tile's last key go before none of it
+            int b0, b1;
+            {
+                const int S = (ti.count + kTileQ - 1) / kTileQ;
+                int c_lo = 0, c_hi = 0;
+#pragma unroll
+                for (int k = 0; k < kTileQ; k++) {
+                    const uint64_t qk = ti.base + w.tile_q[(int64_t)i * kTileQ + k];
+                    c_lo += (earlier ? qk <= tj.base : qk < tj.base) ? 1 : 0;
+                    c_hi += (earlier ? qk <= tj.max_toa : qk < tj.max_toa) ? 1 : 0;
+                }
+                b0 = c_lo * S < ti.count ? c_lo * S : ti.count;
+                b1 = (c_hi + 1) * S < ti.count ? (c_hi + 1) * S : ti.count;
+                if (b1 < b0) b1 = b0;
+            }
+            const int64_t ibase = jr.seg_start + (int64_t)(i - t0) * T + b0;
+#pragma unroll
+            for (int q = 0; q < IPT; q++) rank[q] += (uint32_t)b0;
+            if (b1 == b0) continue;
+            __syncthreads();  // nk and below of the previous neighbour are no longer read
+            for (int e = t; e < b1 - b0; e += kSortThreads) nk[merge_swz(e)] = w.ts_rel[ibase + e];
+            __syncthreads();
+            const int na = tj.count, nb = b1 - b0;
             auto b_first = [&](int bi, int ai) {
                 const uint64_t tb = ti.base + nk[merge_swz(bi)], ta = tj.base + ak[merge_swz(ai)];
                 return earlier ? tb <= ta : tb < ta;
