@@ -214,6 +214,9 @@ def _bind_stream(lib):
     lib.hc_stream_push.restype = ctypes.c_int
     lib.hc_stream_push.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_uint64]
+    lib.hc_stream_push_ids.restype = ctypes.c_int
+    lib.hc_stream_push_ids.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_uint64]
     lib.hc_stream_push_chunks.restype = ctypes.c_int
     lib.hc_stream_push_chunks.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
@@ -259,6 +262,10 @@ class HcStream:
 
     def push(self, hits, labels, tag):
         self.hc_stream_push(hits, hits.numel() // 16, labels, tag)
+
+    def hc_stream_push_ids(self, hits, ids, n, labels, tag):
+        """hc_stream_push with caller-chosen ids (device int32[n])."""
+        _check(self._lib.hc_stream_push_ids(self._h, _ptr(hits), _ptr(ids), int(n), _ptr(labels), int(tag)))
 
     def hc_stream_push_chunks(self, hits, counts, labels, tags):
         """k chunks back to back in the device buffer hits; labels: one device

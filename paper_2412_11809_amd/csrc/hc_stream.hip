@@ -412,28 +412,53 @@ __global__ __launch_bounds__(kCloseThreads) void k_stream_close(const int32_t* _
     const bool has_wmark = sd->has_wmark;
     const uint64_t wmark = sd->wmark;
     const int lane = threadIdx.x & (kWave - 1);
+    constexpr int Q = kCloseBlock / kCloseThreads;
+    // each level's loads for all Q hits of the thread go out together (label,
+    // then the root's rank, then the cluster's last ToA), so a thread waits
+    // for three round trips rather than three per hit
+    int32_t r[Q], cs[Q], gi[Q];
+    uint64_t fmax[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int64_t i = (int64_t)blockIdx.x * kCloseBlock + q * kCloseThreads + threadIdx.x;
+        const bool in = i < n_all;
+        r[q] = in ? lab[i] : 0;
+        cs[q] = in ? cslot[i] : 0;
+        gi[q] = in ? gidx[i] : 0;
+        fmax[q] = (in && i < K) ? f[i].toa_max : 0;
+    }
+    uint32_t rank[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int64_t i = (int64_t)blockIdx.x * kCloseBlock + q * kCloseThreads + threadIdx.x;
+        if (i < n_all && (r[q] < 0 || r[q] > i)) {
+            atomicOr(&w.status->err_internal, 1);
+            r[q] = (int32_t)i;
+        }
+        rank[q] = i < n_all ? root_rank(w, 0, 0, r[q]) : 0u;
+    }
+    uint64_t tmax[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int64_t i = (int64_t)blockIdx.x * kCloseBlock + q * kCloseThreads + threadIdx.x;
+        tmax[q] = i < n_all ? w.slots[rank[q]].toa_max : 0;
+    }
     uint32_t kept = 0, fclosed = 0;
-    for (int q = 0; q < kCloseBlock / kCloseThreads; q++) {
+    for (int q = 0; q < Q; q++) {
         const int64_t i = (int64_t)blockIdx.x * kCloseBlock + q * kCloseThreads + threadIdx.x;
         bool closed = false;
         int32_t slot = -1;
         if (i < n_all) {
-            int32_t r = lab[i];
-            if (r < 0 || r > i) {
-                atomicOr(&w.status->err_internal, 1);
-                r = (int32_t)i;
-            }
-            const uint32_t rank = root_rank(w, 0, 0, r);
-            closed = flush || (has_wmark && sat_add_u64(w.slots[rank].toa_max, dt) <= wmark);
+            closed = flush || (has_wmark && sat_add_u64(tmax[q], dt) <= wmark);
             if (closed) {
-                slot = cslot[i];
+                slot = cs[q];
                 ChunkRec* ch = chunks + slot;
-                ch->labels[gidx[i] - ch->base] = cmin ? cmin[rank] : gidx[r];
+                ch->labels[gi[q] - ch->base] = cmin ? cmin[rank[q]] : gidx[r[q]];
             }
             keep[i] = closed ? 0 : 1;
             kept += closed ? 0u : 1u;
             // feature row i (rows beyond the clusters are never closed)
-            const bool fc = i < K && (flush || (has_wmark && sat_add_u64(f[i].toa_max, dt) <= wmark));
+            const bool fc = i < K && (flush || (has_wmark && sat_add_u64(fmax[q], dt) <= wmark));
             fflag[i] = fc ? 1 : 0;
             fclosed += fc ? 1u : 0u;
         }

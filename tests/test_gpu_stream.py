@@ -272,4 +272,12 @@ def test_stream_push_chunks_argument_errors(hc):
         with pytest.raises(hc.HcError) as ei:
             st.hc_stream_push_chunks(d, counts, lab[:len(counts)], list(range(len(counts))))
         assert ei.value.code == hc.HC_ERR_ARG
+    # a stream that takes ids takes them with every push: several chunks at once carry none
+    hits = hc.hits_to_device(hitgen.blob_stream(40, hitgen.BASE_SEED + 3, span_ticks=40 * 64, disorder=0))
+    ids = torch.arange(40, dtype=torch.int32, device="cuda")
+    lab40 = torch.empty(40, dtype=torch.int32, device="cuda")
+    st.hc_stream_push_ids(hits, ids, 40, lab40, 0)
+    with pytest.raises(hc.HcError) as ei:
+        st.hc_stream_push_chunks(hits, [20, 20], lab[1:3], [1, 2])
+    assert ei.value.code == hc.HC_ERR_ARG
     st.close()
