@@ -495,15 +495,18 @@ def bench_showers(hc, torch, dev, n=10_000_000, reps=5):
 def bench_ingest(hc, torch, dev, hits, p, piece=65536, reps=3):
     """The host ingest front end on the paper's clock: the hits start in a
     host array (the populated host buffer) and are fed in arrival order in
-    pieces of `piece` hits; buffers of 2M hits are filled by the paper's
-    buffer filling, copied to the device (pinned, on their own stream),
-    clustered with exact stitching, and every label ends on the host at its
-    arrival index.  One untimed warm-up run, then the mean of `reps` runs."""
+    pieces of `piece` hits; buffers of b = 256k hits are filled by the
+    paper's buffer filling (b_t = 16k: at most 13.9k hits of this stream
+    arrive within t + t_closing), copied to the device (pinned, on their own
+    stream), clustered with exact stitching, and every label ends on the host
+    at its arrival index.  One untimed warm-up run, then the mean of `reps`
+    runs.  (Buffers of 2M or 8M hits make the host's filling about twice as
+    slow on this machine.)"""
     import numpy as np
     import hitgen
     n = hits.size
     t = hitgen.realised_disorder_ticks(hits) + 1
-    b, bt = 2 << 20, 1 << 17
+    b, bt = 256 << 10, 16 << 10
     labels = torch.empty(n, dtype=torch.int32, pin_memory=True)
     src = np.ascontiguousarray(hits)
     times, st = [], None
