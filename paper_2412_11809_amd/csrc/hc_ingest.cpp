@@ -16,8 +16,10 @@
 // stitched by the stream.  When a buffer's chunk is complete, its labels are
 // copied back and placed at their arrival indices in the caller's array.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <string.h>
 
+#include <atomic>
 #include <deque>
 #include <string>
 #include <vector>
@@ -98,6 +100,24 @@ static int fail_ing(hc_ingest* g, int code, const std::string& msg)
 {
     g->failed = true;
     return set_error(code, msg);
+}
+
+// Copy m hits into a buffer and return the largest ToA among them and mx.
+// Streaming stores: a buffer of several MiB does not stay in the CPU caches
+// until the device reads it, and ordinary stores would first read every
+// line they write (about three times slower for 2M-hit buffers).
+static uint64_t copy_hits_max(hc_hit* dst, const hc_hit* src, int64_t m, uint64_t mx)
+{
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    static_assert(sizeof(hc_hit) == sizeof(u64x2) && offsetof(hc_hit, toa) == 0, "a hit is two words, ToA first");
+    for (int64_t j = 0; j < m; j++) {
+        u64x2 v;
+        ::memcpy(&v, src + j, sizeof(v));
+        __builtin_nontemporal_store(v, reinterpret_cast<u64x2*>(dst + j));
+        mx = v.x > mx ? v.x : mx;
+    }
+    std::atomic_thread_fence(std::memory_order_seq_cst);  // the streaming stores complete before the copy is sent
+    return mx;
 }
 
 static void free_slot(Slot& sl)
@@ -319,11 +339,8 @@ int hc_ingest_feed(hc_ingest* g, const hc_hit* hits, int64_t n)
             // so a whole run of hits moves in one copy.  No hit of the run can
             // trigger the send below (toa_max already covers it).
             const int64_t m = n - k < (b - bt) - buf.count ? n - k : (b - bt) - buf.count;
-            ::memcpy(buf.h_hits + buf.count, hits + k, sizeof(hc_hit) * (size_t)m);
             add_ids(buf, (int32_t)g->fed);
-            uint64_t mx = g->has_max ? g->toa_max : 0;
-            for (int64_t j = 0; j < m; j++) mx = hits[k + j].toa > mx ? hits[k + j].toa : mx;
-            g->toa_max = mx;
+            g->toa_max = copy_hits_max(buf.h_hits + buf.count, hits + k, m, g->has_max ? g->toa_max : 0);
             g->has_max = true;
             buf.count += m;
             g->fed += m;
