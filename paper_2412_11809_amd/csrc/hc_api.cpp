@@ -100,6 +100,10 @@ size_t plan_workspace(int64_t n, uint32_t width, uint32_t height, uint32_t disor
     x.tile_nedge = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.overflow_tiles = (int32_t*)take(4 * (size_t)x.n_link_tiles);
     x.deep_tiles = (int32_t*)take(4 * (size_t)x.n_link_tiles);
+    x.deep_ws = (int32_t*)take(4 * (size_t)x.n_link_tiles);
+    x.run_off = (int32_t*)take(4 * ((size_t)x.n_link_tiles + 1));
+    x.run_base = (int32_t*)take(4 * (size_t)x.n_link_tiles);
+    x.blk_run = (int32_t*)take(4 * ((size_t)x.n_fb_blocks + 1));
     x.slots = (SlotRec*)take(sizeof(SlotRec) * N);
     x.carries = (SlotRec*)take(sizeof(SlotRec) * (size_t)x.carry_cap);
     x.tile_ncarry = (int32_t*)take(4 * (size_t)x.n_feat_tiles);

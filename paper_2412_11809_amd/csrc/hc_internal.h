@@ -67,7 +67,8 @@ struct RadixState {
     int32_t query_done;
     int32_t shift;          // batch sort: chunk id sits above this many ToA bits
     int32_t seg_done[kFbMaxPasses];  // segments of the counter scan finished
-    int32_t pad2_[6];
+    int32_t n_eff;          // elements sorted (the plan may take fewer than count())
+    int32_t pad2_[5];
 };
 
 struct Status {
@@ -146,7 +147,11 @@ struct Work {
     int2* edges;
     int32_t* tile_nedge;     // cross-tile edges of every link tile
     int32_t* overflow_tiles;
-    int32_t* deep_tiles;     // overflow tiles that go on to the all-hits fallback
+    int32_t* deep_tiles;     // overflow tiles that go on to the link fallback
+    int32_t* deep_ws;        // per link tile: its window's first sorted position if deep, else -1
+    int32_t* run_off;        // per deep tile, in tile order: where its run of the windows' union starts (+ total)
+    int32_t* run_base;       // per deep tile: the run's first sorted position
+    int32_t* blk_run;        // per fallback radix block: the run holding its first element (+ last run)
     SlotRec* slots;
     SlotRec* carries;
     int32_t* tile_ncarry;    // carries of every feature tile

@@ -24,7 +24,7 @@
 // goes to k_link_wide, the same index over the tile and a halo of up to 7168
 // hits in one large work-group; a tile whose halo exceeds even that (or whose
 // ToA span exceeds 32 bits) is handled by k_link_fallback: a pixel-sorted copy
-// of all hits plus binary searches.  k_union_edges applies
+// of the hits in such tiles' windows plus binary searches.  k_union_edges applies
 // the queued cross-tile edges with atomic compare-and-swap, and k_flatten
 // writes labels[i] = root(i).
 #include "hc_device.h"
@@ -895,83 +895,232 @@ hipError_t launch_link_wide(const Work& w, hipStream_t s)
 }
 
 // ------------------------------------------- link fallback (big halos)
-// Hits sorted by (pixel, sorted position); for each hit of an overflowed
-// tile and each of its 9 pixels, the latest earlier hit at that pixel is
-// found by binary search and joined if within dt.
+// Only the hits that a deep tile can join are sorted: the union of the deep
+// tiles' windows, each window running from the first hit within dt before
+// the tile's first hit (in its chunk) to the tile's end.  Windows grow with
+// the tile index, so each deep tile adds one run of sorted positions to the
+// union, starting at run_base, which lands at run_off in the sort's input.
+// The hits are sorted by (pixel, sorted position); for each hit of a deep
+// tile and each of its 9 pixels, the latest earlier hit at that pixel is the
+// entry just before (pixel, own position), found by one binary search over
+// all entries (the three pixels of a neighbour row side by side), and it is
+// joined if it lies within dt.  Any hit of that pixel that is within dt lies
+// in the tile's window, so the union holds it.
+static_assert(kFbBlock >= kFbThreads + 1, "the plan keeps one value per thread in the radix LDS arrays");
 struct PixSortJob {
     static constexpr bool kKeepSorted = true;
     Work w;
     __device__ int64_t count() const { return w.n; }
+    // Position of the i-th element of the union: the last run starting at or
+    // before i, searched between the runs holding the first elements of i's
+    // radix block and of the next one.
     __device__ void load(int64_t i, uint64_t& k, uint32_t& v) const
     {
-        const uint32_t xy = w.s_xy[i];
+        const int64_t blk = i / kFbBlock;
+        int a = w.blk_run[blk], b = w.blk_run[blk + 1] + 1;
+        if (a < 0 || b <= a || b > w.status->n_deep) {
+            atomicOr(&w.status->err_internal, 1);
+            a = 0;
+            b = 1;
+        }
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if (w.run_off[m] <= i) a = m; else b = m;
+        }
+        int64_t p = (int64_t)w.run_base[a] + (i - w.run_off[a]);
+        if (w.run_off[a] > i || w.run_off[a + 1] <= i || p < 0 || p >= w.n) {
+            atomicOr(&w.status->err_internal, 1);
+            p = 0;
+        }
+        const uint32_t xy = w.s_xy[p];
         k = (uint64_t)(xy >> 16) * w.width + (xy & 0xFFFFu);
-        v = (uint32_t)i;
+        v = (uint32_t)p;
     }
-    __device__ int plan(RadixState& st, RadixLds&)
+    __device__ int plan(RadixState& st, RadixLds& L)
     {
-        if (threadIdx.x == 0) {
-            const bool on = w.status->n_deep > 0 && w.status->err_range == 0;
-            st.active = on ? 1 : 0;
+        const int t = threadIdx.x;
+        const int nd = w.status->n_deep;
+        if (nd <= 0 || w.status->err_range) return 0;  // st.active stays 0
+        const int nt = w.n_link_tiles;
+        // window start of every deep tile; -1 marks the others
+        for (int k = t; k < nt; k += kFbThreads) w.deep_ws[k] = -1;
+        __syncthreads();
+        for (int q = t; q < nd; q += kFbThreads) {
+            const int tile = w.deep_tiles[q];
+            if (tile < 0 || tile >= nt) {
+                atomicOr(&w.status->err_internal, 1);
+                continue;
+            }
+            const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
+            const uint64_t lo = sat_sub_u64(w.s_toa[tr.start], seg_dt(w, tr.seg));
+            int64_t a = tr.seg_start, b = tr.start;
+            while (a < b) {
+                const int64_t m = (a + b) >> 1;
+                if (w.s_toa[m] < lo) a = m + 1; else b = m;
+            }
+            w.deep_ws[tile] = (int32_t)a;
+        }
+        __syncthreads();
+        // each thread takes a contiguous run of tiles; first the end of the
+        // last deep tile before its run (a max-scan of the runs' last ends)
+        const int per = (nt + kFbThreads - 1) / kFbThreads;
+        const int k0 = t * per < nt ? t * per : nt;
+        const int k1 = k0 + per < nt ? k0 + per : nt;
+        int32_t* lend = reinterpret_cast<int32_t*>(L.k0);  // kFbThreads entries each
+        int32_t* lsum = reinterpret_cast<int32_t*>(L.k1);
+        int32_t* lcnt = reinterpret_cast<int32_t*>(L.key);  // kFbThreads + 1 entries
+        int64_t last = -1;
+        for (int k = k0; k < k1; k++)
+            if (w.deep_ws[k] >= 0) {
+                const TileRange tr = tile_range(w, kLinkKind, k, kLinkTile);
+                last = tr.start + tr.count;
+            }
+        lend[t] = (int32_t)last;
+        __syncthreads();
+        if (t == 0) {
+            int32_t run = -1;
+            for (int i = 0; i < kFbThreads; i++) {
+                const int32_t e = lend[i];
+                lend[i] = run;
+                run = e > run ? e : run;
+            }
+        }
+        __syncthreads();
+        const int64_t prev0 = lend[t];
+        // positions each deep tile adds to the union; the thread's deep tiles
+        int64_t prev = prev0, sum = 0;
+        int32_t cnt = 0;
+        for (int k = k0; k < k1; k++) {
+            const int64_t ws = w.deep_ws[k];
+            if (ws < 0) continue;
+            const TileRange tr = tile_range(w, kLinkKind, k, kLinkTile);
+            const int64_t base = ws > prev ? ws : prev;
+            sum += tr.start + tr.count - base;
+            prev = tr.start + tr.count;
+            cnt++;
+        }
+        lsum[t] = (int32_t)sum;
+        lcnt[t] = cnt;
+        __syncthreads();
+        if (t == 0) {
+            int32_t run = 0, rr = 0;
+            for (int i = 0; i < kFbThreads; i++) {
+                const int32_t c = lsum[i], d = lcnt[i];
+                lsum[i] = run;
+                lcnt[i] = rr;
+                run += c;
+                rr += d;
+            }
+            L.misc = run;
+            lcnt[kFbThreads] = rr;  // deep tiles counted (nd unless a listed tile was bad)
+        }
+        __syncthreads();
+        const int nr = lcnt[kFbThreads];
+        int64_t off = lsum[t];
+        int r = lcnt[t];
+        prev = prev0;
+        for (int k = k0; k < k1; k++) {
+            const int64_t ws = w.deep_ws[k];
+            if (ws < 0) continue;
+            const TileRange tr = tile_range(w, kLinkKind, k, kLinkTile);
+            const int64_t base = ws > prev ? ws : prev;
+            w.run_off[r] = (int32_t)off;
+            w.run_base[r] = (int32_t)base;
+            r++;
+            off += tr.start + tr.count - base;
+            prev = tr.start + tr.count;
+        }
+        if (t == 0) w.run_off[nr] = L.misc;
+        __syncthreads();
+        // the run holding the first element of every radix block
+        const int64_t total = L.misc;
+        const int nbk = (int)((total + kFbBlock - 1) / kFbBlock);
+        for (int q = t; q < nr; q += kFbThreads) {
+            const int64_t b0 = ((int64_t)w.run_off[q] + kFbBlock - 1) / kFbBlock;
+            const int64_t b1 = ((int64_t)w.run_off[q + 1] + kFbBlock - 1) / kFbBlock;
+            for (int64_t b = b0; b < b1; b++) w.blk_run[b] = q;
+        }
+        if (t == 0) w.blk_run[nbk] = nr > 0 ? nr - 1 : 0;
+        if (t == 0) {
+            st.active = nr > 0 ? 1 : 0;
             st.key_min = 0;
             const uint64_t top = (uint64_t)w.width * w.height - 1;
             const int bits = top == 0 ? 0 : 64 - __builtin_clzll(top);
             st.passes = bits <= 8 ? 1 : (bits + 7) / 8;
+            st.n_eff = (int32_t)total;
         }
-        return w.status->n_deep;
+        __threadfence();  // the tables are read by every work-group once the plan is published
+        return nd;
     }
     __device__ void store(int64_t, uint64_t, uint32_t) const {}
-    __device__ void extra(int q, const uint64_t* keys, const uint32_t* vals, RadixLds&)
+    // One extra task per deep tile.
+    __device__ void extra(int e, const uint64_t* keys, const uint32_t* vals, RadixLds&)
     {
-        const int tile = w.deep_tiles[q];
+        RadixState& st = w.status->rs[1];
+        const int64_t ne = st.n_eff;
+        const int tile = w.deep_tiles[e];
         const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
         const int64_t p0 = tr.start;
         const int64_t p1 = tr.start + tr.count;
         const uint64_t dt = seg_dt(w, tr.seg);
-        const int64_t n = w.n;
+        if (ne <= 0) {
+            signal_done(&st.query_done);
+            return;
+        }
+        const int32_t n1 = (int32_t)ne;
         for (int64_t p = p0 + threadIdx.x; p < p1; p += kFbThreads) {
             const uint32_t xy = w.s_xy[p];
             const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
             const uint64_t toa = w.s_toa[p];
+            // one neighbour row at a time, its three pixels side by side
             for (int dy = -1; dy <= 1; dy++) {
                 const int qy = y + dy;
                 if (qy < 0 || qy >= (int)w.height) continue;
-                for (int dx = -1; dx <= 1; dx++) {
-                    const int qx = x + dx;
-                    if (qx < 0 || qx >= (int)w.width) continue;
-                    const uint64_t key = (uint64_t)qy * w.width + qx;
-                    // [lo, hi): entries of pixel key
-                    int64_t a = 0, b = n;
-                    while (a < b) {
-                        const int64_t m = (a + b) >> 1;
-                        if (keys[m] < key) a = m + 1; else b = m;
+                uint32_t key[3];
+                int32_t a[3], b[3];
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    const int qx = x + d - 1;
+                    const bool in = qx >= 0 && qx < (int)w.width;
+                    key[d] = in ? (uint32_t)qy * w.width + (uint32_t)qx : 0u;  // below 2^32: 16-bit coordinates
+                    a[d] = 0;
+                    b[d] = in ? n1 : 0;
+                }
+                // first entry not before (pixel, p), the three searches in
+                // lockstep with every load issued (a finished search reads a
+                // valid entry and keeps its bounds)
+                for (int32_t span = n1; span > 0; span >>= 1) {
+                    uint64_t km[3];
+                    uint32_t vm[3];
+                    int32_t mm[3];
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        const int32_t m = (a[d] + b[d]) >> 1;
+                        mm[d] = m < n1 ? m : n1 - 1;
+                        km[d] = keys[mm[d]];
+                        vm[d] = vals[mm[d]];
                     }
-                    const int64_t lo = a;
-                    b = n;
-                    while (a < b) {
-                        const int64_t m = (a + b) >> 1;
-                        if (keys[m] <= key) a = m + 1; else b = m;
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        const bool go = a[d] < b[d];
+                        const bool before = km[d] < key[d] || (km[d] == key[d] && (int64_t)vm[d] < p);
+                        a[d] = go && before ? mm[d] + 1 : a[d];
+                        b[d] = go && !before ? mm[d] : b[d];
                     }
-                    const int64_t hi = a;
-                    // last entry with position < p
-                    a = lo;
-                    b = hi;
-                    while (a < b) {
-                        const int64_t m = (a + b) >> 1;
-                        if ((int64_t)vals[m] < p) a = m + 1; else b = m;
-                    }
-                    if (a > lo) {
-                        const int64_t c = vals[a - 1];
-                        if (c < 0 || c >= p) {
-                            atomicOr(&w.status->err_internal, 1);
-                        } else if (c >= tr.seg_start && toa - w.s_toa[c] <= dt) {
-                            gunion(w.gparent, w.s_idx[c], w.s_idx[p], &w.status->err_internal);
-                        }
+                }
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    if (a[d] == 0 || keys[a[d] - 1] != key[d]) continue;  // outside, or nothing before
+                    const int64_t c = vals[a[d] - 1];
+                    if (c < 0 || c >= p) {
+                        atomicOr(&w.status->err_internal, 1);
+                    } else if (c >= tr.seg_start && toa - w.s_toa[c] <= dt) {
+                        gunion(w.gparent, w.s_idx[c], w.s_idx[p], &w.status->err_internal);
                     }
                 }
             }
         }
-        signal_done(&w.status->rs[1].query_done);
+        signal_done(&st.query_done);
     }
 };
 

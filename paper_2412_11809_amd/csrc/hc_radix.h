@@ -60,16 +60,17 @@ __device__ inline void radix_scan_counts(uint32_t* h, int64_t len, RadixLds& L)
 //      (pass-0 keys, raw: the engine subtracts st.key_min).
 // Plan: __device__ void plan(RadixState& st, RadixLds& L) run by task 0's
 //      work-group; sets st.active, st.key_min, st.passes (>= 1) and the
-//      number of extra tasks through its return value.
+//      number of extra tasks through its return value.  It may also lower
+//      st.n_eff (preset to count()): only elements 0..n_eff-1 are sorted.
 // Final: void store(int64 pos, uint64 rel_key, uint32 val) for the last pass.
 // Extra: void extra(int task, const uint64* keys, const uint32* vals, RadixLds& L)
 template <class Job>
 __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uint32_t* val_buf[2],
-                             uint32_t* hist, int32_t nb, int32_t* err)
+                             uint32_t* hist, int32_t nb_max, int32_t* err)
 {
     __shared__ RadixLds L;
     const int t = threadIdx.x;
-    const int64_t n = job.count();
+    const int64_t n_max = job.count();
     while (true) {
         __syncthreads();
         if (t == 0) L.task = __hip_atomic_fetch_add(&st->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -81,13 +82,19 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
                 st->passes = 1;
                 st->key_min = 0;
                 st->total_tasks = 1;
+                st->n_eff = (int32_t)n_max;
             }
             __syncthreads();
             const int extra = job.plan(*st, L);
             __syncthreads();
             if (t == 0) {
-                const int nh = (nb + kFbGroup - 1) / kFbGroup;
-                if (st->active) st->total_tasks = 1 + st->passes * (2 * nh + fb_scan_segments(nb) + 1) + extra;
+                if (st->n_eff < 0 || st->n_eff > n_max) {
+                    atomicOr(err, 1);
+                    st->active = 0;
+                }
+                const int nbe = (int)((st->n_eff + kFbBlock - 1) / kFbBlock);
+                const int nh = (nbe + kFbGroup - 1) / kFbGroup;
+                if (st->active) st->total_tasks = 1 + st->passes * (2 * nh + fb_scan_segments(nbe) + 1) + extra;
                 __threadfence();
                 __hip_atomic_store(&st->plan_done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -97,6 +104,9 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
         if (task >= __hip_atomic_load(&st->total_tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
         const int passes = st->passes;
         const uint64_t kmin = st->key_min;
+        const int64_t n = st->n_eff;  // elements sorted; the counters are laid out for nbe blocks
+        const int nb = (int)((n + kFbBlock - 1) / kFbBlock);
+        if (nb > nb_max) return;  // never: the plan keeps n_eff <= count()
         const int nseg = fb_scan_segments(nb);
         const int nh = (nb + kFbGroup - 1) / kFbGroup;  // tasks of kFbGroup blocks
         const int per_pass = 2 * nh + nseg + 1;

@@ -192,7 +192,7 @@ def test_mixed_10m_full_size(hc):
 
 # ---- dense showers: tiles with more than 1024 hits within dt before them go
 # to the wide second level (halo up to 7168 hits), deeper ones on to the
-# all-hits fallback; both search variants, and a batch of shower chunks
+# fallback over their windows; both search variants, and a batch of shower chunks
 @pytest.mark.parametrize("showers", [(1500, 6000), (9000, 14000)])
 @pytest.mark.parametrize("flags", [0, 2])
 def test_dense_showers(hc, showers, flags):
@@ -255,6 +255,23 @@ def test_large_sensor_coordinates(hc, w, h):
     hits["toa"] = np.sort(rng.integers(0, 4_000_000, n))
     hits["tot"] = rng.integers(1, 100, n)
     assert_parity(hc, hits, w, h, 100, 512)
+
+
+@pytest.mark.parametrize("w,h", [(20000, 24), (600, 600)])
+def test_sensor_beyond_both_searches(hc, w, h):
+    # wider than the window scan's 14-bit limit and too many pixels for the
+    # LDS bitmap (or, for 600 x 600, the index forced on a sensor too large
+    # for it): every link tile goes to the link fallback, whose windows
+    # then cover the whole input
+    rng = np.random.default_rng(w * h)
+    n = 60_000
+    hits = np.zeros(n, dtype=oracle.HIT_DTYPE)
+    hits["x"] = rng.choice([0, 1, 2, w // 2, w - 2, w - 1], n)
+    hits["y"] = rng.choice([0, 1, h // 2, h - 2, h - 1], n)
+    hits["toa"] = np.sort(rng.integers(0, 3_000_000, n))
+    hits["tot"] = rng.integers(1, 100, n)
+    flags = hc.HC_FLAG_LINK_PIXEL_INDEX if w < 16384 else 0
+    assert_parity(hc, hits, w, h, 100, 512, flags=flags)
 
 
 def test_random_sweep(hc):

@@ -116,6 +116,14 @@ def test_stream_timepix4_1m_chunks(hc):
     check(hc, hits, [1_000_000] * 16, p["width"], p["height"], p["dt"], p["disorder"])
 
 
+def test_stream_dense_shower_chunks(hc):
+    # showers of 9000-14000 hits within 100 ns: link tiles whose halo exceeds
+    # the wide kernel's go to the fallback, inside pushes whose open hits
+    # ride ahead of each chunk
+    hits = hitgen.shower_stream(900_000, seed=hitgen.BASE_SEED + 88, shower_hits=(9000, 14000))
+    check(hc, hits, [150_000] * 6, 256, 256, DT_STREAM, 4096)
+
+
 def test_stream_large_disorder_bound(hc):
     """A declared disorder bound ten times the realised one keeps about ten
     times more hits open (about 200k ahead of every 1M-hit chunk): the sort
