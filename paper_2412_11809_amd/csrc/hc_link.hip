@@ -1059,14 +1059,14 @@ struct PixSortJob {
         RadixState& st = w.status->rs[1];
         const int64_t ne = st.n_eff;
         const int tile = w.deep_tiles[e];
+        if (ne <= 0 || tile < 0 || tile >= w.n_link_tiles) {  // a bad entry is flagged by the plan
+            signal_done(&st.query_done);
+            return;
+        }
         const TileRange tr = tile_range(w, kLinkKind, tile, kLinkTile);
         const int64_t p0 = tr.start;
         const int64_t p1 = tr.start + tr.count;
         const uint64_t dt = seg_dt(w, tr.seg);
-        if (ne <= 0) {
-            signal_done(&st.query_done);
-            return;
-        }
         const int32_t n1 = (int32_t)ne;
         for (int64_t p = p0 + threadIdx.x; p < p1; p += kFbThreads) {
             const uint32_t xy = w.s_xy[p];
