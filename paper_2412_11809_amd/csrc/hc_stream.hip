@@ -72,6 +72,7 @@ struct StreamDev {
     // global index of its first hit
     unsigned long long c_inv_min[kMaxPushChunks], c_max[kMaxPushChunks];
     int32_t c_flags[kMaxPushChunks], c_dest[kMaxPushChunks], c_base[kMaxPushChunks];
+    long long q_base;             // q_tail before the push's closed records (set by the closing)
 };
 
 // The stream state and the chunk table share one device block (state at
@@ -493,54 +494,97 @@ __global__ __launch_bounds__(kCloseThreads) void k_stream_close(const int32_t* _
     if (!last_group(sd, (uint32_t)nb)) return;
     scan_counts_in_place(hcount, nb, &sd->n_open, wsum);
     scan_counts_in_place(fcount, nb, &sd->n_closed, wsum);
+    if (threadIdx.x == 0) sd->q_base = sd->q_tail;
 }
 
-// position of every flagged item of this block (PER consecutive items per thread)
+// Stable compaction of block b's flagged items, emitting those of slices
+// [q0, q1).  Lanes take consecutive items (slice q holds items
+// b * kCmpBlock + q * kCmpThreads + t), so reads and writes of runs of
+// flagged items coalesce; an item's place is off (the block's first) plus the
+// flagged items of earlier slices, of earlier waves in its slice and of
+// earlier lanes in its wave.
 template <class F>
-__device__ inline void flag_scatter(const uint8_t* __restrict__ flag, int n, const uint32_t* offs, F&& emit)
+__device__ inline void flag_scatter(const uint8_t* __restrict__ flag, int n, int b, uint32_t off, int q0, int q1,
+                                    F&& emit)
 {
-    __shared__ uint32_t wsum[kCmpThreads / kWave];
     constexpr int PER = kCmpBlock / kCmpThreads;
-    const int64_t i0 = (int64_t)blockIdx.x * kCmpBlock + (int64_t)threadIdx.x * PER;
-    uint32_t bits = 0;
+    constexpr int NW = kCmpThreads / kWave;
+    __shared__ uint32_t wcnt[PER * NW];
+    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+    const int64_t b0 = (int64_t)b * kCmpBlock;
+    unsigned long long bal[PER];
 #pragma unroll
-    for (int q = 0; q < PER; q++)
-        if (i0 + q < n && flag[i0 + q]) bits |= 1u << q;
-    uint64_t pos = (uint64_t)offs[blockIdx.x] + block_exclusive_scan<kCmpThreads>(__popc(bits), wsum, nullptr);
+    for (int q = 0; q < PER; q++) {
+        const int64_t i = b0 + q * kCmpThreads + t;
+        bal[q] = __ballot(i < n && flag[i] != 0);
+        if (lane == 0) wcnt[q * NW + wv] = (uint32_t)__popcll(bal[q]);
+    }
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    uint32_t pos = off;
 #pragma unroll
-    for (int q = 0; q < PER; q++)
-        if (bits & (1u << q)) emit(i0 + q, pos++);
+    for (int q = 0; q < PER; q++) {
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < NW; k++) {
+            const uint32_t c = wcnt[q * NW + k];
+            before += k < wv ? c : 0u;
+            all += c;
+        }
+        if (q >= q0 && q < q1 && ((bal[q] >> lane) & 1ull))
+            emit(b0 + q * kCmpThreads + t, (uint64_t)pos + before + (uint32_t)__popcll(bal[q] & below));
+        pos += all;
+    }
+    __syncthreads();  // wcnt is read before another call writes it
 }
 
 // Both stable compactions of a push: the open hits to the front of the other
 // buffer, the closed clusters' features (with their stream-global labels) to
-// the ring; the last work-group to finish ends the push.
+// the ring.  Work-groups [0, nb_grid) take one block of hits each, and the
+// last of them to finish ends the push; the next nb_grid * PER take one slice
+// of kCmpThreads feature rows each (only the first rows of a push are feature
+// rows, so blocks of rows would leave most work-groups idle).  The rows go
+// behind q_base, which the closing set, so they never read the tail that the
+// end of the push moves.
 __global__ __launch_bounds__(kCmpThreads) void k_stream_scatter(
     const uint8_t* __restrict__ keep, const uint8_t* __restrict__ fflag, const uint32_t* hoff, const uint32_t* foff,
     StreamDev* sd, const hc_hit* __restrict__ sb, const int32_t* __restrict__ sg, const int32_t* __restrict__ sc,
     const int32_t* __restrict__ si, hc_hit* db, int32_t* dg, int32_t* dc, int32_t* di,
-    const hc_features* __restrict__ f, const int32_t* __restrict__ cmin, hc_features* q, int64_t q_cap)
+    const hc_features* __restrict__ f, const int32_t* __restrict__ cmin, hc_features* q, int64_t q_cap, int nb_grid)
 {
+    constexpr int PER = kCmpBlock / kCmpThreads;
     const int n = sd->n_all;
     const int nb = (n + kCmpBlock - 1) / kCmpBlock;
     if (sd->n_clusters < 0 || nb == 0) {  // nothing to move
         if (blockIdx.x == 0 && threadIdx.x == 0) end_push(sd);
         return;
     }
-    if ((int)blockIdx.x >= nb) return;
-    const int64_t tail = sd->q_tail;
-    flag_scatter(keep, n, hoff, [&](int64_t i, uint64_t p) {
-        db[p] = sb[i];
-        dg[p] = sg[i];
-        dc[p] = sc[i];
-        if (si) di[p] = si[i];
-    });
-    flag_scatter(fflag, n, foff, [&](int64_t k, uint64_t p) {
-        hc_features r = f[k];
-        r.label = cmin ? cmin[k] : sg[r.label];  // row k is the cluster of rank k
-        q[(tail + (int64_t)p) % q_cap] = r;
-    });
-    if (last_group(sd, (uint32_t)nb) && threadIdx.x == 0) end_push(sd);
+    const int g = (int)blockIdx.x;
+    const bool rows = g >= nb_grid;
+    const int b = rows ? (g - nb_grid) / PER : g;
+    if (b >= nb || nb > nb_grid) return;  // beyond this push (nb <= nb_grid: the grid's bound)
+    if (!rows) {
+        flag_scatter(keep, n, b, hoff[b], 0, PER, [&](int64_t i, uint64_t p) {
+            db[p] = sb[i];
+            dg[p] = sg[i];
+            dc[p] = sc[i];
+            if (si) di[p] = si[i];
+        });
+        if (last_group(sd, (uint32_t)nb) && threadIdx.x == 0) end_push(sd);
+    } else {
+        const int slice = (g - nb_grid) % PER;
+        const int K = sd->n_clusters;
+        if ((int64_t)b * kCmpBlock + (int64_t)slice * kCmpThreads < K) {  // rows from K on are never flagged
+            const int64_t tmod = sd->q_base % q_cap;
+            flag_scatter(fflag, n, b, foff[b], slice, slice + 1, [&](int64_t k, uint64_t p) {
+                hc_features r = f[k];
+                r.label = cmin ? cmin[k] : sg[r.label];  // row k is the cluster of rank k
+                int64_t x = tmod + (int64_t)p;
+                if (x >= q_cap) x %= q_cap;
+                q[x] = r;
+            });
+        }
+    }
 }
 
 }  // namespace hc
@@ -996,10 +1040,10 @@ static int enqueue_push(hc_stream* st, const hc_hit* hits, const int32_t* in_ids
             hipLaunchKernelGGL(k_stream_close, dim3(nb), dim3(kCloseThreads), 0, st->s, st->lab, w, st->gidx[st->cur],
                                st->cslot[st->cur], cmin, st->feats, st->chunks_dev, st->sd, st->dt, pc.k == 0, st->flags,
                                fflag, st->counts, fcount);
-            hipLaunchKernelGGL(k_stream_scatter, dim3(nb), dim3(kCmpThreads), 0, st->s, st->flags, fflag, st->counts,
-                               fcount, st->sd, st->buf[st->cur], st->gidx[st->cur], st->cslot[st->cur],
-                               st->ids[st->cur], st->buf[nxt], st->gidx[nxt], st->cslot[nxt], st->ids[nxt], st->feats,
-                               cmin, st->queue, st->q_cap);
+            hipLaunchKernelGGL(k_stream_scatter, dim3(nb * (1 + kCmpBlock / kCmpThreads)), dim3(kCmpThreads), 0, st->s,
+                               st->flags, fflag, st->counts, fcount, st->sd, st->buf[st->cur], st->gidx[st->cur],
+                               st->cslot[st->cur], st->ids[st->cur], st->buf[nxt], st->gidx[nxt], st->cslot[nxt],
+                               st->ids[nxt], st->feats, cmin, st->queue, st->q_cap, nb);
         }
         if ((e = hipGetLastError()) != hipSuccess) return give_back(set_device_error(e, "stream close"));
     }
