@@ -88,11 +88,11 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
             const int extra = job.plan(*st, L);
             __syncthreads();
             if (t == 0) {
-                if (st->n_eff < 0 || st->n_eff > n_max) {
+                const int nbe = (int)((st->n_eff + kFbBlock - 1) / kFbBlock);
+                if (st->n_eff < 0 || st->n_eff > n_max || nbe > nb_max) {  // more than the buffers hold
                     atomicOr(err, 1);
                     st->active = 0;
                 }
-                const int nbe = (int)((st->n_eff + kFbBlock - 1) / kFbBlock);
                 const int nh = (nbe + kFbGroup - 1) / kFbGroup;
                 if (st->active) st->total_tasks = 1 + st->passes * (2 * nh + fb_scan_segments(nbe) + 1) + extra;
                 __threadfence();
@@ -105,8 +105,7 @@ __device__ void radix_engine(Job& job, RadixState* st, uint64_t* key_buf[2], uin
         const int passes = st->passes;
         const uint64_t kmin = st->key_min;
         const int64_t n = st->n_eff;  // elements sorted; the counters are laid out for nbe blocks
-        const int nb = (int)((n + kFbBlock - 1) / kFbBlock);
-        if (nb > nb_max) return;  // never: the plan keeps n_eff <= count()
+        const int nb = (int)((n + kFbBlock - 1) / kFbBlock);  // <= nb_max, checked by the plan
         const int nseg = fb_scan_segments(nb);
         const int nh = (nb + kFbGroup - 1) / kFbGroup;  // tasks of kFbGroup blocks
         const int per_pass = 2 * nh + nseg + 1;
