@@ -719,10 +719,32 @@ def _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels,
     rate), on one server that stays up across the passes as a service would,
     so its device buffers are allocated in the untimed warm-up pass; the
     median of `passes` timed passes, pass k replaying the pools k periods
-    later (each stream is flushed at the end of a pass).  Then the same chunks
+    later (each stream is flushed at the end of a pass).  A consumer thread
+    reads the closed clusters' features while the pass runs, as the service's
+    client would (the server reuses the blocks it has read out), and the
+    count it read is checked against the chunks' closed counts.  Then the same chunks
     pushed through one hc_stream at a time."""
+    import threading
     import numpy as np
     rates, sats = [], []
+    buf = np.zeros(1 << 16, dtype=hc.FEATURE_DTYPE)  # the consumer's reused buffer
+
+    def consume(srv, stop, got):
+        while True:
+            last = stop.is_set()
+            moved = 0
+            for s in range(n_streams):
+                while True:
+                    k = srv.closed_into(s, buf)
+                    moved += k
+                    if k < buf.size:
+                        break
+            got[0] += moved
+            if last:
+                return
+            if moved == 0:
+                time.sleep(0.0002)
+
     keys = ("pushes", "ns_admit_wait", "ns_push", "ns_drain", "ns_final")
     srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
     prev = {k: 0 for k in keys}
@@ -731,6 +753,9 @@ def _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels,
         cp = rep % 2  # last read two passes ago; every pass has completed before the next
         for s in range(n_streams):
             copies[s][cp][1]["toa"] = pools[s]["toa"] + np.uint64(rep * period)
+        stop, got = threading.Event(), [0]
+        reader = threading.Thread(target=consume, args=(srv, stop, got))
+        reader.start()
         t0 = hc.hc_server_now_ns()
         for s in range(n_streams):
             at = 0
@@ -741,9 +766,14 @@ def _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels,
             srv.flush(s)
         srv.wait_idle(600000)
         t1 = hc.hc_server_now_ns()
+        stop.set()
+        reader.join()
         comp = srv.poll(1 << 16)
         st = srv.stats()
         assert (comp["status"] == 0).all() and comp.size == sum(len(p) for p in plans)
+        # at least the chunks' closed clusters (those the end-of-pass flushes
+        # close belong to no chunk)
+        assert got[0] >= int(comp["n_closed"].sum()) > 0, (got[0], int(comp["n_closed"].sum()))
         done += comp.size
         if rep:
             rates.append(n_streams * pool / ((t1 - t0) / 1e9) / 1e6)

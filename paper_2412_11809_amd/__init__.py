@@ -753,6 +753,14 @@ class HcServer:
         _check(self._lib.hc_server_closed(self._h, int(stream_id), out.ctypes.data, cap, ctypes.byref(k)))
         return out[: k.value].copy()
 
+    def closed_into(self, stream_id, out):
+        """Closed features of one stream into ``out`` (a FEATURE_DTYPE array,
+        reused by the caller); returns how many were written."""
+        assert out.dtype == FEATURE_DTYPE and out.flags["C_CONTIGUOUS"]
+        k = ctypes.c_int32()
+        _check(self._lib.hc_server_closed(self._h, int(stream_id), out.ctypes.data, int(out.size), ctypes.byref(k)))
+        return k.value
+
     def wait_idle(self, timeout_ms=60000):
         _check(self._lib.hc_server_wait_idle(self._h, int(timeout_ms)))
 

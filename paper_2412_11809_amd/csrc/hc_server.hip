@@ -71,6 +71,7 @@ struct StreamCtx {
     std::mutex cmu;                              // guards closed / closed_head
     std::deque<std::vector<hc_features>> closed; // closed-cluster features, one block per drain
     size_t closed_head = 0;                      // rows of closed.front() already handed out
+    std::vector<std::vector<hc_features>> spare; // blocks read out by the caller, for reuse
     std::unordered_map<uint64_t, Pending> pend;  // worker-only, keyed by internal sequence number
     uint64_t seq = 0;
     int in_device = 0;                           // pushed chunks not yet retired (worker-only)
@@ -84,6 +85,7 @@ struct StreamCtx {
 };
 
 constexpr int kDrainTags = 256, kDrainFeats = 1 << 16;
+constexpr size_t kSpareBlocks = 8;  // read-out closed-feature blocks kept per stream for reuse
 
 uint64_t now_ns()
 {
@@ -207,8 +209,19 @@ void hc_server::advance(StreamCtx* cx)
         if (hc_stream_poll(cx->st, cx->tags_pin, cx->status_pin, kDrainTags, &nd, cx->feats_pin, kDrainFeats, &nc) !=
             HC_OK)
             break;
-        if (nc > 0) {  // copied outside any lock; only the hand-over is guarded
-            std::vector<hc_features> blk(cx->feats_pin, cx->feats_pin + nc);
+        if (nc > 0) {  // copied outside any lock; only the hand-overs are guarded
+            // a block the caller has read out is reused: fresh host memory
+            // costs a page fault per 4 KiB on first touch, far more than the copy
+            std::vector<hc_features> blk;
+            {
+                std::lock_guard<std::mutex> lk(cx->cmu);
+                if (!cx->spare.empty()) {
+                    blk = std::move(cx->spare.back());
+                    cx->spare.pop_back();
+                }
+            }
+            if (blk.capacity() < (size_t)kDrainFeats) blk.reserve(kDrainFeats);
+            blk.assign(cx->feats_pin, cx->feats_pin + nc);
             std::lock_guard<std::mutex> lk(cx->cmu);
             cx->closed.push_back(std::move(blk));
         }
@@ -677,6 +690,7 @@ int hc_server_closed(hc_server* s, int32_t stream_id, hc_features* out, int32_t 
         k += (int32_t)take;
         cx->closed_head += take;
         if (cx->closed_head == blk.size()) {
+            if (cx->spare.size() < kSpareBlocks) cx->spare.push_back(std::move(cx->closed.front()));
             cx->closed.pop_front();
             cx->closed_head = 0;
         }
