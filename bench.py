@@ -614,6 +614,11 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
     # -- rate-limited: Poisson arrivals at the aggregate rate for `seconds`
 
     srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
+    import threading
+    read_stop, closed_read = threading.Event(), [0]
+    reader = threading.Thread(target=_read_closed, args=(srv, n_streams, np.zeros(1 << 16, dtype=hc.FEATURE_DTYPE),
+                                                         read_stop, closed_read))
+    reader.start()
     ex = ThreadPoolExecutor(max_workers=4)
     ready = [[None, None] for _ in range(n_streams)]   # future of the in-place re-offset
     passes = [[0, 1] for _ in range(n_streams)]        # pass held by each copy
@@ -677,6 +682,8 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
         srv.flush(s)
     srv.wait_idle(600000)
     collect()
+    read_stop.set()
+    reader.join()
     if check_pass is not None:
         for s in range(n_streams):
             for cp in range(2):
@@ -696,13 +703,14 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
                        "chunks log-uniform in [4k, 1M] hits, dt = 200 ns, HBM budget 16 GiB, pools of %d hits "
                        "replayed with a ToA offset per pass" % (n_streams, rate_mhits / n_streams, rate_mhits, pool),
            "seconds": seconds, "chunks": int(comps.size), "rejected": int((comps["status"] != 0).sum()),
-           "hits_served": hits_done,
+           "hits_served": hits_done, "closed_clusters_read": int(closed_read[0]),
            "offered_mhits": rate_mhits, "offered_chunks_per_s": round(lam * n_streams, 1),
            "achieved_mhits": round(hits_done / t_span / 1e6, 1),
            "processing_latency_ms": {"p50": q(proc, 0.5), "p99": q(proc, 0.99)},
            "final_latency_ms": {"p50": q(fin, 0.5), "p99": q(fin, 0.99)},
            "hbm_peak_bytes": int(stats["hbm_peak"]), "peak_slots_in_use": int(stats["peak_slots_in_use"]),
-           "note": "end-to-end from pinned host memory (H2D hits, D2H labels and closed features)"}
+           "note": "end-to-end from pinned host memory (H2D hits, D2H labels and closed features); a client "
+                   "thread reads the closed clusters' features as they come"}
     if sat is not None:
         out.update({"saturated_mhits": round(sat_mhits, 1), "one_stream_at_a_time_mhits": round(seq_mhits, 1),
                     "saturated_speedup": round(sat_mhits / seq_mhits, 2),
@@ -712,6 +720,25 @@ def bench_served(hc, torch, dev, seconds, n_streams=8, pool=4_000_000, rate_mhit
                     "saturated_worker_ms": {k: round(sat[k] / 1e6, 2) for k in ("ns_admit_wait", "ns_push",
                                                                                "ns_drain", "ns_final")}})
     return out
+
+
+def _read_closed(srv, n_streams, buf, stop, got):
+    """A server's client: reads every stream's closed-cluster features into
+    one reused buffer until `stop` is set, then once more; got[0] counts them."""
+    while True:
+        last = stop.is_set()
+        moved = 0
+        for s in range(n_streams):
+            while True:
+                k = srv.closed_into(s, buf)
+                moved += k
+                if k < buf.size:
+                    break
+        got[0] += moved
+        if last:
+            return
+        if moved == 0:
+            time.sleep(0.0002)
 
 
 def _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels, plans, pools, period, passes=5):
@@ -728,22 +755,7 @@ def _served_saturated(hc, torch, dev, n_streams, pool, dt, tdis, copies, labels,
     import numpy as np
     rates, sats = [], []
     buf = np.zeros(1 << 16, dtype=hc.FEATURE_DTYPE)  # the consumer's reused buffer
-
-    def consume(srv, stop, got):
-        while True:
-            last = stop.is_set()
-            moved = 0
-            for s in range(n_streams):
-                while True:
-                    k = srv.closed_into(s, buf)
-                    moved += k
-                    if k < buf.size:
-                        break
-            got[0] += moved
-            if last:
-                return
-            if moved == 0:
-                time.sleep(0.0002)
+    consume = lambda srv, stop, got: _read_closed(srv, n_streams, buf, stop, got)
 
     keys = ("pushes", "ns_admit_wait", "ns_push", "ns_drain", "ns_final")
     srv = hc.HcServer(n_streams, dt, tdis, hbm_budget=16 << 30, disorder_hint=512)
