@@ -69,10 +69,11 @@ __global__ __launch_bounds__(kFeatThreads) void k_features(Work w, const int32_t
         toa[q] = tfirst;
         uint32_t key = 0u;  // label + 1; 0 for no hit
         if (valid) {
-            idx[q] = w.s_idx[p];
-            toa[q] = w.s_toa[p];
-            xy[q] = w.s_xy[p];
-            tot[q] = w.s_tot[p];
+            // read once by this pass: streamed past the caches the gathers use
+            idx[q] = __builtin_nontemporal_load(w.s_idx + p);
+            toa[q] = __builtin_nontemporal_load(w.s_toa + p);
+            xy[q] = __builtin_nontemporal_load(w.s_xy + p);
+            tot[q] = __builtin_nontemporal_load(w.s_tot + p);
             int32_t lab = 0;
             if (idx[q] >= 0 && idx[q] < w.n) lab = labels[idx[q]] + lab0;
             else atomicOr(&w.status->err_internal, 1);
