@@ -142,11 +142,13 @@ def test_server_rejections(hc):
     srv.close()
 
 
-@pytest.mark.parametrize("read_while_serving", [True, False])
-def test_server_closed_records_read_while_serving(hc, read_while_serving):
+@pytest.mark.parametrize("read", ["while_serving", "into_small_buffer", "at_end"])
+def test_server_closed_records_read_while_serving(hc, read):
     """A stream that closes about 333k clusters, its closed-cluster records
-    read while it is served or only at the end: either way every record
-    arrives once and equals the oracle's, and the labels are the oracle's."""
+    read while it is served (whole, or through a small reused buffer that
+    splits the server's blocks, whose read-out blocks it then reuses) or only
+    at the end: every record arrives once and equals the oracle's, and the
+    labels are the oracle's."""
     import torch
     n, m = 2_000_000, 100_000
     h = hitgen.blob_stream(n, [hitgen.BASE_SEED + 7, 0], span_ticks=n * 64, disorder=512)
@@ -155,10 +157,22 @@ def test_server_closed_records_read_while_serving(hc, read_while_serving):
     lab = torch.full((n,), -5, dtype=torch.int32, pin_memory=True)
     hits = pinned_copy(h)
     got, comp = [], []
+    buf = np.zeros(10_007, dtype=hc.FEATURE_DTYPE)
+
+    def read_small():
+        while True:
+            k = srv.closed_into(0, buf)
+            got.append(buf[:k].copy())
+            if k < buf.size:
+                return
+
     for c, at in enumerate(range(0, n, m)):
         srv.submit(0, hits[16 * at:16 * (at + m)], lab[at:at + m], tag=c)
-        if read_while_serving:
+        if read == "while_serving":
             got.append(srv.closed(0))
+        elif read == "into_small_buffer":
+            read_small()
+        if read != "at_end":
             comp.append(srv.poll())
     srv.flush(0)
     srv.wait_idle(120000)
