@@ -484,7 +484,10 @@ int hc_server_flush(hc_server* s, int32_t stream_id);
 int hc_server_poll(hc_server* s, hc_completion* out, int32_t cap, int32_t* n_out);
 
 /* Features of closed clusters of one stream (stream-global labels), in
- * closing order. */
+ * closing order; up to cap into out (caller's memory), *n_out written.
+ * Records not read yet stay in host memory held by the server; reading them
+ * as they come lets it reuse those host blocks (fresh host memory costs the
+ * workers a page fault per 4 KiB, which limits a saturated server). */
 int hc_server_closed(hc_server* s, int32_t stream_id, hc_features* out, int32_t cap, int32_t* n_out);
 
 /* Wait until no chunk is queued or in device processing (chunks waiting for
